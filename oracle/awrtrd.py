@@ -1,0 +1,304 @@
+"""AWRTRD / SAWRTRD per-core update sweep in plain FP64 numpy (oracle).
+
+TEST INFRASTRUCTURE ONLY: the HIP library never imports or calls this module, and
+only the tests, the smoke check and the bench's CPU-baseline leg use it.
+
+Everything is explicit: the subchain unfolding A = Z^{!=k}_{[2]} and the cyclic
+unfolding X_[k] are formed in full (Thm. 1), the Gram matrix is formed both as
+A^T A and by FGMC (Prop. 2, eq. 13), and the weight, gradient, scaled direction,
+step length and update follow eqs. (7) and (9)-(12) (sketched form: (14)-(18)) in
+the order of Alg. 1.
+
+Readings of passages the paper leaves open or prints garbled (each is also listed
+with its justification in the design notes):
+  * weight (eq. 7): w = exp(-e^2 / (2 sigma^2)) in (0, 1], w(0) = 1; the printed
+    g'(x)/x has the opposite sign for the stated g.  sigma = +inf gives w = 1.
+  * update (eqs. 11, 17): Z_k <- Z_k + eta * fold(h).  d of eq. (9) is the negative
+    gradient of the weighted LS objective and eta of eq. (12) is the exact minimiser
+    along +h, so the printed minus sign would climb.
+  * FGMC (eq. 13): Phi is not defined; the Kronecker form K_j = sum_i Z_j(i) (x) Z_j(i)
+    with the explicit realignment below is used and pinned against A^T A.
+  * lambda (eq. 10): lambda = lambda_rel * tr(G) / R^2 (scale free).
+  * W is recomputed from the current cores at every core update.
+  * eta = 0 (core unchanged) when the line-search denominator is 0.
+  * convergence (Alg. 1): no stop test after the first sweep.
+  * sigma schedule: 'fixed', 'given' (one value per sweep) or 'quantile'.  The paper
+    defers to an external adaptive rule that is not reproduced in its text; the
+    quantile rule is this project's own choice: PARITY UNPINNED beyond the
+    sigma -> inf limit.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+from scipy.linalg import cho_factor, cho_solve
+
+from . import rng as _rng
+from .tr import (cyclic_order, fold_core, reconstruct, subchain_unfolding, unfold_core,
+                 unfold_cyclic)
+
+
+# ----------------------------------------------------------------------------------
+# entry-wise pieces
+# ----------------------------------------------------------------------------------
+
+def weights(E: np.ndarray, sigma: float) -> np.ndarray:
+    """Correntropy weights of eq. (7): exp(-E^2 / (2 sigma^2))."""
+    if math.isinf(sigma):
+        return np.ones_like(E)
+    return np.exp(-(E * E) / (2.0 * sigma * sigma))
+
+
+def welsch(E: np.ndarray, sigma: float) -> np.ndarray:
+    """Per-entry loss sigma^2 (1 - exp(-e^2 / 2 sigma^2)), i.e. g_sigma(0) - g_sigma(e) for
+    the Gaussian-kernel correntropy g of eq. (4); its sigma -> inf limit is e^2 / 2."""
+    if math.isinf(sigma):
+        return 0.5 * E * E
+    return -(sigma * sigma) * np.expm1(-(E * E) / (2.0 * sigma * sigma))
+
+
+# ----------------------------------------------------------------------------------
+# FGMC
+# ----------------------------------------------------------------------------------
+
+def fgmc_factor(Z: np.ndarray) -> np.ndarray:
+    """K = sum_i Z(i) (x) Z(i)  (r_k^2 x r_{k+1}^2, numpy kron index order)."""
+    r0, I, r1 = Z.shape
+    K = np.zeros((r0 * r0, r1 * r1))
+    for i in range(I):
+        K += np.kron(Z[:, i, :], Z[:, i, :])
+    return K
+
+
+def realign(P: np.ndarray, rk: int, rk1: int) -> np.ndarray:
+    """G[(a + b r_k), (a' + b' r_k)] = P[(b r_{k+1} + b'), (a r_k + a')]."""
+    return P.reshape(rk1, rk1, rk, rk).transpose(0, 2, 1, 3).reshape(rk1 * rk, rk1 * rk)
+
+
+def gram_fgmc(cores: Sequence[np.ndarray], k: int) -> np.ndarray:
+    """G^{!=k} by the ring product of the other cores' factors (eq. 13)."""
+    order = cyclic_order(len(cores), k)
+    P = fgmc_factor(cores[order[0]])
+    for j in order[1:]:
+        P = P @ fgmc_factor(cores[j])
+    return realign(P, cores[k].shape[0], cores[order[0]].shape[0])
+
+
+def gram_explicit(cores: Sequence[np.ndarray], k: int) -> np.ndarray:
+    """G^{!=k} = A^T A with A formed explicitly (the cost FGMC avoids)."""
+    A = subchain_unfolding(cores, k)
+    return A.T @ A
+
+
+# ----------------------------------------------------------------------------------
+# one core update
+# ----------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class StepInfo:
+    d: np.ndarray            # gradient, eq. (9)/(15)   (I_k x R^2)
+    h: np.ndarray            # scaled direction, eq. (10)/(16)
+    G: np.ndarray            # Gram of the full subchain (eq. 13)
+    eta: float               # step length, eq. (12)/(18)
+    num: float               # <d, h>
+    den: float               # || sqrt(W) o P o (h A^T) ||^2
+    loss: float              # sum over the update's observed entries of sigma^2 (1 - w)
+    wls: float               # sum of w e^2 over the same entries
+    n_obs: int               # observed entries the update touched
+    W: np.ndarray            # weights on the update's unfolded entries (x P)
+    E: np.ndarray            # residual on the update's unfolded entries (x P)
+
+
+def _sub(cores, idx):
+    return [Z[:, ix, :] for Z, ix in zip(cores, idx)]
+
+
+def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, sigma: float,
+                lambda_rel: float = 1e-9, sketch: Optional[Sequence[Sequence[int]]] = None,
+                gram: str = "fgmc", direction: str = "scaled"):
+    """One update of core k (Alg. 1 body).  Returns (new core k, StepInfo).
+
+    sketch: None for the full path (AWRTRD), else index lists I_1..I_N (RStS,
+    eqs. 14-18): the gradient and the line search use the subtensor, the Gram matrix
+    always uses the full cores.
+    gram: 'fgmc' (eq. 13) or 'explicit' (A^T A).
+    direction: 'scaled' (eq. 10) or 'gradient' (plain steepest descent with d).
+    """
+    N = len(cores)
+    if sketch is None:
+        Xs, Ps, cs = X, P, cores
+    else:
+        ix = np.ix_(*[np.asarray(s, dtype=np.int64) for s in sketch])
+        Xs, Ps = X[ix], P[ix]
+        cs = _sub(cores, sketch)
+        assert len(sketch[k]) == cores[k].shape[1], "mode k must be taken whole"
+    rk, rk1 = cores[k].shape[0], cores[k].shape[2]
+    A = subchain_unfolding(cs, k)                       # (M x R^2)
+    Pk = unfold_cyclic(Ps, k).astype(bool)
+    Xk = np.where(Pk, unfold_cyclic(Xs, k), 0.0)        # unobserved values never used
+    Zk2 = unfold_core(cores[k])
+    E = np.where(Pk, Xk - Zk2 @ A.T, 0.0)               # residual on observed entries
+    W = np.where(Pk, weights(E, sigma), 0.0)            # eq. (7)
+    d = (W * E) @ A                                      # eq. (9) / (15)
+    G = gram_fgmc(cores, k) if gram == "fgmc" else gram_explicit(cores, k)
+    if direction == "scaled":
+        R2 = G.shape[0]
+        lam = lambda_rel * np.trace(G) / R2
+        C = G + lam * np.eye(R2)
+        h = cho_solve(cho_factor(C, lower=True), d.T).T  # eq. (10) / (16)
+    else:
+        h = d.copy()
+    num = float(np.sum(d * h))
+    Q = h @ A.T
+    den = float(np.sum(W * Q * Q))                        # eq. (12) / (18) denominator
+    eta = num / den if den > 0.0 else 0.0
+    new = fold_core(Zk2 + eta * h, rk, rk1)              # eq. (11) / (17), sign '+'
+    loss = float(np.sum(np.where(Pk, welsch(E, sigma), 0.0)))
+    info = StepInfo(d=d, h=h, G=G, eta=eta, num=num, den=den, loss=loss,
+                    wls=float(np.sum(W * E * E)), n_obs=int(Pk.sum()), W=W, E=E)
+    return new, info
+
+
+# ----------------------------------------------------------------------------------
+# sweep, convergence, sigma, fit
+# ----------------------------------------------------------------------------------
+
+def convergence_matrix(cores: Sequence[np.ndarray]) -> np.ndarray:
+    """D^t = Z_{N(2)} G^{!=N} Z_{N(2)}^T (Alg. 1), equal to Xhat_[N] Xhat_[N]^T."""
+    N = len(cores)
+    Z = unfold_core(cores[N - 1])
+    return Z @ gram_fgmc(cores, N - 1) @ Z.T
+
+
+def residual_abs(X, P, cores, sketch=None) -> np.ndarray:
+    """|x - xhat| on the observed entries (of the sketch, if given), in a fixed order."""
+    if sketch is None:
+        Xs, Ps, cs = X, P, cores
+    else:
+        ix = np.ix_(*[np.asarray(s, dtype=np.int64) for s in sketch])
+        Xs, Ps, cs = X[ix], P[ix], _sub(cores, sketch)
+    Xh = reconstruct(cs)
+    m = Ps.astype(bool)
+    return np.abs(Xs[m] - Xh[m])
+
+
+def quantile_sigma(abs_e: np.ndarray, q: float, c: float, sigma_min: float) -> float:
+    """sigma = max(sigma_min, c * Q_q(|e|)), Q_q the element of rank floor((n-1) q) of the
+    ascending sort (no interpolation).  Own rule (parity unpinned)."""
+    n = abs_e.size
+    if n == 0:
+        return sigma_min if sigma_min > 0 else 1.0
+    srt = np.sort(abs_e)
+    return max(sigma_min, c * float(srt[int(math.floor((n - 1) * q))]))
+
+
+@dataclasses.dataclass
+class FitOptions:
+    max_sweeps: int = 30
+    tol: float = 1e-3
+    lambda_rel: float = 1e-9
+    sigma_mode: str = "quantile"    # 'fixed' | 'given' | 'quantile'
+    sigma: float = math.inf         # 'fixed'
+    sigma_given: Sequence[float] = ()
+    q: float = 0.5
+    c: float = 5.0
+    shrink: float = 0.5             # sigma_t >= shrink * sigma_{t-1} (quantile mode)
+    sigma_min_rel: float = 1e-6     # sigma_min = sigma_min_rel * max |x| over observed
+    sketch_sizes: Optional[Sequence[int]] = None
+    seed: int = 0
+    gram: str = "fgmc"
+    direction: str = "scaled"
+
+
+def sketch_for(opts: FitOptions, t: int, k: int, dims):
+    if opts.sketch_sizes is None:
+        return None
+    return _rng.sketch_indices(opts.seed, t, k, dims, opts.sketch_sizes)
+
+
+def sweep_sigma(X, P, cores, opts: FitOptions, t: int, sigma_min: float,
+                sigma_prev: float = math.inf) -> float:
+    """Kernel width for sweep t.  'quantile' (own rule, parity unpinned): over the
+    observed entries the sweep's first update touches (all of them on the full path,
+    its sketch under RStS), sigma_t = max(c * Q_q(|e|), sigma_min, shrink * sigma_{t-1})
+    with the cores as they stand at the start of the sweep."""
+    if opts.sigma_mode == "fixed":
+        return float(opts.sigma)
+    if opts.sigma_mode == "given":
+        return float(opts.sigma_given[t])
+    dims = [Z.shape[1] for Z in cores]
+    e = residual_abs(X, P, cores, sketch_for(opts, t, 0, dims))
+    s = quantile_sigma(e, opts.q, opts.c, sigma_min)
+    if math.isfinite(sigma_prev):
+        s = max(s, opts.shrink * sigma_prev)
+    return s
+
+
+def sweep(X, P, cores: List[np.ndarray], sigma: float, opts: FitOptions, t: int = 0):
+    """One pass over k = 1..N, each update seeing the latest cores (Alg. 1)."""
+    dims = [Z.shape[1] for Z in cores]
+    infos = []
+    cores = list(cores)
+    for k in range(len(cores)):
+        new, info = core_update(X, P, cores, k, sigma, opts.lambda_rel,
+                                sketch_for(opts, t, k, dims), opts.gram, opts.direction)
+        cores[k] = new
+        infos.append(info)
+    return cores, infos
+
+
+def fit(X, P, cores: List[np.ndarray], opts: FitOptions):
+    """Alg. 1: sweeps until t = C or the change of D^t falls below tol."""
+    cores = [np.array(Z, dtype=np.float64) for Z in cores]
+    Pb = P.astype(bool)
+    sigma_min = opts.sigma_min_rel * float(np.max(np.abs(X[Pb]))) if Pb.any() else 0.0
+    hist: Dict[str, list] = {"sigma": [], "e": [], "eta": [], "loss": []}
+    D_prev = None
+    sigma = math.inf
+    for t in range(opts.max_sweeps):
+        sigma = sweep_sigma(X, P, cores, opts, t, sigma_min, sigma)
+        cores, infos = sweep(X, P, cores, sigma, opts, t)
+        D = convergence_matrix(cores)
+        e = math.inf if D_prev is None else float(np.linalg.norm(D - D_prev) / np.linalg.norm(D))
+        D_prev = D
+        hist["sigma"].append(sigma)
+        hist["e"].append(e)
+        hist["eta"].append([i.eta for i in infos])
+        hist["loss"].append([i.loss for i in infos])
+        if e < opts.tol:
+            break
+    return cores, hist
+
+
+# ----------------------------------------------------------------------------------
+# differentiation form and metrics
+# ----------------------------------------------------------------------------------
+
+def loss(X, P, cores, sigma: float) -> float:
+    """L = sum over observed entries of sigma^2 (1 - exp(-e^2 / 2 sigma^2))."""
+    Xh = reconstruct(cores)
+    m = P.astype(bool)
+    return float(np.sum(welsch(X[m] - Xh[m], sigma)))
+
+
+def loss_grads(X, P, cores, sigma: float) -> List[np.ndarray]:
+    """dL/dZ_k = -fold(d_k) for every k, d_k of eq. (9) with W = w(E) at these cores."""
+    grads = []
+    for k in range(len(cores)):
+        N = len(cores)
+        A = subchain_unfolding(cores, k)
+        Pk = unfold_cyclic(P, k).astype(bool)
+        Xk = np.where(Pk, unfold_cyclic(X, k), 0.0)
+        E = np.where(Pk, Xk - unfold_core(cores[k]) @ A.T, 0.0)
+        d = (np.where(Pk, weights(E, sigma), 0.0) * E) @ A
+        grads.append(fold_core(-d, cores[k].shape[0], cores[k].shape[2]))
+    return grads
+
+
+def relative_error(cores, xstar) -> float:
+    """||Xhat - X*||_F / ||X*||_F over every entry."""
+    Xh = reconstruct(cores)
+    return float(np.linalg.norm(Xh - xstar) / np.linalg.norm(xstar))

@@ -1,0 +1,105 @@
+"""Counter-based index sampling for randomized subtensor sketching (oracle side).
+
+RStS (Sec. 4.2.2 and Alg. 1) draws, for every core update k of sweep t and every
+mode j != k, an index set I_j of s_j lateral slices uniformly at random; I_k is the
+whole range.  The paper does not fix the sampling law or generator.  Reading used
+here (and by the library, which implements the same published generator on its
+own): uniform without replacement, sorted ascending, fresh for every (t, k, j).
+
+Generator: SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+generators", OOPSLA 2014).  The n-th output (n = 1, 2, ...) of a SplitMix64 stream
+seeded with s is mix64(s + n * GOLDEN); ``counter_u64(key, c)`` is output c + 1.
+Bounded integers: Lemire's multiply-shift with rejection ("Fast random integer
+generation in an interval", ACM TOMACS 2019) on the top 32 bits.
+Subset: Floyd's algorithm (Bentley and Floyd, "A sample of brilliance", CACM 1987).
+Everything is integer-only, so any two faithful implementations agree bit for bit.
+"""
+from __future__ import annotations
+
+from typing import List, Sequence
+
+M64 = (1 << 64) - 1
+GOLDEN = 0x9E3779B97F4A7C15
+DOMAIN_RSTS = 0x5253545300000000  # "RStS" tag separating this use from others
+
+
+def mix64(z: int) -> int:
+    """SplitMix64 output function."""
+    z &= M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def splitmix64_stream(seed: int, n: int) -> List[int]:
+    """First n outputs of the sequential SplitMix64 generator seeded with ``seed``."""
+    s = seed & M64
+    out = []
+    for _ in range(n):
+        s = (s + GOLDEN) & M64
+        out.append(mix64(s))
+    return out
+
+
+def counter_u64(key: int, ctr: int) -> int:
+    """Output number ctr + 1 of the SplitMix64 stream seeded with key."""
+    return mix64((key + (ctr + 1) * GOLDEN) & M64)
+
+
+def sketch_key(seed: int, t: int, k: int, j: int) -> int:
+    """Stream key for sweep t, core update k, sampled mode j."""
+    a = counter_u64((seed ^ DOMAIN_RSTS) & M64, t)
+    b = counter_u64(a, k)
+    return counter_u64(b, j)
+
+
+def bounded(key: int, ctr: int, n: int):
+    """Uniform integer in [0, n) (1 <= n <= 2^32) and the next counter value."""
+    assert 1 <= n <= (1 << 32)
+    threshold = ((1 << 32) - n) % n
+    while True:
+        x = counter_u64(key, ctr) >> 32
+        ctr += 1
+        m = x * n
+        if (m & 0xFFFFFFFF) >= threshold:
+            return m >> 32, ctr
+
+
+def floyd_sample(key: int, n: int, s: int) -> List[int]:
+    """s distinct indices from [0, n), uniform, sorted ascending (s >= n: all)."""
+    if s >= n:
+        return list(range(n))
+    chosen = set()
+    ctr = 0
+    for jj in range(n - s, n):
+        t, ctr = bounded(key, ctr, jj + 1)
+        chosen.add(jj if t in chosen else t)
+    return sorted(chosen)
+
+
+def sketch_indices(seed: int, t: int, k: int, dims: Sequence[int], sizes: Sequence[int]):
+    """Index sets I_1..I_N for update k of sweep t; mode k takes every index."""
+    out = []
+    for j, (I, s) in enumerate(zip(dims, sizes)):
+        if j == k:
+            out.append(list(range(I)))
+        else:
+            out.append(floyd_sample(sketch_key(seed, t, k, j), I, s))
+    return out
+
+
+def sizes_from_J(J: int, dims: Sequence[int]) -> List[int]:
+    """Per-mode sample size from the sample parameter J.
+
+    The printed size rule is garbled (it evaluates to 1 for any real tensor); the
+    reading used here takes the (N-1)-th root: s_j = min(I_j, ceil(J^(1/(N-1)))),
+    computed exactly as the least integer s with s^(N-1) >= J."""
+    N = len(dims)
+    lo, hi = 1, max(1, int(J))
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if mid ** (N - 1) >= J:
+            hi = mid
+        else:
+            lo = mid + 1
+    return [min(I, lo) for I in dims]

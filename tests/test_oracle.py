@@ -1,0 +1,394 @@
+"""Pins for the FP64 oracle: each check ties it to something other than itself
+(brute force, a closed form, a textbook/library solution, an invariant, published
+generator outputs), so a dropped term, a wrong sign, a wrong index or a transposed
+operand anywhere in it fails at least one test.  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import awrtrd as aw
+from oracle import rng as orng
+from oracle import tr
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rand_cores(dims, ranks, seed, std=1.0):
+    g = np.random.default_rng(seed)
+    N = len(dims)
+    return [g.standard_normal((ranks[j], dims[j], ranks[(j + 1) % N])) * std for j in range(N)]
+
+
+CASES = [((3, 4, 5), (2, 3, 2)), ((3, 4, 2, 3), (2, 3, 2, 3)), ((2, 3, 2, 2, 3), (1, 2, 3, 2, 2)),
+         ((4, 5), (3, 2))]
+
+
+# ---------------------------------------------------------------- TR format (Def. 1-2, Thm. 1)
+
+@pytest.mark.parametrize("dims,ranks", CASES)
+def test_merge_reconstruction_equals_bruteforce(dims, ranks):
+    Z = rand_cores(dims, ranks, 1)
+    np.testing.assert_allclose(tr.reconstruct(Z), tr.reconstruct_bruteforce(Z), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("dims,ranks", CASES)
+def test_cyclic_shift_invariance(dims, ranks):
+    # R(Z_2..Z_N, Z_1)[i_2..i_N, i_1] = R(Z)[i_1..i_N]  (trace is cyclic)
+    Z = rand_cores(dims, ranks, 2)
+    X = tr.reconstruct(Z)
+    Xs = tr.reconstruct(Z[1:] + Z[:1])
+    np.testing.assert_allclose(np.moveaxis(Xs, -1, 0), X, rtol=1e-12, atol=1e-12)
+
+
+def test_rank_one_is_outer_product():
+    g = np.random.default_rng(3)
+    vs = [g.standard_normal(n) for n in (3, 4, 5)]
+    Z = [v.reshape(1, -1, 1) for v in vs]
+    np.testing.assert_allclose(tr.reconstruct(Z), np.multiply.outer(np.multiply.outer(vs[0], vs[1]), vs[2]),
+                               rtol=1e-13)
+
+
+def test_reconstruct_layout_is_column_major():
+    Z = rand_cores((3, 4, 5), (2, 2, 2), 4)
+    X = tr.reconstruct(Z)
+    lin = np.array([0, 1, 3, 7, 59])
+    np.testing.assert_allclose(X.ravel(order="F")[lin], tr.reconstruct_at(Z, lin), rtol=1e-12)
+
+
+@pytest.mark.parametrize("dims,ranks", CASES)
+def test_theorem1_unfolding(dims, ranks):
+    Z = rand_cores(dims, ranks, 5)
+    X = tr.reconstruct(Z)
+    for k in range(len(dims)):
+        A = tr.subchain_unfolding(Z, k)
+        np.testing.assert_allclose(tr.unfold_cyclic(X, k), tr.unfold_core(Z[k]) @ A.T, rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(tr.fold_cyclic(tr.unfold_cyclic(X, k), k, dims), X)
+
+
+def test_subchain_row_by_hand():
+    dims, ranks = (3, 4, 2, 3), (2, 3, 2, 3)
+    Z = rand_cores(dims, ranks, 6)
+    k = 1
+    A = tr.subchain_unfolding(Z, k)
+    # row for (i_2, i_3, i_0) = (1, 2, 2): little-endian in the cyclic order 2, 3, 0
+    i2, i3, i0 = 1, 2, 2
+    m = i2 + dims[2] * (i3 + dims[3] * i0)
+    Am = Z[2][:, i2, :] @ Z[3][:, i3, :] @ Z[0][:, i0, :]    # r_2 x r_1
+    rk = ranks[k]
+    for a in range(ranks[k]):
+        for b in range(ranks[k + 1]):
+            assert abs(A[m, a + b * rk] - Am[b, a]) < 1e-12
+
+
+def test_core_unfold_roundtrip_and_layout():
+    Z = rand_cores((4,), (3,), 7)[0][:, :, :2] if False else np.random.default_rng(7).standard_normal((3, 4, 2))
+    U = tr.unfold_core(Z)
+    assert U.shape == (4, 6)
+    assert U[2, 1 + 1 * 3] == Z[1, 2, 1]
+    np.testing.assert_array_equal(tr.fold_core(U, 3, 2), Z)
+
+
+# ---------------------------------------------------------------- weights (eq. 7) and loss
+
+def test_weight_properties():
+    e = np.linspace(-5, 5, 101)
+    w = aw.weights(e, 1.3)
+    assert np.all(w > 0) and np.all(w <= 1)
+    assert aw.weights(np.array([0.0]), 0.7)[0] == 1.0
+    # half-height at |e| = sigma sqrt(2 ln 2)
+    s = 0.9
+    assert abs(aw.weights(np.array([s * math.sqrt(2 * math.log(2))]), s)[0] - 0.5) < 1e-14
+    assert np.all(aw.weights(e, math.inf) == 1.0)
+    # large sigma tends to the least-squares weights (sec. 4.1)
+    assert np.max(np.abs(aw.weights(e, 1e8) - 1)) < 1e-14
+
+
+def test_welsch_limits():
+    e = np.array([0.0, 1e-4, 0.3, 2.0])
+    np.testing.assert_allclose(aw.welsch(e, 1e6), 0.5 * e * e, rtol=1e-9)
+    np.testing.assert_array_equal(aw.welsch(e, math.inf), 0.5 * e * e)
+    # bounded by sigma^2 for gross errors (the robustness of eq. 4)
+    assert aw.welsch(np.array([1e3]), 2.0)[0] == pytest.approx(4.0)
+
+
+# ---------------------------------------------------------------- gradient (eq. 9)
+
+def _masked_problem(dims, ranks, seed, rho=0.6):
+    g = np.random.default_rng(seed)
+    Z = rand_cores(dims, ranks, seed, 0.7)
+    P = (g.random(dims) < rho).astype(np.uint8)
+    X = tr.reconstruct(rand_cores(dims, ranks, seed + 100, 0.7)) + 0.1 * g.standard_normal(dims)
+    return Z, P, X
+
+
+@pytest.mark.parametrize("sigma", [0.8, math.inf])
+def test_gradient_is_minus_fd_of_frozen_weight_objective(sigma):
+    dims, ranks = (3, 4, 3, 2), (2, 3, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 11)
+    k = 2
+    _, info = aw.core_update(X, P, Z, k, sigma, lambda_rel=1e-9)
+    W = info.W
+    A = tr.subchain_unfolding(Z, k)
+    Pk = tr.unfold_cyclic(P, k).astype(bool)
+    Xk = np.where(Pk, tr.unfold_cyclic(X, k), 0)
+
+    def f(Zk2):  # 1/2 || sqrt(W) o P o (X - Z A^T) ||^2 with W frozen (eq. 8)
+        E = np.where(Pk, Xk - Zk2 @ A.T, 0)
+        return 0.5 * np.sum(W * E * E)
+
+    Zk2 = tr.unfold_core(Z[k])
+    fd = np.zeros_like(Zk2)
+    h = 1e-6
+    for idx in np.ndindex(*Zk2.shape):
+        Zp = Zk2.copy(); Zp[idx] += h
+        Zm = Zk2.copy(); Zm[idx] -= h
+        fd[idx] = (f(Zp) - f(Zm)) / (2 * h)
+    np.testing.assert_allclose(info.d, -fd, rtol=1e-6, atol=1e-8)
+
+
+def test_loss_grads_match_finite_differences():
+    dims, ranks = (3, 3, 4), (2, 2, 3)
+    Z, P, X = _masked_problem(dims, ranks, 12)
+    sigma = 0.5
+    grads = aw.loss_grads(X, P, Z, sigma)
+    h = 1e-6
+    for k in range(3):
+        for idx in [(0, 0, 0), (1, 2, 1), (Z[k].shape[0] - 1, 1, Z[k].shape[2] - 1)]:
+            Zp = [z.copy() for z in Z]; Zp[k][idx] += h
+            Zm = [z.copy() for z in Z]; Zm[k][idx] -= h
+            fd = (aw.loss(X, P, Zp, sigma) - aw.loss(X, P, Zm, sigma)) / (2 * h)
+            assert abs(grads[k][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, idx, grads[k][idx], fd)
+
+
+def test_unobserved_values_never_used():
+    dims, ranks = (3, 4, 3), (2, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 13)
+    X2 = X.copy()
+    X2[P == 0] = 1e30
+    a, ia = aw.core_update(X, P, Z, 1, 0.7)
+    b, ib = aw.core_update(X2, P, Z, 1, 0.7)
+    np.testing.assert_array_equal(a, b)
+    assert ia.eta == ib.eta
+
+
+# ---------------------------------------------------------------- FGMC (eq. 13)
+
+@pytest.mark.parametrize("dims,ranks", CASES)
+def test_fgmc_equals_explicit_gram(dims, ranks):
+    Z = rand_cores(dims, ranks, 21)
+    for k in range(len(dims)):
+        Ge = aw.gram_explicit(Z, k)
+        Gf = aw.gram_fgmc(Z, k)
+        np.testing.assert_allclose(Gf, Ge, rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(Gf, Gf.T, rtol=1e-12, atol=1e-12)
+        assert np.min(np.linalg.eigvalsh(Gf)) > -1e-9 * np.max(np.abs(Gf))
+
+
+@pytest.mark.parametrize("dims,ranks", CASES)
+def test_fgmc_trace_identities(dims, ranks):
+    Z = rand_cores(dims, ranks, 22)
+    X = tr.reconstruct(Z)
+    nrm2 = float(np.sum(X * X))
+    K = [aw.fgmc_factor(z) for z in Z]
+    P = K[0]
+    for Kj in K[1:]:
+        P = P @ Kj
+    assert np.trace(P) == pytest.approx(nrm2, rel=1e-11)
+    for k in range(len(dims)):
+        Zk = tr.unfold_core(Z[k])
+        assert np.trace(Zk @ aw.gram_fgmc(Z, k) @ Zk.T) == pytest.approx(nrm2, rel=1e-11)
+
+
+def test_fgmc_factor_by_hand():
+    Z = np.random.default_rng(23).standard_normal((2, 3, 3))
+    K = aw.fgmc_factor(Z)
+    # K[(a r + a'), (b r' + b')] = sum_i Z(i)[a, b] Z(i)[a', b']
+    a, a2, b, b2 = 1, 0, 2, 1
+    ref = sum(Z[a, i, b] * Z[a2, i, b2] for i in range(3))
+    assert K[a * 2 + a2, b * 3 + b2] == pytest.approx(ref, rel=1e-14)
+
+
+# ---------------------------------------------------------------- step (eqs. 10-12)
+
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_full_ls_step_is_tr_als(k):
+    # P = 1, sigma = inf, lambda = 0: eta = 1 and Z + eta h solves the LS problem (1)
+    dims, ranks = (3, 4, 3, 4), (2, 2, 3, 2)
+    Z = rand_cores(dims, ranks, 31, 0.8)
+    X = np.random.default_rng(32).standard_normal(dims)
+    P = np.ones(dims, dtype=np.uint8)
+    new, info = aw.core_update(X, P, Z, k, math.inf, lambda_rel=0.0)
+    assert info.eta == pytest.approx(1.0, abs=1e-10)
+    A = tr.subchain_unfolding(Z, k)
+    sol = np.linalg.lstsq(A, tr.unfold_cyclic(X, k).T, rcond=None)[0].T
+    np.testing.assert_allclose(tr.unfold_core(new), sol, rtol=1e-8, atol=1e-9)
+
+
+def _wls(X, P, Z, k, W, Zk2):
+    A = tr.subchain_unfolding(Z, k)
+    Pk = tr.unfold_cyclic(P, k).astype(bool)
+    E = np.where(Pk, tr.unfold_cyclic(X, k) - Zk2 @ A.T, 0)
+    return 0.5 * np.sum(W * E * E)
+
+
+@pytest.mark.parametrize("sigma", [0.6, math.inf])
+def test_eta_is_exact_line_minimiser_and_decreases(sigma):
+    dims, ranks = (4, 3, 3, 2), (2, 3, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 33)
+    k = 1
+    new, info = aw.core_update(X, P, Z, k, sigma, lambda_rel=1e-6)
+    Zk2 = tr.unfold_core(Z[k])
+    # fit a parabola through three points of L(Z + t h) and locate its minimum
+    ts = np.array([0.0, 0.5, 1.0]) * 2 * info.eta
+    Ls = [_wls(X, P, Z, k, info.W, Zk2 + t * info.h) for t in ts]
+    c2, c1, _ = np.polyfit(ts, Ls, 2)
+    assert -c1 / (2 * c2) == pytest.approx(info.eta, rel=1e-7)
+    assert _wls(X, P, Z, k, info.W, tr.unfold_core(new)) < _wls(X, P, Z, k, info.W, Zk2)
+    # the opposite sign (as printed in eq. 11) increases the objective
+    assert _wls(X, P, Z, k, info.W, Zk2 - info.eta * info.h) > _wls(X, P, Z, k, info.W, Zk2)
+
+
+def test_repeated_masked_steps_reach_rowwise_least_squares():
+    # with W fixed (sigma = inf) repeating the step on one core converges to the
+    # weighted masked LS solution, row by row (textbook lstsq)
+    dims, ranks = (3, 4, 4, 3), (2, 2, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 34, rho=0.7)
+    k = 0
+    cur = [z.copy() for z in Z]
+    for _ in range(300):
+        cur[k], info = aw.core_update(X, P, cur, k, math.inf, lambda_rel=1e-12)
+    A = tr.subchain_unfolding(Z, k)
+    Pk = tr.unfold_cyclic(P, k).astype(bool)
+    Xk = tr.unfold_cyclic(X, k)
+    ref = np.stack([np.linalg.lstsq(A[Pk[i]], Xk[i, Pk[i]], rcond=None)[0] for i in range(dims[k])])
+    np.testing.assert_allclose(tr.unfold_core(cur[k]), ref, rtol=1e-6, atol=1e-7)
+
+
+def test_gradient_direction_variant_also_descends():
+    dims, ranks = (3, 3, 4), (2, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 35)
+    new, info = aw.core_update(X, P, Z, 2, 0.9, direction="gradient")
+    assert _wls(X, P, Z, 2, info.W, tr.unfold_core(new)) < _wls(X, P, Z, 2, info.W, tr.unfold_core(Z[2]))
+
+
+def test_empty_update_gives_zero_step():
+    dims, ranks = (3, 3, 3), (2, 2, 2)
+    Z, _, X = _masked_problem(dims, ranks, 36)
+    P = np.zeros(dims, dtype=np.uint8)
+    new, info = aw.core_update(X, P, Z, 0, 1.0)
+    assert info.eta == 0.0 and info.n_obs == 0
+    np.testing.assert_array_equal(new, Z[0])
+
+
+# ---------------------------------------------------------------- sweep / fit (Alg. 1)
+
+def test_exact_rank_full_observation_fits_to_zero():
+    dims, ranks = (6, 5, 7, 4), (2, 3, 2, 2)
+    Zt = rand_cores(dims, ranks, 41, 0.8)
+    X = tr.reconstruct(Zt)
+    P = np.ones(dims, dtype=np.uint8)
+    g = np.random.default_rng(42)
+    Z0 = [z + 0.05 * g.standard_normal(z.shape) for z in Zt]
+    opts = aw.FitOptions(max_sweeps=60, tol=0.0, sigma_mode="fixed", sigma=math.inf, lambda_rel=1e-13)
+    Z, hist = aw.fit(X, P, Z0, opts)
+    assert aw.relative_error(Z, X) < 1e-8
+
+
+def test_convergence_matrix_invariants():
+    dims, ranks = (3, 4, 5), (2, 3, 2)
+    Z = rand_cores(dims, ranks, 43)
+    D = aw.convergence_matrix(Z)
+    X = tr.reconstruct(Z)
+    np.testing.assert_allclose(D, D.T, rtol=1e-12, atol=1e-12)
+    assert np.trace(D) == pytest.approx(float(np.sum(X * X)), rel=1e-12)
+    Xn = tr.unfold_cyclic(X, 2)
+    np.testing.assert_allclose(D, Xn @ Xn.T, rtol=1e-10, atol=1e-10)
+
+
+def test_robust_fit_downweights_outliers():
+    import synth
+    w = synth.WORKLOADS["tr3_30_r3"]
+    w = synth.scaled(w, (16, 16, 16))
+    Zt, xstar, mask, X = synth.make_workload(w, 0, tr.reconstruct)
+    sel, _ = synth.select_observed(mask, w.outlier_frac, 0)
+    Z0 = synth.perturbed_cores(Zt, 0, rel=0.3)
+    opts = aw.FitOptions(max_sweeps=40, tol=1e-9)
+    Z, hist = aw.fit(X, mask, Z0, opts)
+    assert aw.relative_error(Z, xstar) < 1e-3
+    e = np.abs(X - tr.reconstruct(Z))
+    wts = aw.weights(e, hist["sigma"][-1])
+    assert np.all(wts[sel.astype(bool)] < 1e-3)
+
+
+def test_rsts_with_full_sizes_equals_full_path():
+    dims, ranks = (4, 3, 5), (2, 2, 3)
+    Z, P, X = _masked_problem(dims, ranks, 44)
+    a = aw.FitOptions(max_sweeps=2, tol=0, sigma_mode="fixed", sigma=0.9)
+    b = aw.FitOptions(max_sweeps=2, tol=0, sigma_mode="fixed", sigma=0.9, sketch_sizes=dims)
+    Za, _ = aw.fit(X, P, Z, a)
+    Zb, _ = aw.fit(X, P, Z, b)
+    for u, v in zip(Za, Zb):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_rsts_step_uses_subtensor_identity():
+    # eq. (14): the sketch of the reconstruction is the reconstruction of the sampled cores
+    dims, ranks = (6, 5, 7), (2, 3, 2)
+    Z = rand_cores(dims, ranks, 45)
+    sk = orng.sketch_indices(3, 0, 1, dims, (3, 5, 4))
+    X = tr.reconstruct(Z)
+    np.testing.assert_allclose(X[np.ix_(*sk)], tr.reconstruct([z[:, s, :] for z, s in zip(Z, sk)]),
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_quantile_rule():
+    assert aw.quantile_sigma(np.array([5.0, 1.0, 3.0, 2.0, 4.0]), 0.5, 1.0, 0.0) == 3.0
+    assert aw.quantile_sigma(np.array([5.0, 1.0, 3.0, 2.0]), 0.5, 2.0, 0.0) == 4.0   # rank floor(1.5) = 1
+    assert aw.quantile_sigma(np.array([1e-9]), 0.5, 3.0, 1e-3) == 1e-3
+
+
+# ---------------------------------------------------------------- sampling (RStS index sets)
+
+def test_splitmix64_known_answers():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "splitmix64_kat.txt")) if l[0] != "#"]
+    for seed, n, val in rows:
+        seed, n, val = int(seed), int(n), int(val, 16)
+        assert orng.splitmix64_stream(seed, n)[-1] == val
+        assert orng.counter_u64(seed, n - 1) == val
+
+
+def test_floyd_sample_properties():
+    for key in range(50):
+        s = orng.floyd_sample(orng.mix64(key), 37, 9)
+        assert len(s) == 9 and s == sorted(set(s)) and 0 <= s[0] and s[-1] < 37
+    assert orng.floyd_sample(5, 7, 7) == list(range(7))
+    assert orng.floyd_sample(5, 7, 10) == list(range(7))
+
+
+def test_floyd_inclusion_is_uniform():
+    n, s, trials = 20, 5, 4000
+    cnt = np.zeros(n)
+    for t in range(trials):
+        for i in orng.floyd_sample(orng.sketch_key(9, t, 0, 1), n, s):
+            cnt[i] += 1
+    expected = trials * s / n
+    chi2 = np.sum((cnt - expected) ** 2 / expected)
+    assert chi2 < 45.0        # 19 dof; p ~ 1e-3 threshold
+
+
+def test_bounded_is_uniform_and_in_range():
+    n = 7
+    cnt = np.zeros(n)
+    ctr = 0
+    for _ in range(7000):
+        v, ctr = orng.bounded(12345, ctr, n)
+        cnt[v] += 1
+    assert np.sum((cnt - 1000) ** 2 / 1000) < 22.5   # 6 dof
+
+
+def test_sizes_from_J():
+    assert orng.sizes_from_J(30000, (240, 320, 3, 200)) == [32, 32, 3, 32]
+    assert orng.sizes_from_J(8000, (100, 100, 100, 100)) == [20, 20, 20, 20]
+    assert orng.sizes_from_J(27, (9, 9, 9, 9)) == [3, 3, 3, 3]
