@@ -1,0 +1,232 @@
+/*
+ * trd.h -- C ABI of libtrd: the per-core update sweep of auto-weighted robust
+ * tensor-ring decomposition (AWRTRD) and its sketched form (SAWRTRD), He & Atia,
+ * "Scalable and Robust Tensor Ring Decomposition for Large-scale Data", UAI 2023.
+ *
+ * Every call is extern "C", takes plain pointers and sizes, never throws, and
+ * returns TRD_OK (0) or a negative TRD_E* code; trd_last_error() gives the message.
+ * Calls that take a `stream` (a hipStream_t passed as void*, NULL = default
+ * stream) only enqueue work on it and return before it runs, unless stated.
+ *
+ * Conventions (0-based indices):
+ *  - Tensor X with dims I_0..I_{N-1} is column-major: entry (i_0..i_{N-1}) sits at
+ *    l = sum_j i_j * prod_{j'<j} I_{j'} (the index linearisation of Def. 2).
+ *  - ranks[j] is r_j; core j is r_j x I_j x r_{(j+1) mod N} (Def. 1) and is stored
+ *    as its mode-2 unfolding Z_{j(2)} row-major: element (a, i, b) at
+ *    i*r_j*r_{j+1} + b*r_j + a, so each lateral slice Z_j(i) is a contiguous
+ *    column-major r_j x r_{j+1} matrix.  d and h of eqs. (9)-(10) use the same layout.
+ *  - `cores` arguments are host arrays of N device pointers, one per core, in the
+ *    problem dtype.
+ *  - Limits: 2 <= N <= 8, 1 <= r_j <= 16, r_k * r_s <= 128 for the pair the fused
+ *    pass contracts (r_s the rank at the split of the subchain), every
+ *    r_k*r_{k+1} <= 256, dims >= 1, prod(dims) < 2^62, observed entries < 2^31.
+ *
+ * Ownership: the library owns only the workspace inside a trd_ctx.  X, mask, cores
+ * and all outputs are borrowed caller memory; they must stay valid until the
+ * enqueued work that reads or writes them has finished.
+ */
+#ifndef TRD_H
+#define TRD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TRD_OK            0
+#define TRD_EINVAL       -1   /* bad argument */
+#define TRD_ENOMEM       -2   /* device allocation failed */
+#define TRD_EDEVICE      -3   /* HIP runtime error */
+#define TRD_ENOTSPD      -4   /* G + lambda I not positive definite (eq. 10) */
+#define TRD_ESTATE       -5   /* call needs trd_set_problem first */
+#define TRD_EUNSUPPORTED -6   /* size outside the limits above */
+
+/* element types */
+#define TRD_F32 0
+#define TRD_F64 1
+
+/* precision of the entry-wise passes (problem dtype TRD_F32 only for BF16) */
+#define TRD_PREC_NATIVE 0     /* subchain tables and passes in the problem dtype */
+#define TRD_PREC_BF16   1     /* subchain tables in bf16, residual/weights/accumulators fp32 */
+
+/* device flag bits written by trd_step / trd_fit */
+#define TRD_FLAG_EMPTY     1u /* the update touched no observed entry: eta = 0 */
+#define TRD_FLAG_ZERO_DEN  2u /* line-search denominator <= 0 or not finite: eta = 0 */
+#define TRD_FLAG_NOTSPD    4u /* G + lambda I not positive definite: h = 0, eta = 0 */
+
+/* kernel-width schedule modes for trd_fit */
+#define TRD_SIGMA_FIXED    0
+#define TRD_SIGMA_GIVEN    1
+#define TRD_SIGMA_QUANTILE 2
+
+typedef struct trd_ctx trd_ctx;
+
+/*
+ * Randomized subtensor sketch (RStS, Sec. 4.2.2, eq. 14, Alg. 1): for update k
+ * every mode j != k keeps sizes[j] lateral slices chosen uniformly without
+ * replacement (sorted ascending), mode k keeps all I_k.  When `idx` is NULL the
+ * library draws the sets itself from (seed, sweep, k, j) with the counter-based
+ * SplitMix64 generator described at trd_sample_sketch; otherwise idx[j] (host array
+ * of N device pointers) holds the caller's sorted index list for mode j, of length
+ * sizes[j] (ignored for j == k).
+ */
+typedef struct trd_sketch {
+  uint64_t seed;
+  int32_t sweep;
+  int32_t sizes[8];
+  const int32_t* const* idx;
+} trd_sketch;
+
+typedef struct trd_fit_opts {
+  int32_t max_sweeps;        /* C of Alg. 1 */
+  double tol;                /* epsilon of Alg. 1 (no test after the first sweep) */
+  double lambda_rel;         /* lambda of eq. (10) = lambda_rel * tr(G) / R^2 */
+  int32_t sigma_mode;        /* TRD_SIGMA_* */
+  double sigma;              /* FIXED: kernel width (+inf = masked least squares) */
+  const double* sigma_given; /* GIVEN: host array, one width per sweep */
+  double q, c, shrink;       /* QUANTILE: sigma_t = max(c*Q_q|e|, sigma_min, shrink*sigma_{t-1}) */
+  double sigma_min_rel;      /* QUANTILE: sigma_min = sigma_min_rel * max |x| over observed */
+  int32_t use_sketch;        /* 0: full path (AWRTRD); 1: RStS (SAWRTRD) */
+  int32_t sketch_sizes[8];
+  uint64_t seed;
+  int32_t precision;         /* TRD_PREC_* */
+} trd_fit_opts;
+
+typedef struct trd_fit_report {
+  int32_t sweeps;            /* sweeps run */
+  double last_e;             /* relative change of D^t at the last sweep */
+  double last_sigma;
+  uint32_t flags;            /* OR of the step flags over the run */
+  double* e_hist;            /* optional host array [max_sweeps] (NULL = skip) */
+  double* sigma_hist;        /* optional host array [max_sweeps] */
+  double* eta_hist;          /* optional host array [max_sweeps * N] */
+} trd_fit_report;
+
+/* Create a context on HIP device `device`.  Allocates nothing on the device yet. */
+int trd_create(trd_ctx** out, int device);
+/* Free the context and its workspace.  NULL is ignored. */
+void trd_destroy(trd_ctx* ctx);
+/* Message of the last failure on ctx (or of the last context-free call when ctx is NULL). */
+const char* trd_last_error(const trd_ctx* ctx);
+
+/*
+ * Bind a problem (Alg. 1 inputs X, mask P of eq. 2, TR ranks) and build the
+ * observed-entry layouts, one per core: for core k the entries are grouped as a
+ * matrix whose rows are (i_k, the first modes of the cyclic subchain) and whose
+ * columns are the remaining modes (Thm. 1), cut into 256-row x column tiles and
+ * stored as 64-row sliced ELL lists (value, column-in-tile).
+ *  X: device, prod(dims) values of `dtype` (column-major).  mask: device uint8, same
+ *  size, nonzero = observed.  Values where mask == 0 are never used.  Both are read
+ *  only during this call and by later RStS updates (so keep them alive while
+ *  sketches are used).  Synchronizes `stream`.  Returns TRD_EUNSUPPORTED outside the
+ *  limits in the file header.
+ */
+int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ranks, int dtype,
+                    const void* X, const uint8_t* mask, void* stream);
+
+/* Host-side query: observed count, bytes of device workspace held, and the
+ * subchain split chosen for core k (rows = I_k times the first `split` modes). */
+int trd_problem_info(const trd_ctx* ctx, int64_t* n_obs, size_t* workspace_bytes, int32_t* split);
+
+/*
+ * TR reconstruction (Def. 1): out[t] = Tr(Z_0(i_0) ... Z_{N-1}(i_{N-1})) for the
+ * entry at column-major linear index lin_idx[t] (device int64, n entries), or for
+ * every entry in column-major order when lin_idx is NULL (then n must equal
+ * prod(dims)).  out: device, problem dtype.
+ */
+int trd_reconstruct(trd_ctx* ctx, const void* const* cores, const int64_t* lin_idx, int64_t n,
+                    void* out, void* stream);
+
+/*
+ * Correntropy weights of eq. (7): w = exp(-e^2 / (2 sigma^2)) (sign reading: the
+ * printed g'(x)/x is negative for the stated kernel; w in (0, 1], w(0) = 1).
+ * sigma = +inf gives w = 1.  resid, w_out: device, n values of dtype.
+ * TRD_EINVAL for sigma <= 0 or NaN.  Needs no context.
+ */
+int trd_weights(const void* resid, int64_t n, int dtype, double sigma, void* w_out, void* stream);
+
+/*
+ * Gradient of eq. (9) (full path) or eq. (15) (sketch != NULL) for core k:
+ * d = (W o P o (X_[k] - Z_{k(2)} A^T)) A with A the subchain unfolding, W from the
+ * current residual.  d_out: device, I_k * r_k * r_{k+1} values of the problem dtype
+ * (core layout).  stats_dev: optional device double[3] receiving
+ * {sum sigma^2 (1 - w), sum w e^2, observed count} over the touched entries.
+ */
+int trd_grad(trd_ctx* ctx, const void* const* cores, int k, double sigma, const trd_sketch* sketch,
+             void* d_out, double* stats_dev, void* stream);
+
+/*
+ * Gram matrix G^{!=k} = A^T A of the full subchain by FGMC (Prop. 2, eq. 13): the
+ * ring product of K_j = sum_i Z_j(i) (x) Z_j(i) over j != k in cyclic order, then
+ * realigned.  G_out: device double, R x R row-major with R = r_k r_{k+1} and row
+ * index a + b*r_k (a < r_k, b < r_{k+1}).  Computed in FP64.
+ */
+int trd_fgmc_gram(trd_ctx* ctx, const void* const* cores, int k, double* G_out, void* stream);
+
+/*
+ * One core update (Alg. 1 body, eqs. 9-12 or 15-18): gradient, FGMC Gram of the
+ * full cores, h = d (G + lambda I)^{-1} with lambda = lambda_rel * tr(G)/R^2,
+ * exact line search eta = <d, h> / ||sqrt(W) o P o (h A^T)||^2, and the update
+ * Z_k <- Z_k + eta * fold(h) (sign reading: d is the negative gradient, eta the
+ * minimiser along +h).  cores[k] is updated in place.  eta_dev (optional device
+ * double) receives eta; flags_dev (optional device uint32) is OR-ed with TRD_FLAG_*.
+ */
+int trd_step(trd_ctx* ctx, void* const* cores, int k, double sigma, double lambda_rel,
+             const trd_sketch* sketch, double* eta_dev, uint32_t* flags_dev, void* stream);
+
+/*
+ * Algorithm 1: sweeps k = 0..N-1 (Gauss-Seidel) until max_sweeps or the relative
+ * change e = ||D^t - D^{t-1}||_F / ||D^t||_F of D^t = Z_{N(2)} G^{!=N} Z_{N(2)}^T
+ * falls below tol (no test after the first sweep).  cores updated in place.
+ * Synchronizes `stream` once per sweep.  Returns TRD_ENOTSPD if a step hit a
+ * non-positive-definite G + lambda I (the run stops after that sweep).
+ */
+int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* opts, trd_fit_report* report,
+            void* stream);
+
+/*
+ * Differentiation form: L = sum over observed of sigma^2 (1 - exp(-e^2 / 2 sigma^2))
+ * (sigma = +inf: sum e^2 / 2), the Welsch loss equal to sum g_sigma(0) - g_sigma(e)
+ * for the correntropy objective of eq. (4).  loss_dev: device double.
+ */
+int trd_loss_fwd(trd_ctx* ctx, const void* const* cores, double sigma, double* loss_dev, void* stream);
+/*
+ * Its gradient for every core at one point: dL/dZ_k = -fold(d_k) with d_k of eq. (9)
+ * and W = w(E) at the same cores (half-quadratic identity); subchain tables are
+ * recomputed per core, never stored for all k.  grads_out[k] (device, problem dtype,
+ * core layout) receives grad_scale * dL/dZ_k.
+ */
+int trd_loss_bwd(trd_ctx* ctx, const void* const* cores, double sigma, double grad_scale,
+                 void* const* grads_out, void* stream);
+
+/*
+ * Draw the RStS index sets of update k in sweep t on the device: for each mode
+ * j != k, s_j = min(sizes[j], I_j) distinct indices of [0, I_j), uniform, sorted;
+ * mode k gets 0..I_k-1.  Generator: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014)
+ * in counter form, u(key, c) = mix64(key + (c+1) * 0x9E3779B97F4A7C15);
+ * key = u(u(u(seed ^ 0x5253545300000000, t), k), j); bounded draws by Lemire's
+ * multiply-shift with rejection on the top 32 bits; subsets by Floyd's algorithm.
+ * idx_out: host array of N device pointers, idx_out[j] with room for min(sizes[j], I_j)
+ * int32 (I_k for j == k).  Needs no context.
+ */
+int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, const int32_t* sizes,
+                      int32_t* const* idx_out, void* stream);
+
+/*
+ * Per-launch timing of the fused reconstruct+weight+gradient pass, for measurement:
+ * enable != 0 records HIP events around every launch of that kernel on its stream;
+ * trd_profile_read returns the number of launches and their summed duration (ms) and
+ * summed entry slots since the last read, then resets the counters (synchronizes).
+ */
+int trd_profile(trd_ctx* ctx, int enable);
+int trd_profile_read(trd_ctx* ctx, int64_t* launches, double* total_ms, int64_t* slots,
+                     int64_t* entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRD_H */

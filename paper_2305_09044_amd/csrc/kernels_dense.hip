@@ -1,0 +1,548 @@
+// Small dense FP64 pieces of the update: FGMC factors and ring product (eq. 13),
+// the scaled direction (eq. 10) through an in-LDS Gauss-Jordan inverse of the SPD
+// matrix G + lambda I, the exact line-search step (eq. 12), the core update (eq. 11),
+// the convergence matrix of Alg. 1, the weights of eq. (7) and TR reconstruction (Def. 1).
+#include "trd_internal.h"
+
+#include <cmath>
+
+namespace trd {
+
+static int grid_for(int64_t n, int threads, int64_t cap = 1 << 20) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+// ---------------------------------------------------------------- FGMC
+
+// K[(al*r0 + al2), (be*r1 + be2)] = sum_i Z(i)[al, be] * Z(i)[al2, be2]
+template <typename real>
+__global__ void k_kron(const real* __restrict__ Z, int r0, int64_t I, int r1, double* __restrict__ K) {
+  const int64_t n = (int64_t)r0 * r0 * r1 * r1;
+  const int cols = r1 * r1;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int rr = (int)(t / cols), cc = (int)(t % cols);
+    const int al = rr / r0, al2 = rr % r0, be = cc / r1, be2 = cc % r1;
+    const int64_t sl = (int64_t)r0 * r1;
+    double s = 0.0;
+    for (int64_t i = 0; i < I; ++i) {
+      const real* zi = Z + i * sl;
+      s = fma((double)zi[al + r0 * be], (double)zi[al2 + r0 * be2], s);
+    }
+    K[t] = s;
+  }
+}
+
+hipError_t launch_kron_factor(int dtype, const void* Z, int r0, int64_t I, int r1, double* K,
+                              hipStream_t st) {
+  const int64_t n = (int64_t)r0 * r0 * r1 * r1;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_kron<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, (const float*)Z,
+                       r0, I, r1, K);
+  else
+    hipLaunchKernelGGL(k_kron<double>, dim3(grid_for(n, 256)), dim3(256), 0, st,
+                       (const double*)Z, r0, I, r1, K);
+  return hipGetLastError();
+}
+
+// C = A (m x kk) @ B (kk x n), row-major FP64
+__global__ void k_gemm64(const double* __restrict__ A, const double* __restrict__ B,
+                         double* __restrict__ C, int m, int kk, int n) {
+  const int64_t total = (int64_t)m * n;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t / n), j = (int)(t % n);
+    double s = 0.0;
+    for (int l = 0; l < kk; ++l) s = fma(A[(int64_t)i * kk + l], B[(int64_t)l * n + j], s);
+    C[t] = s;
+  }
+}
+
+hipError_t launch_gemm64(const double* A, const double* B, double* C, int m, int kk, int n,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_gemm64, dim3(grid_for((int64_t)m * n, 256)), dim3(256), 0, st, A, B, C, m,
+                     kk, n);
+  return hipGetLastError();
+}
+
+// G[(a + b r_k), (a2 + b2 r_k)] = P[(b r_k1 + b2), (a r_k + a2)]
+__global__ void k_realign(const double* __restrict__ P, double* __restrict__ G, int r_k, int r_k1) {
+  const int R = r_k * r_k1;
+  const int64_t total = (int64_t)R * R;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t / R), j = (int)(t % R);
+    const int a = i % r_k, b = i / r_k, a2 = j % r_k, b2 = j / r_k;
+    G[t] = P[(int64_t)(b * r_k1 + b2) * (r_k * r_k) + (a * r_k + a2)];
+  }
+}
+
+hipError_t launch_realign(const double* P, double* G, int r_k, int r_k1, hipStream_t st) {
+  const int64_t R = (int64_t)r_k * r_k1;
+  hipLaunchKernelGGL(k_realign, dim3(grid_for(R * R, 256)), dim3(256), 0, st, P, G, r_k, r_k1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scaled direction
+
+// Cinv = (G + lambda I)^{-1}, lambda = lambda_rel * tr(G) / n, by in-place Gauss-Jordan
+// elimination without pivoting (stable for SPD matrices, whose pivots are the positive
+// Schur-complement diagonals).  A pivot <= 64 eps * max diag (or not finite) marks the
+// matrix as not positive definite: flag set, Cinv = 0.
+template <bool kLDS>
+__global__ __launch_bounds__(1024) void k_inverse(const double* __restrict__ G,
+                                                  double* __restrict__ Cinv, int n,
+                                                  double lambda_rel, uint32_t* flags) {
+  extern __shared__ double lds[];
+  __shared__ double f[256];
+  __shared__ double s_lam, s_thr;
+  __shared__ int s_bad;
+  double* A = kLDS ? lds : Cinv;
+  const int nn = n * n;
+  if (threadIdx.x == 0) {
+    double tr = 0.0, mx = 0.0;
+    for (int i = 0; i < n; ++i) {
+      tr += G[(int64_t)i * n + i];
+      mx = fmax(mx, G[(int64_t)i * n + i]);
+    }
+    const double lam = lambda_rel * tr / n;
+    s_lam = lam;
+    s_thr = 64.0 * 2.220446049250313e-16 * (mx + lam);
+    s_bad = 0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int i = t / n, j = t % n;
+    A[t] = G[t] + (i == j ? s_lam : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = A[k * n + k];
+    if (!(piv > s_thr) || !isfinite(piv)) {
+      if (threadIdx.x == 0) s_bad = 1;
+      break;  // uniform: every thread read the same pivot
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) f[i] = A[i * n + k];
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * inv;
+    __syncthreads();
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+      const int i = t / n, j = t % n;
+      if (i != k) A[t] = (j == k ? 0.0 : A[t]) - f[i] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const bool bad = s_bad != 0;
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) Cinv[t] = bad ? 0.0 : A[t];
+  if (bad && threadIdx.x == 0) atomicOr(flags, TRD_FLAG_NOTSPD_BIT);
+}
+
+hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
+                          uint32_t* flags, hipStream_t st) {
+  if ((int64_t)n * n * (int64_t)sizeof(double) + 4096 <= g_lds_max) {
+    hipLaunchKernelGGL(k_inverse<true>, dim3(1), dim3(1024), (size_t)n * n * sizeof(double), st,
+                       G, Cinv, n, lambda_rel, flags);
+  } else {
+    hipLaunchKernelGGL(k_inverse<false>, dim3(1), dim3(1024), 0, st, G, Cinv, n, lambda_rel,
+                       flags);
+  }
+  return hipGetLastError();
+}
+
+// h = d Cinv (I_k x n), written in FP64 and in the problem dtype; per-block partial
+// sums of <d, h> (fixed order).  A NOTSPD flag zeroes h.
+template <typename real>
+__global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict__ d64,
+                                                       const double* __restrict__ Cinv, int64_t Ik,
+                                                       int n, double* __restrict__ h64,
+                                                       real* __restrict__ h_real,
+                                                       double* __restrict__ part,
+                                                       const uint32_t* flags) {
+  __shared__ double red[4];
+  const int64_t total = Ik * n;
+  const bool bad = (*flags & TRD_FLAG_NOTSPD_BIT) != 0;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double contrib = 0.0;
+  if (t < total) {
+    const int64_t i = t / n;
+    const int c = (int)(t % n);
+    double s = 0.0;
+    if (!bad)
+      for (int l = 0; l < n; ++l) s = fma(d64[i * n + l], Cinv[(int64_t)l * n + c], s);
+    h64[t] = s;
+    if (h_real) h_real[t] = (real)s;
+    contrib = d64[t] * s;
+  }
+  for (int o = 32; o > 0; o >>= 1) contrib += __shfl_xor(contrib, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = contrib;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t launch_apply_inverse(const double* d64, const double* Cinv, int64_t Ik, int n,
+                                double* h64, void* h_real, int dtype, double* part_num,
+                                const uint32_t* flags, hipStream_t st) {
+  const int64_t total = Ik * n;
+  const int nb = (int)((total + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_apply_inverse<float>, dim3(nb), dim3(256), 0, st, d64, Cinv, Ik, n, h64,
+                       (float*)h_real, part_num, flags);
+  else
+    hipLaunchKernelGGL(k_apply_inverse<double>, dim3(nb), dim3(256), 0, st, d64, Cinv, Ik, n, h64,
+                       (double*)h_real, part_num, flags);
+  return hipGetLastError();
+}
+
+// out[c] = sum over rows r < n of part[r*width + c], c < width; one work-group,
+// fixed per-thread assignment and fixed tree order.
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part, int64_t n,
+                                                 int width, double* __restrict__ out) {
+  __shared__ double buf[1024];
+  for (int c = 0; c < width; ++c) {
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += 1024) s += part[r * width + c];
+    buf[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+      if (threadIdx.x < o) buf[threadIdx.x] += buf[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = buf[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_reduce_partials(const double* part, int64_t n, int width, double* out,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, part, n, width, out);
+  return hipGetLastError();
+}
+
+__global__ void k_set_scalar(double* p, double v) { *p = v; }
+
+hipError_t launch_set_scalar(double* p, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
+}
+
+// eta of eq. (12) = num / den; 0 with a flag when nothing was observed or den <= 0.
+__global__ void k_eta(const double* num, const double* den, const int64_t* nobs, double* eta,
+                      uint32_t* flags, uint32_t* flags_user, double* eta_user) {
+  const double a = *num, b = *den;
+  uint32_t f = *flags;
+  double e = 0.0;
+  if (*nobs == 0) f |= TRD_FLAG_EMPTY_BIT;
+  if (!(b > 0.0) || !isfinite(b) || !isfinite(a)) f |= TRD_FLAG_ZERO_DEN_BIT;
+  else e = a / b;
+  if (f & TRD_FLAG_NOTSPD_BIT) e = 0.0;
+  *eta = e;
+  *flags = f;
+  if (eta_user) *eta_user = e;
+  if (flags_user) *flags_user |= f;
+}
+
+hipError_t launch_eta(const double* num, const double* den, const int64_t* nobs, double* eta,
+                      uint32_t* flags, uint32_t* flags_user, double* eta_user, hipStream_t st) {
+  hipLaunchKernelGGL(k_eta, dim3(1), dim3(1), 0, st, num, den, nobs, eta, flags, flags_user,
+                     eta_user);
+  return hipGetLastError();
+}
+
+// Z_k <- Z_k + eta * h (eq. 11 with the '+' reading)
+template <typename real>
+__global__ void k_update(real* __restrict__ Z, const double* __restrict__ h, const double* eta,
+                         int64_t n) {
+  const double e = *eta;
+  if (e == 0.0) return;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    Z[t] = (real)fma(e, h[t], (double)Z[t]);
+}
+
+hipError_t launch_update(int dtype, void* Z, const double* h64, const double* eta, int64_t n,
+                         hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_update<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, (float*)Z, h64,
+                       eta, n);
+  else
+    hipLaunchKernelGGL(k_update<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, (double*)Z,
+                       h64, eta, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- convergence (Alg. 1)
+
+template <typename real>
+__global__ void k_zg(const real* __restrict__ Z, const double* __restrict__ G, int64_t IN, int n,
+                     double* __restrict__ M) {
+  const int64_t total = IN * n;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / n;
+    const int c = (int)(t % n);
+    double s = 0.0;
+    for (int l = 0; l < n; ++l) s = fma((double)Z[i * n + l], G[(int64_t)l * n + c], s);
+    M[t] = s;
+  }
+}
+
+// D = M Z^T, with per-block partials of sum (D - Dprev)^2 and sum D^2
+template <typename real>
+__global__ __launch_bounds__(256) void k_mzt(const double* __restrict__ M, const real* __restrict__ Z,
+                                             int64_t IN, int n, double* __restrict__ D,
+                                             const double* __restrict__ Dprev, int have_prev,
+                                             double* __restrict__ part) {
+  __shared__ double red[2][4];
+  const int64_t total = IN * IN;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double a = 0.0, b = 0.0;
+  if (t < total) {
+    const int64_t i = t / IN, j = t % IN;
+    double s = 0.0;
+    for (int l = 0; l < n; ++l) s = fma(M[i * n + l], (double)Z[j * n + l], s);
+    D[t] = s;
+    const double dd = have_prev ? s - Dprev[t] : s;
+    a = dd * dd;
+    b = s * s;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const double* r = red[threadIdx.x];
+    part[blockIdx.x * 2 + threadIdx.x] = (r[0] + r[1]) + (r[2] + r[3]);
+  }
+}
+
+hipError_t launch_convergence(int dtype, const void* ZN, const double* G, int64_t IN, int n,
+                              double* M, double* D, const double* Dprev, int have_prev,
+                              double* part, hipStream_t st) {
+  // part must hold 2 * ceil(IN*IN/256) doubles; the caller reduces it (width 2)
+  if (dtype == 0) {
+    hipLaunchKernelGGL(k_zg<float>, dim3(grid_for(IN * n, 256)), dim3(256), 0, st,
+                       (const float*)ZN, G, IN, n, M);
+    hipLaunchKernelGGL(k_mzt<float>, dim3((unsigned)((IN * IN + 255) / 256)), dim3(256), 0, st, M,
+                       (const float*)ZN, IN, n, D, Dprev, have_prev, part);
+  } else {
+    hipLaunchKernelGGL(k_zg<double>, dim3(grid_for(IN * n, 256)), dim3(256), 0, st,
+                       (const double*)ZN, G, IN, n, M);
+    hipLaunchKernelGGL(k_mzt<double>, dim3((unsigned)((IN * IN + 255) / 256)), dim3(256), 0, st,
+                       M, (const double*)ZN, IN, n, D, Dprev, have_prev, part);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- weights (eq. 7)
+
+template <typename real>
+__global__ void k_weights(const real* __restrict__ r, int64_t n, real inv2s2, int lim,
+                          real* __restrict__ w) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const real e = r[t];
+    w[t] = lim ? real(1) : exp(-(e * e) * inv2s2);
+  }
+}
+
+hipError_t launch_weights(int dtype, const void* r, int64_t n, double sigma, void* w,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int lim = std::isinf(sigma) ? 1 : 0;
+  const double inv = lim ? 0.0 : 0.5 / (sigma * sigma);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_weights<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, (const float*)r,
+                       n, (float)inv, lim, (float*)w);
+  else
+    hipLaunchKernelGGL(k_weights<double>, dim3(grid_for(n, 256)), dim3(256), 0, st,
+                       (const double*)r, n, inv, lim, (double*)w);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reconstruction (Def. 1)
+
+struct CoreSet {
+  const void* core[kMaxN];
+  int64_t dims[kMaxN];
+  int ranks[kMaxN];
+  int N;
+};
+
+// x = sum_a (e_a^T Z_0(i_0) Z_1(i_1) ... Z_{N-1}(i_{N-1}))[a], one row vector at a time
+template <typename real, int MAXR>
+__global__ void k_reconstruct(CoreSet cs, const int64_t* __restrict__ lin, int64_t n,
+                              int64_t total, real* __restrict__ out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = lin ? lin[t] : t;
+    if (rem < 0 || rem >= total) {  // out-of-range request: NaN, no read
+      out[t] = real(NAN);
+      continue;
+    }
+    int64_t idx[kMaxN];
+    for (int j = 0; j < cs.N; ++j) {
+      idx[j] = rem % cs.dims[j];
+      rem /= cs.dims[j];
+    }
+    const int r0 = cs.ranks[0];
+    real total = real(0);
+    for (int a = 0; a < r0; ++a) {
+      real v[MAXR], nv[MAXR];
+#pragma unroll
+      for (int b = 0; b < MAXR; ++b) v[b] = b == a ? real(1) : real(0);
+      int rin = r0;
+      for (int j = 0; j < cs.N; ++j) {
+        const int rout = cs.ranks[(j + 1) % cs.N];
+        const real* zs = static_cast<const real*>(cs.core[j]) + idx[j] * (int64_t)rin * rout;
+#pragma unroll
+        for (int c = 0; c < MAXR; ++c) {
+          real s = real(0);
+          if (c < rout) {
+#pragma unroll
+            for (int b = 0; b < MAXR; ++b)
+              if (b < rin) s = fma(v[b], zs[b + rin * c], s);
+          }
+          nv[c] = s;
+        }
+#pragma unroll
+        for (int c = 0; c < MAXR; ++c) v[c] = nv[c];
+        rin = rout;
+      }
+#pragma unroll
+      for (int b = 0; b < MAXR; ++b)
+        if (b == a) total += v[b];
+    }
+    out[t] = total;
+  }
+}
+
+template <typename real>
+static hipError_t recon_real(const CoreSet& cs, int maxr, const int64_t* lin, int64_t n, void* out,
+                             hipStream_t st) {
+  dim3 g(grid_for(n, 256, 1 << 16)), b(256);
+  int64_t total = 1;
+  for (int j = 0; j < cs.N; ++j) total *= cs.dims[j];
+  if (maxr <= 4)
+    hipLaunchKernelGGL((k_reconstruct<real, 4>), g, b, 0, st, cs, lin, n, total, (real*)out);
+  else if (maxr <= 8)
+    hipLaunchKernelGGL((k_reconstruct<real, 8>), g, b, 0, st, cs, lin, n, total, (real*)out);
+  else
+    hipLaunchKernelGGL((k_reconstruct<real, 16>), g, b, 0, st, cs, lin, n, total, (real*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(int dtype, int N, const int64_t* dims, const int32_t* ranks,
+                              const void* const* cores, const int64_t* lin, int64_t n, void* out,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  CoreSet cs;
+  cs.N = N;
+  int maxr = 1;
+  for (int j = 0; j < kMaxN; ++j) {
+    cs.core[j] = j < N ? cores[j] : nullptr;
+    cs.dims[j] = j < N ? dims[j] : 1;
+    cs.ranks[j] = j < N ? ranks[j] : 1;
+    if (j < N && ranks[j] > maxr) maxr = ranks[j];
+  }
+  return dtype == 0 ? recon_real<float>(cs, maxr, lin, n, out, st)
+                    : recon_real<double>(cs, maxr, lin, n, out, st);
+}
+
+// ---------------------------------------------------------------- kernel-width quantile
+// Radix select of the element of rank floor((n-1) q) among non-negative float keys
+// (padding slots hold +inf and sort last), digits of 11, 11 and 10 bits.
+// state: [0] prefix, [1] remaining rank (as uint32 pair), [3] valid.
+
+__global__ __launch_bounds__(256) void k_qhist(const float* __restrict__ keys,
+                                               const int64_t* __restrict__ nslots, int shift,
+                                               int bits, const uint32_t* __restrict__ state,
+                                               uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[2048];
+  const uint32_t nb = 1u << bits;
+  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) lh[i] = 0u;
+  __syncthreads();
+  const int64_t n = *nslots;
+  const uint32_t prefix = state[0];
+  const int hi_shift = shift + bits;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = __float_as_uint(keys[i]);
+    const bool match = hi_shift >= 32 ? true : ((key >> hi_shift) == prefix);
+    if (match) atomicAdd(&lh[(key >> shift) & (nb - 1u)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+    if (lh[i]) atomicAdd(&hist[i], lh[i]);
+}
+
+__global__ void k_qinit(const int64_t* nobs, double q, uint32_t* state, uint32_t* hist) {
+  const int64_t n = *nobs;
+  uint64_t rank = 0;
+  if (n > 0) rank = (uint64_t)floor((double)(n - 1) * q);
+  state[0] = 0u;
+  state[1] = (uint32_t)(rank & 0xFFFFFFFFu);
+  state[2] = (uint32_t)(rank >> 32);
+  state[3] = n > 0 ? 1u : 0u;
+  for (int i = 0; i < 2048; ++i) hist[i] = 0u;
+}
+
+__global__ void k_qpick(int bits, uint32_t* state, uint32_t* hist) {
+  const uint32_t nb = 1u << bits;
+  uint64_t rank = (uint64_t)state[1] | ((uint64_t)state[2] << 32);
+  uint64_t cum = 0;
+  uint32_t b = 0;
+  for (; b < nb; ++b) {
+    if (cum + hist[b] > rank) break;
+    cum += hist[b];
+  }
+  if (b == nb) b = nb - 1u;  // only when nothing matched (no observed entries)
+  rank -= cum;
+  state[0] = (state[0] << bits) | b;
+  state[1] = (uint32_t)(rank & 0xFFFFFFFFu);
+  state[2] = (uint32_t)(rank >> 32);
+  for (uint32_t i = 0; i < nb; ++i) hist[i] = 0u;
+}
+
+__global__ void k_qsigma(const uint32_t* state, double c, const double* sigma_min, double shrink,
+                         double* sigma) {
+  const double smin = *sigma_min;
+  double s;
+  if (state[3] == 0u) {
+    s = smin > 0.0 ? smin : 1.0;
+  } else {
+    const double qv = (double)__uint_as_float(state[0]);
+    s = fmax(c * qv, smin);
+  }
+  const double prev = *sigma;
+  if (isfinite(prev)) s = fmax(s, shrink * prev);
+  *sigma = s;
+}
+
+hipError_t launch_quantile_sigma(const float* keys, int64_t n_slots_hint, const int64_t* nslots,
+                                 double q, double c, const double* sigma_min, double shrink,
+                                 double* sigma, uint32_t* hist, uint32_t* state,
+                                 const int64_t* nobs, hipStream_t st) {
+  hipLaunchKernelGGL(k_qinit, dim3(1), dim3(1), 0, st, nobs, q, state, hist);
+  const int shifts[3] = {21, 10, 0};
+  const int bitsv[3] = {11, 11, 10};
+  const int g = grid_for(n_slots_hint, 256, 2048);
+  for (int r = 0; r < 3; ++r) {
+    hipLaunchKernelGGL(k_qhist, dim3(g), dim3(256), 0, st, keys, nslots, shifts[r], bitsv[r],
+                       state, hist);
+    hipLaunchKernelGGL(k_qpick, dim3(1), dim3(1), 0, st, bitsv[r], state, hist);
+  }
+  hipLaunchKernelGGL(k_qsigma, dim3(1), dim3(1), 0, st, state, c, sigma_min, shrink, sigma);
+  return hipGetLastError();
+}
+
+}  // namespace trd

@@ -1,0 +1,336 @@
+// Observed-entry layouts (sliced ELL per core-k matrix) and RStS index sampling.
+#include "trd_internal.h"
+
+namespace trd {
+
+// ---------------------------------------------------------------- small utilities
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+static int grid_for(int64_t n, int threads, int cap = 4096) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// out[i] = in[i] clamped into [0, dim); any clamped entry raises *bad
+__global__ void k_copy_clamp(const int32_t* __restrict__ in, int64_t n, int64_t dim,
+                             int32_t* __restrict__ out, uint32_t* bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t v = in[i];
+    if (v < 0 || v >= dim) {
+      atomicOr(bad, 1u);
+      v = v < 0 ? 0 : dim - 1;
+    }
+    out[i] = (int32_t)v;
+  }
+}
+
+hipError_t launch_copy_clamp(const int32_t* in, int64_t n, int64_t dim, int32_t* out,
+                             uint32_t* bad, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_clamp, dim3(grid_for(n, 256)), dim3(256), 0, st, in, n, dim, out, bad);
+  return hipGetLastError();
+}
+
+// Zero a buffer with a kernel (no memset node, so it is safe inside captured graphs).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  // callers only zero 4-byte-multiple buffers
+  int64_t n = (int64_t)(bytes / 4);
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, 256)), dim3(256), 0, st, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- offsets
+// out[t] = sum_j idx_j(t) * stride_j, t decoded little-endian over the mode counts.
+
+__global__ void k_offsets(ModeSet ms, int64_t n, int64_t* out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = t, off = 0;
+    for (int j = 0; j < ms.n; ++j) {
+      int64_t d = rem % ms.count[j];
+      rem /= ms.count[j];
+      int64_t idx = ms.list[j] ? (int64_t)ms.list[j][d] : d;
+      off += idx * ms.stride[j];
+    }
+    out[t] = off;
+  }
+}
+
+hipError_t launch_offsets(const ModeSet& ms, int64_t n, int64_t* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_offsets, dim3(grid_for(n, 256)), dim3(256), 0, st, ms, n, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- count / slices / scan / fill
+// Work-group w <-> (column tile ct, row group g) with w = ct * n_rg + g; thread t of the
+// group owns row g*256 + t; slice id = w*4 + t/64, lane = t%64.
+
+struct LayoutArgs {
+  const int64_t* rowoff;
+  const int64_t* coloff;
+  int32_t* counts;
+  int32_t* slice_len;
+  int64_t* slice_off;
+  int64_t* total;
+  int64_t* nobs;
+  int64_t nrows, ncols, n_rg, n_slices;
+  int ct_w, n_ct;
+};
+
+static LayoutArgs largs(const Layout& L) {
+  LayoutArgs a;
+  a.rowoff = L.rowoff; a.coloff = L.coloff; a.counts = L.counts; a.slice_len = L.slice_len;
+  a.slice_off = L.slice_off; a.total = L.total_dev; a.nobs = L.nobs_dev;
+  a.nrows = L.nrows; a.ncols = L.ncols; a.n_rg = L.n_rg; a.n_slices = L.n_slices;
+  a.ct_w = L.ct_w; a.n_ct = L.n_ct;
+  return a;
+}
+
+__global__ __launch_bounds__(256) void k_count(LayoutArgs a, const uint8_t* __restrict__ mask) {
+  const int64_t w = blockIdx.x;
+  const int64_t ct = w / a.n_rg, g = w % a.n_rg;
+  const int64_t row = g * kRowsPerWG + threadIdx.x;
+  const int64_t col0 = ct * a.ct_w;
+  const int64_t nct = min((int64_t)a.ct_w, a.ncols - col0);
+  int cnt = 0;
+  if (row < a.nrows) {
+    const int64_t ro = a.rowoff[row];
+    for (int64_t c = 0; c < nct; ++c) cnt += mask[ro + a.coloff[col0 + c]] != 0;
+  }
+  a.counts[ct * (a.n_rg * kRowsPerWG) + row] = cnt;
+}
+
+hipError_t launch_count(const Layout& L, const uint8_t* mask, hipStream_t st) {
+  int64_t nwg = L.n_rg * L.n_ct;
+  hipLaunchKernelGGL(k_count, dim3((unsigned)nwg), dim3(kRowsPerWG), 0, st, largs(L), mask);
+  return hipGetLastError();
+}
+
+__global__ void k_slices(LayoutArgs a) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= a.n_slices) return;
+  const int64_t w = s / 4, wave = s % 4;
+  const int64_t ct = w / a.n_rg, g = w % a.n_rg;
+  const int32_t* c = a.counts + ct * (a.n_rg * kRowsPerWG) + g * kRowsPerWG + wave * kWave;
+  int mx = 0;
+  long long sum = 0;
+  for (int l = 0; l < kWave; ++l) {
+    mx = max(mx, c[l]);
+    sum += c[l];
+  }
+  a.slice_len[s] = mx;
+  if (sum) atomicAdd((unsigned long long*)a.nobs, (unsigned long long)sum);
+}
+
+hipError_t launch_slices(const Layout& L, hipStream_t st) {
+  hipLaunchKernelGGL(k_slices, dim3(grid_for(L.n_slices, 256, 1 << 30)), dim3(256), 0, st,
+                     largs(L));
+  return hipGetLastError();
+}
+
+// Exclusive scan of slice sizes (len * 64) by one work-group, in fixed order.
+__global__ __launch_bounds__(1024) void k_scan(LayoutArgs a) {
+  __shared__ int64_t buf[1024];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < a.n_slices; base += 1024) {
+    int64_t i = base + threadIdx.x;
+    int64_t v = i < a.n_slices ? (int64_t)a.slice_len[i] * kWave : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      int64_t add = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < a.n_slices) a.slice_off[i] = carry + buf[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.slice_off[a.n_slices] = carry;
+    *a.total = carry;
+  }
+}
+
+hipError_t launch_scan(const Layout& L, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, largs(L));
+  return hipGetLastError();
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_fill(LayoutArgs a, const uint8_t* __restrict__ mask,
+                                              const real* __restrict__ X, real* __restrict__ vals,
+                                              uint16_t* __restrict__ cols) {
+  const int64_t w = blockIdx.x;
+  const int64_t ct = w / a.n_rg, g = w % a.n_rg;
+  const int64_t row = g * kRowsPerWG + threadIdx.x;
+  const int64_t col0 = ct * a.ct_w;
+  const int64_t nct = min((int64_t)a.ct_w, a.ncols - col0);
+  const int64_t sid = w * 4 + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int64_t base = a.slice_off[sid] + lane;
+  const int len = a.slice_len[sid];
+  int t = 0;
+  if (row < a.nrows) {
+    const int64_t ro = a.rowoff[row];
+    for (int64_t c = 0; c < nct; ++c) {
+      const int64_t off = ro + a.coloff[col0 + c];
+      if (mask[off]) {
+        vals[base + (int64_t)t * kWave] = X[off];
+        cols[base + (int64_t)t * kWave] = (uint16_t)c;
+        ++t;
+      }
+    }
+  }
+  for (; t < len; ++t) {
+    vals[base + (int64_t)t * kWave] = real(0);
+    cols[base + (int64_t)t * kWave] = kPad;
+  }
+}
+
+hipError_t launch_fill(const Layout& L, const uint8_t* mask, const void* X, int dtype,
+                       hipStream_t st) {
+  int64_t nwg = L.n_rg * L.n_ct;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)nwg), dim3(kRowsPerWG), 0, st, largs(L),
+                       mask, (const float*)X, (float*)L.vals, L.cols);
+  else
+    hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)nwg), dim3(kRowsPerWG), 0, st, largs(L),
+                       mask, (const double*)X, (double*)L.vals, L.cols);
+  return hipGetLastError();
+}
+
+// max |x| over the observed entries of a layout (non-negative doubles compare like
+// their bit patterns, so an integer atomic max is exact and order independent)
+template <typename real>
+__global__ void k_max_abs(const real* vals, const uint16_t* cols, const int64_t* total,
+                          double* out) {
+  const int64_t n = *total;
+  unsigned long long best = 0ull;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (cols[i] != kPad) {
+      double v = fabs((double)vals[i]);
+      unsigned long long b = (unsigned long long)__double_as_longlong(v);
+      best = b > best ? b : best;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long other = __shfl_xor(best, o);
+    best = other > best ? other : best;
+  }
+  if ((threadIdx.x & 63) == 0 && best) atomicMax((unsigned long long*)out, best);
+}
+
+hipError_t launch_max_abs_observed(const Layout& L, int dtype, double* out, hipStream_t st) {
+  hipError_t e = launch_zero(out, sizeof(double), st);
+  if (e != hipSuccess) return e;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_max_abs<float>, dim3(1024), dim3(256), 0, st, (const float*)L.vals,
+                       L.cols, L.total_dev, out);
+  else
+    hipLaunchKernelGGL(k_max_abs<double>, dim3(1024), dim3(256), 0, st, (const double*)L.vals,
+                       L.cols, L.total_dev, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- RStS sampling
+// SplitMix64 in counter form, Lemire bounded draws, Floyd subsets (integer only).
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t counter_u64(uint64_t key, uint64_t c) {
+  return mix64(key + (c + 1ull) * 0x9E3779B97F4A7C15ull);
+}
+__device__ uint64_t bounded(uint64_t key, uint64_t* ctr, uint64_t n) {
+  const uint64_t threshold = ((1ull << 32) - n) % n;
+  for (;;) {
+    uint64_t x = counter_u64(key, (*ctr)++) >> 32;
+    uint64_t m = x * n;
+    if ((m & 0xFFFFFFFFull) >= threshold) return m >> 32;
+  }
+}
+
+struct SampleArgs {
+  uint64_t seed;
+  int t, k, N;
+  int64_t dims[kMaxN];
+  int32_t sizes[kMaxN];
+  int32_t* out[kMaxN];
+};
+
+__global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
+  const int j = blockIdx.x;
+  const int64_t n = a.dims[j];
+  int32_t* o = a.out[j];
+  if (j == a.k || (int64_t)a.sizes[j] >= n) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) o[i] = (int32_t)i;
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  const int64_t s = a.sizes[j];
+  uint64_t key = counter_u64(a.seed ^ 0x5253545300000000ull, (uint64_t)a.t);
+  key = counter_u64(key, (uint64_t)a.k);
+  key = counter_u64(key, (uint64_t)j);
+  uint64_t ctr = 0;
+  int64_t m = 0;  // current size of the sorted set in o[0..m)
+  for (int64_t jj = n - s; jj < n; ++jj) {
+    int64_t tv = (int64_t)bounded(key, &ctr, (uint64_t)(jj + 1));
+    // membership by binary search
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (o[mid] < tv) lo = mid + 1; else hi = mid;
+    }
+    int64_t v = (lo < m && o[lo] == tv) ? jj : tv;
+    // jj exceeds every element so far, so it goes to the end
+    int64_t pos = (v == jj) ? m : lo;
+    for (int64_t q = m; q > pos; --q) o[q] = o[q - 1];
+    o[pos] = (int32_t)v;
+    ++m;
+  }
+}
+
+hipError_t launch_sample(uint64_t seed, int t, int k, int N, const int64_t* dims,
+                         const int32_t* sizes, int32_t* const* out, hipStream_t st) {
+  SampleArgs a;
+  a.seed = seed; a.t = t; a.k = k; a.N = N;
+  for (int j = 0; j < kMaxN; ++j) {
+    a.dims[j] = j < N ? dims[j] : 1;
+    a.sizes[j] = j < N ? sizes[j] : 1;
+    a.out[j] = j < N ? out[j] : nullptr;
+  }
+  hipLaunchKernelGGL(k_sample, dim3(N), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace trd

@@ -1,0 +1,1085 @@
+// Host side of libtrd: context, workspace, per-core plans and the orchestration of
+// one core update (Alg. 1 body) and of the sweep loop.  Every compute step runs in a
+// kernel on the caller's stream; the host only plans sizes and launches.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/trd.h"
+#include "trd_internal.h"
+
+namespace trd {
+int64_t g_lds_max = 65536;
+}
+
+using namespace trd;
+
+namespace {
+
+thread_local std::string g_free_err;
+
+struct SketchWS {
+  // index lists per mode (device), capacity per mode
+  int32_t* idx[kMaxN] = {nullptr};
+  int64_t idx_cap[kMaxN] = {0};
+  Layout L;                 // layout storage at capacity
+  int64_t cap_rows = 0, cap_cols = 0, cap_slices = 0, cap_counts = 0, cap_slots = 0;
+  bool ready = false;
+};
+
+}  // namespace
+
+struct trd_ctx {
+  int device = 0;
+  std::string err;
+  std::vector<void*> allocs;
+  size_t ws_bytes = 0;
+
+  bool has_problem = false;
+  int N = 0;
+  int64_t dims[kMaxN] = {0};
+  int32_t ranks[kMaxN] = {0};
+  int64_t strides[kMaxN] = {0};
+  int dtype = 0;
+  const void* X = nullptr;
+  const uint8_t* mask = nullptr;
+  int64_t nobs = 0;
+  double maxabs = 0.0;            // max |x| over the observed entries
+  std::vector<Split> splits;      // full-path split per core
+  std::vector<Layout> layouts;    // full-path layout per core
+
+  // tables and work buffers (sized for the largest core and sketch)
+  void* T = nullptr; void* TH = nullptr; void* V = nullptr; void* S = nullptr;
+  void* U = nullptr; void* chainA = nullptr; void* chainB = nullptr;
+  int64_t cap_T = 0, cap_V = 0, cap_U = 0, cap_chain = 0;
+  double* K[kMaxN] = {nullptr};
+  double* P0 = nullptr; double* P1 = nullptr; double* G = nullptr; double* Cinv = nullptr;
+  double* d64 = nullptr; double* h64 = nullptr; void* h_real = nullptr;
+  int64_t cap_d = 0;
+  double* part_pass = nullptr; int64_t cap_part_pass = 0;
+  double* part_misc = nullptr; int64_t cap_part_misc = 0;
+  double* scal = nullptr;         // device scalars, see kS* below
+  uint32_t* flags = nullptr;      // [0] step flags, [1] fit flags
+  float* resid = nullptr; int64_t cap_resid = 0;
+  uint32_t* qhist = nullptr; uint32_t* qstate = nullptr;
+  double* Dbuf[2] = {nullptr, nullptr}; double* M = nullptr;
+  double* eta_hist = nullptr;     // [N] per sweep
+  SketchWS sk;
+
+  // profiling of the fused gradient pass
+  bool prof = false;
+  std::vector<hipEvent_t> ev_free, ev_pairs;
+  int64_t prof_slots = 0, prof_entries = 0;
+};
+
+namespace {
+
+enum {
+  kSigma = 0, kNum = 1, kDen = 2, kEta = 3, kStats = 4 /* 3 */, kMaxAbs = 7, kSigmaMin = 8,
+  kConv = 9 /* 2 */, kLoss = 11, kTmp = 12 /* 4 */, kScalCount = 16
+};
+
+int fail(trd_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_free_err = msg;
+  return code;
+}
+
+#define CK(expr)                                                                          \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return fail(ctx, TRD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));  \
+  } while (0)
+
+#define TRY(expr)                   \
+  do {                              \
+    int _r = (expr);                \
+    if (_r != TRD_OK) return _r;    \
+  } while (0)
+
+int dev_alloc(trd_ctx* ctx, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    hipGetLastError();
+    return fail(ctx, TRD_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+  }
+  ctx->allocs.push_back(*p);
+  ctx->ws_bytes += bytes;
+  return TRD_OK;
+}
+
+template <typename P>
+int alloc_n(trd_ctx* ctx, P** p, int64_t n) {
+  return dev_alloc(ctx, (void**)p, (size_t)std::max<int64_t>(n, 1) * sizeof(P));
+}
+
+void free_all(trd_ctx* ctx) {
+  for (void* p : ctx->allocs) hipFree(p);
+  ctx->allocs.clear();
+  ctx->ws_bytes = 0;
+}
+
+size_t esz(int dtype) { return dtype == 0 ? 4 : 8; }
+
+// ---------------------------------------------------------------- planning
+
+// counts[j]: indices of mode j taking part (I_j on the full path, s_j in a sketch).
+int plan_split(trd_ctx* ctx, int k, const int64_t* counts, Split& sp, int64_t& nrows,
+               int64_t& ncols, int& ct_w, int& n_ct) {
+  const int N = ctx->N;
+  double best = -1;
+  int bestp = -1;
+  for (int p = 0; p <= N - 2; ++p) {
+    const int s = (k + p + 1) % N;
+    const int RR = ctx->ranks[k] * ctx->ranks[s];
+    const int RRP = pass_rrp(RR);
+    if (RRP < 0) continue;
+    int64_t nr = counts[k], nc = 1;
+    for (int t = 1; t <= p; ++t) nr *= counts[(k + t) % N];
+    for (int t = p + 1; t <= N - 1; ++t) nc *= counts[(k + t) % N];
+    const int64_t wmax = pass_ct_w(ctx->dtype, 0, RRP);
+    const int64_t nct = (nc + wmax - 1) / wmax;
+    // bytes of the two tables plus the gradient accumulator traffic of the tiles
+    const double cost = (double)(nr + nc) * RRP * esz(ctx->dtype) + (double)nct * nr * RR * 4.0;
+    if (bestp < 0 || cost < best) {
+      best = cost;
+      bestp = p;
+    }
+  }
+  if (bestp < 0)
+    return fail(ctx, TRD_EUNSUPPORTED, "no subchain split with r_k * r_s <= 128 for core " +
+                                           std::to_string(k));
+  sp.k = k;
+  sp.p = bestp;
+  sp.q = N - 1 - bestp;
+  for (int t = 1; t <= sp.p; ++t) sp.B[t - 1] = (k + t) % N;
+  for (int t = sp.p + 1; t <= N - 1; ++t) sp.C[t - sp.p - 1] = (k + t) % N;
+  sp.r_k = ctx->ranks[k];
+  sp.r_k1 = ctx->ranks[(k + 1) % N];
+  sp.r_s = ctx->ranks[(k + sp.p + 1) % N];
+  sp.RR = sp.r_k * sp.r_s;
+  sp.RRP = pass_rrp(sp.RR);
+  nrows = counts[k];
+  for (int t = 0; t < sp.p; ++t) nrows *= counts[sp.B[t]];
+  ncols = 1;
+  for (int t = 0; t < sp.q; ++t) ncols *= counts[sp.C[t]];
+  const int64_t wmax = pass_ct_w(ctx->dtype, 0, sp.RRP);
+  n_ct = (int)((ncols + wmax - 1) / wmax);
+  ct_w = (int)((ncols + n_ct - 1) / n_ct);
+  return TRD_OK;
+}
+
+void layout_dims(Layout& L, int64_t nrows, int64_t ncols, int ct_w, int n_ct) {
+  L.nrows = nrows;
+  L.ncols = ncols;
+  L.ct_w = ct_w;
+  L.n_ct = n_ct;
+  L.n_rg = (nrows + kRowsPerWG - 1) / kRowsPerWG;
+  L.n_slices = L.n_rg * n_ct * 4;
+}
+
+ModeSet rows_set(trd_ctx* ctx, const Split& sp, const int64_t* counts, const int32_t* const* lists) {
+  ModeSet ms;
+  ms.n = 1 + sp.p;
+  for (int t = 0; t < ms.n; ++t) {
+    const int m = t == 0 ? sp.k : sp.B[t - 1];
+    ms.mode[t] = m;
+    ms.count[t] = counts[m];
+    ms.stride[t] = ctx->strides[m];
+    ms.list[t] = (lists && m != sp.k) ? lists[m] : nullptr;
+  }
+  return ms;
+}
+
+ModeSet cols_set(trd_ctx* ctx, const Split& sp, const int64_t* counts, const int32_t* const* lists) {
+  ModeSet ms;
+  ms.n = sp.q;
+  for (int t = 0; t < ms.n; ++t) {
+    const int m = sp.C[t];
+    ms.mode[t] = m;
+    ms.count[t] = counts[m];
+    ms.stride[t] = ctx->strides[m];
+    ms.list[t] = lists ? lists[m] : nullptr;
+  }
+  return ms;
+}
+
+// count -> slices -> scan (-> fill when vals/cols are in place)
+int build_layout_head(trd_ctx* ctx, const Split& sp, const int64_t* counts,
+                      const int32_t* const* lists, Layout& L, hipStream_t st) {
+  CK(launch_offsets(rows_set(ctx, sp, counts, lists), L.nrows, L.rowoff, st));
+  CK(launch_offsets(cols_set(ctx, sp, counts, lists), L.ncols, L.coloff, st));
+  CK(launch_zero(L.nobs_dev, sizeof(int64_t), st));
+  CK(launch_count(L, ctx->mask, st));
+  CK(launch_slices(L, st));
+  CK(launch_scan(L, st));
+  return TRD_OK;
+}
+
+int alloc_layout_index(trd_ctx* ctx, Layout& L) {
+  TRY(alloc_n(ctx, &L.rowoff, L.nrows));
+  TRY(alloc_n(ctx, &L.coloff, L.ncols));
+  TRY(alloc_n(ctx, &L.counts, (int64_t)L.n_ct * L.n_rg * kRowsPerWG));
+  TRY(alloc_n(ctx, &L.slice_len, L.n_slices));
+  TRY(alloc_n(ctx, &L.slice_off, L.n_slices + 1));
+  TRY(alloc_n(ctx, &L.total_dev, 1));
+  TRY(alloc_n(ctx, &L.nobs_dev, 1));
+  return TRD_OK;
+}
+
+// table sizes a split needs
+void table_needs(trd_ctx* ctx, const Split& sp, const int64_t* counts, int64_t nrows, int64_t ncols,
+                 int64_t& needT, int64_t& needV, int64_t& needU, int64_t& needChain) {
+  int64_t nB = 1;
+  for (int t = 0; t < sp.p; ++t) nB *= counts[sp.B[t]];
+  needT = nrows * sp.RRP;
+  needV = ncols * sp.RRP;
+  needU = sp.p >= 2 ? nB * sp.r_k1 * sp.r_s : 0;
+  needChain = std::max<int64_t>(nB, ncols) * kMaxRank * kMaxRank;
+  (void)ctx;
+}
+
+int ensure_tables(trd_ctx* ctx, int64_t needT, int64_t needV, int64_t needU, int64_t needChain) {
+  const size_t e = esz(ctx->dtype);
+  if (needT > ctx->cap_T) {
+    TRY(dev_alloc(ctx, &ctx->T, needT * e));
+    TRY(dev_alloc(ctx, &ctx->TH, needT * e));
+    TRY(dev_alloc(ctx, &ctx->S, needT * e));
+    ctx->cap_T = needT;
+  }
+  if (needV > ctx->cap_V) {
+    TRY(dev_alloc(ctx, &ctx->V, needV * e));
+    ctx->cap_V = needV;
+  }
+  if (needU > ctx->cap_U) {
+    TRY(dev_alloc(ctx, &ctx->U, needU * e));
+    ctx->cap_U = needU;
+  }
+  if (needChain > ctx->cap_chain) {
+    TRY(dev_alloc(ctx, &ctx->chainA, needChain * e));
+    TRY(dev_alloc(ctx, &ctx->chainB, needChain * e));
+    ctx->cap_chain = needChain;
+  }
+  return TRD_OK;
+}
+
+int ensure_part(trd_ctx* ctx, int64_t need_pass, int64_t need_misc) {
+  if (need_pass > ctx->cap_part_pass) {
+    TRY(alloc_n(ctx, &ctx->part_pass, need_pass));
+    ctx->cap_part_pass = need_pass;
+  }
+  if (need_misc > ctx->cap_part_misc) {
+    TRY(alloc_n(ctx, &ctx->part_misc, need_misc));
+    ctx->cap_part_misc = need_misc;
+  }
+  return TRD_OK;
+}
+
+int contract_chunks(int64_t Ik, int64_t nB) {
+  int64_t by_work = (nB + 15) / 16;
+  int64_t by_grid = std::max<int64_t>(1, 2048 / std::max<int64_t>(Ik, 1));
+  return (int)std::max<int64_t>(1, std::min(by_work, by_grid));
+}
+
+// ---------------------------------------------------------------- per-update state
+
+struct Update {
+  Split sp;
+  Layout* L = nullptr;
+  const int64_t* counts = nullptr;        // per-mode counts of this update
+  const int32_t* const* lists = nullptr;  // per-mode device lists (nullptr = full)
+  int64_t cnt[kMaxN];
+  const int32_t* lst[kMaxN];
+};
+
+// sample the sketch of update (t, k) and build its layout into the sketch workspace
+int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
+  const int N = ctx->N;
+  SketchWS& W = ctx->sk;
+  for (int j = 0; j < N; ++j) {
+    int64_t s = j == k ? ctx->dims[j] : std::min<int64_t>(std::max(1, sk->sizes[j]), ctx->dims[j]);
+    up.cnt[j] = s;
+  }
+  // index lists: caller's or sampled
+  for (int j = 0; j < N; ++j) {
+    if (W.idx_cap[j] < ctx->dims[j]) {
+      TRY(alloc_n(ctx, &W.idx[j], ctx->dims[j]));
+      W.idx_cap[j] = ctx->dims[j];
+    }
+  }
+  if (sk->idx) {
+    // copy the caller's lists into the workspace, clamped into range (never read out of bounds)
+    for (int j = 0; j < N; ++j)
+      if (j != k) CK(launch_copy_clamp(sk->idx[j], up.cnt[j], ctx->dims[j], W.idx[j], ctx->flags + 2, st));
+    for (int j = 0; j < N; ++j) up.lst[j] = j == k ? nullptr : W.idx[j];
+  } else {
+    int32_t sizes[kMaxN];
+    for (int j = 0; j < N; ++j) sizes[j] = (int32_t)up.cnt[j];
+    CK(launch_sample(sk->seed, sk->sweep, k, N, ctx->dims, sizes, W.idx, st));
+    for (int j = 0; j < N; ++j) up.lst[j] = j == k ? nullptr : W.idx[j];
+  }
+  int64_t nrows, ncols;
+  int ct_w, n_ct;
+  TRY(plan_split(ctx, k, up.cnt, up.sp, nrows, ncols, ct_w, n_ct));
+  Layout& L = W.L;
+  layout_dims(L, nrows, ncols, ct_w, n_ct);
+  const int64_t need_counts = (int64_t)n_ct * L.n_rg * kRowsPerWG;
+  const int64_t need_slots = need_counts * (int64_t)ct_w;  // dense bound
+  if (nrows > W.cap_rows) { TRY(alloc_n(ctx, &L.rowoff, nrows)); W.cap_rows = nrows; }
+  if (ncols > W.cap_cols) { TRY(alloc_n(ctx, &L.coloff, ncols)); W.cap_cols = ncols; }
+  if (need_counts > W.cap_counts) { TRY(alloc_n(ctx, &L.counts, need_counts)); W.cap_counts = need_counts; }
+  if (L.n_slices > W.cap_slices) {
+    TRY(alloc_n(ctx, &L.slice_len, L.n_slices));
+    TRY(alloc_n(ctx, &L.slice_off, L.n_slices + 1));
+    W.cap_slices = L.n_slices;
+  }
+  if (need_slots > W.cap_slots) {
+    TRY(dev_alloc(ctx, &L.vals, need_slots * esz(ctx->dtype)));
+    TRY(alloc_n(ctx, &L.cols, need_slots));
+    W.cap_slots = need_slots;
+  }
+  if (!L.total_dev) {
+    TRY(alloc_n(ctx, &L.total_dev, 1));
+    TRY(alloc_n(ctx, &L.nobs_dev, 1));
+  }
+  L.slots_cap = W.cap_slots;
+  L.slots = need_slots;  // upper bound; the device holds the exact value
+  L.k = k;
+  up.counts = up.cnt;
+  up.lists = up.lst;
+  up.L = &L;
+  TRY(build_layout_head(ctx, up.sp, up.cnt, up.lst, L, st));
+  CK(launch_fill(L, ctx->mask, ctx->X, ctx->dtype, st));
+  return TRD_OK;
+}
+
+int prepare_update(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
+  if (sk) return prepare_sketch(ctx, k, sk, up, st);
+  up.sp = ctx->splits[k];
+  up.L = &ctx->layouts[k];
+  for (int j = 0; j < ctx->N; ++j) {
+    up.cnt[j] = ctx->dims[j];
+    up.lst[j] = nullptr;
+  }
+  up.counts = up.cnt;
+  up.lists = nullptr;
+  return TRD_OK;
+}
+
+// ---------------------------------------------------------------- tables
+
+ItemRef core_ref(trd_ctx* ctx, const void* core, int m, const int32_t* const* lists) {
+  ItemRef r;
+  r.ptr = core;
+  r.stride = (int64_t)ctx->ranks[m] * ctx->ranks[(m + 1) % ctx->N];
+  r.list = lists ? lists[m] : nullptr;
+  return r;
+}
+
+// U(m_B) = product of the B cores (p >= 2 only; p == 1 uses the core directly)
+int build_U(trd_ctx* ctx, const Update& up, const void* const* cores, ItemRef& Uref, int64_t& nB,
+            hipStream_t st) {
+  const Split& sp = up.sp;
+  const int N = ctx->N;
+  nB = 1;
+  for (int t = 0; t < sp.p; ++t) nB *= up.counts[sp.B[t]];
+  if (sp.p == 0) {
+    Uref = ItemRef();
+    return TRD_OK;
+  }
+  if (sp.p == 1) {
+    Uref = core_ref(ctx, cores[sp.B[0]], sp.B[0], up.lists);
+    return TRD_OK;
+  }
+  ItemRef L = core_ref(ctx, cores[sp.B[0]], sp.B[0], up.lists);
+  int64_t nL = up.counts[sp.B[0]];
+  const int r0 = ctx->ranks[sp.B[0]];
+  int rB = ctx->ranks[(sp.B[0] + 1) % N];
+  void* bufs[2] = {ctx->chainA, ctx->chainB};
+  for (int t = 1; t < sp.p; ++t) {
+    const int m = sp.B[t];
+    const int rC = ctx->ranks[(m + 1) % N];
+    void* out = (t == sp.p - 1) ? ctx->U : bufs[t & 1];
+    CK(launch_merge(ctx->dtype, L, nL, r0, rB, core_ref(ctx, cores[m], m, up.lists), up.counts[m],
+                    rC, out, (int64_t)r0 * rC, 0, st));
+    L.ptr = out;
+    L.stride = (int64_t)r0 * rC;
+    L.list = nullptr;
+    nL *= up.counts[m];
+    rB = rC;
+  }
+  Uref = L;
+  return TRD_OK;
+}
+
+// T-like table: left(i_k) @ U(m_B), padded to RRP.  left in core layout (I_k items).
+int build_rowtable(trd_ctx* ctx, const Update& up, const void* left, const ItemRef& Uref,
+                   int64_t nB, void* out, hipStream_t st) {
+  const Split& sp = up.sp;
+  ItemRef L;
+  L.ptr = left;
+  L.stride = (int64_t)sp.r_k * sp.r_k1;
+  const int64_t Ik = up.counts[sp.k];
+  if (sp.p == 0) {
+    CK(launch_pack(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, out, sp.RRP, 0, st));
+  } else {
+    CK(launch_merge(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, Uref, nB, sp.r_s, out, sp.RRP, 0, st));
+  }
+  return TRD_OK;
+}
+
+// V^T(m_C): product of the C cores, stored transposed (a + r_k*c) and padded to RRP
+int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hipStream_t st) {
+  const Split& sp = up.sp;
+  const int N = ctx->N;
+  const int m0 = sp.C[0];
+  ItemRef L = core_ref(ctx, cores[m0], m0, up.lists);
+  int64_t nL = up.counts[m0];
+  const int r0 = ctx->ranks[m0];  // == r_s
+  int rB = ctx->ranks[(m0 + 1) % N];
+  if (sp.q == 1) {
+    CK(launch_pack(ctx->dtype, L, nL, r0, rB, ctx->V, sp.RRP, 1, st));
+    return TRD_OK;
+  }
+  void* bufs[2] = {ctx->chainA, ctx->chainB};
+  for (int t = 1; t < sp.q; ++t) {
+    const int m = sp.C[t];
+    const int rC = ctx->ranks[(m + 1) % N];
+    const bool last = t == sp.q - 1;
+    void* out = last ? ctx->V : bufs[t & 1];
+    CK(launch_merge(ctx->dtype, L, nL, r0, rB, core_ref(ctx, cores[m], m, up.lists), up.counts[m],
+                    rC, out, last ? sp.RRP : (int64_t)r0 * rC, last ? 1 : 0, st));
+    L.ptr = out;
+    L.stride = (int64_t)r0 * rC;
+    L.list = nullptr;
+    nL *= up.counts[m];
+    rB = rC;
+  }
+  return TRD_OK;
+}
+
+PassArgs pass_args(trd_ctx* ctx, const Update& up) {
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  const Layout& L = *up.L;
+  a.T = ctx->T;
+  a.TH = ctx->TH;
+  a.V = ctx->V;
+  a.S = ctx->S;
+  a.vals = L.vals;
+  a.cols = L.cols;
+  a.slice_off = L.slice_off;
+  a.slice_len = L.slice_len;
+  a.resid = ctx->resid;
+  a.partials = ctx->part_pass;
+  a.sigma = ctx->scal + kSigma;
+  a.nrows = L.nrows;
+  a.ncols = L.ncols;
+  a.n_rg = L.n_rg;
+  a.ct_w = L.ct_w;
+  a.RR = up.sp.RR;
+  a.RRP = up.sp.RRP;
+  a.n_ct = L.n_ct;
+  return a;
+}
+
+int64_t n_wg(const Layout& L) { return L.n_rg * L.n_ct; }
+
+int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
+  PassArgs a = pass_args(ctx, up);
+  const bool timed = ctx->prof && mode == kModeGrad;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    CK(hipEventRecord(e0, st));
+  }
+  CK(launch_pass(ctx->dtype, 0, mode, a, st));
+  if (timed) {
+    CK(hipEventRecord(e1, st));
+    ctx->ev_pairs.push_back(e0);
+    ctx->ev_pairs.push_back(e1);
+    ctx->prof_slots += up.L->slots;
+    ctx->prof_entries += up.L->nobs;
+  }
+  return TRD_OK;
+}
+
+// gradient of eq. (9)/(15) for the prepared update: tables, pass, contraction -> d64
+int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_out, double scale,
+            double* stats_dev, hipStream_t st, ItemRef* Uout, int64_t* nBout) {
+  const Split& sp = up.sp;
+  const Layout& L = *up.L;
+  int64_t needT, needV, needU, needC;
+  table_needs(ctx, sp, up.counts, L.nrows, L.ncols, needT, needV, needU, needC);
+  TRY(ensure_tables(ctx, needT, needV, needU, needC));
+  const int64_t Ik = up.counts[sp.k];
+  int64_t nB = 1;
+  for (int t = 0; t < sp.p; ++t) nB *= up.counts[sp.B[t]];
+  const int nchunk = contract_chunks(Ik, nB);
+  TRY(ensure_part(ctx, n_wg(L) * 3, std::max<int64_t>((int64_t)nchunk * Ik * sp.r_k * sp.r_k1, 8)));
+  const int64_t nd = Ik * sp.r_k * sp.r_k1;
+  if (nd > ctx->cap_d) {
+    TRY(alloc_n(ctx, &ctx->d64, nd));
+    TRY(alloc_n(ctx, &ctx->h64, nd));
+    TRY(dev_alloc(ctx, &ctx->h_real, nd * esz(ctx->dtype)));
+    ctx->cap_d = nd;
+  }
+  ItemRef Uref;
+  TRY(build_U(ctx, up, cores, Uref, nB, st));
+  TRY(build_rowtable(ctx, up, cores[sp.k], Uref, nB, ctx->T, st));
+  TRY(build_coltable(ctx, up, cores, st));
+  CK(launch_zero(ctx->S, (size_t)L.nrows * sp.RRP * esz(ctx->dtype), st));
+  TRY(run_pass(ctx, up, kModeGrad, st));
+  CK(launch_reduce_partials(ctx->part_pass, n_wg(L), 3, stats_dev ? stats_dev : ctx->scal + kStats,
+                            st));
+  CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, Ik, nB, sp.r_k, sp.r_s, sp.r_k1, Uref,
+                     ctx->part_misc, nchunk, st));
+  CK(launch_contract_finish(ctx->dtype, ctx->part_misc, nchunk, Ik, sp.r_k * sp.r_k1, ctx->d64,
+                            d_out, scale, st));
+  if (Uout) *Uout = Uref;
+  if (nBout) *nBout = nB;
+  return TRD_OK;
+}
+
+int ensure_dense(trd_ctx* ctx) {
+  if (ctx->G) return TRD_OK;
+  int64_t maxR2 = 1, maxr2 = 1;
+  for (int j = 0; j < ctx->N; ++j) {
+    const int64_t R = (int64_t)ctx->ranks[j] * ctx->ranks[(j + 1) % ctx->N];
+    maxR2 = std::max(maxR2, R * R);
+    maxr2 = std::max<int64_t>(maxr2, (int64_t)ctx->ranks[j] * ctx->ranks[j]);
+  }
+  // K_j is r_j^2 x r_{j+1}^2; ring partial products are r_{k+1}^2 x r_m^2
+  for (int j = 0; j < ctx->N; ++j) TRY(alloc_n(ctx, &ctx->K[j], maxR2));
+  TRY(alloc_n(ctx, &ctx->P0, maxr2 * maxr2));
+  TRY(alloc_n(ctx, &ctx->P1, maxr2 * maxr2));
+  TRY(alloc_n(ctx, &ctx->G, maxR2));
+  TRY(alloc_n(ctx, &ctx->Cinv, maxR2));
+  return TRD_OK;
+}
+
+int refresh_K(trd_ctx* ctx, const void* const* cores, int j, hipStream_t st) {
+  CK(launch_kron_factor(ctx->dtype, cores[j], ctx->ranks[j], ctx->dims[j], ctx->ranks[(j + 1) % ctx->N],
+                        ctx->K[j], st));
+  return TRD_OK;
+}
+
+// G^{!=k} from the cached factors (eq. 13): ring product in cyclic order, realigned
+int ring_gram(trd_ctx* ctx, int k, double* G_out, hipStream_t st) {
+  const int N = ctx->N;
+  const int s1 = (k + 1) % N;
+  const double* cur = ctx->K[s1];
+  int rows = ctx->ranks[s1] * ctx->ranks[s1];
+  int inner = ctx->ranks[(s1 + 1) % N] * ctx->ranks[(s1 + 1) % N];
+  double* bufs[2] = {ctx->P0, ctx->P1};
+  int which = 0;
+  for (int t = 2; t <= N - 1; ++t) {
+    const int m = (k + t) % N;
+    const int cols = ctx->ranks[(m + 1) % N] * ctx->ranks[(m + 1) % N];
+    CK(launch_gemm64(cur, ctx->K[m], bufs[which], rows, inner, cols, st));
+    cur = bufs[which];
+    which ^= 1;
+    inner = cols;
+  }
+  CK(launch_realign(cur, G_out, ctx->ranks[k], ctx->ranks[s1], st));
+  return TRD_OK;
+}
+
+int set_sigma(trd_ctx* ctx, double sigma, hipStream_t st) {
+  CK(launch_set_scalar(ctx->scal + kSigma, sigma, st));
+  return TRD_OK;
+}
+
+// one full core update (eqs. 9-12 / 15-18); K factors of the other cores must be current
+int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const trd_sketch* sk,
+            double* eta_user, uint32_t* flags_user, hipStream_t st) {
+  Update up;
+  TRY(prepare_update(ctx, k, sk, up, st));
+  const Split& sp = up.sp;
+  const int64_t Ik = ctx->dims[k];
+  const int R = sp.r_k * sp.r_k1;
+  CK(launch_zero(ctx->flags, sizeof(uint32_t), st));
+  ItemRef Uref;
+  int64_t nB;
+  TRY(do_grad(ctx, up, (const void* const*)cores, nullptr, 1.0, nullptr, st, &Uref, &nB));
+  TRY(ring_gram(ctx, k, ctx->G, st));
+  CK(launch_inverse(ctx->G, ctx->Cinv, R, lambda_rel, ctx->flags, st));
+  const int64_t nbl = (Ik * R + 255) / 256;
+  TRY(ensure_part(ctx, 0, nbl));
+  CK(launch_apply_inverse(ctx->d64, ctx->Cinv, Ik, R, ctx->h64, ctx->h_real, ctx->dtype,
+                          ctx->part_misc, ctx->flags, st));
+  CK(launch_reduce_partials(ctx->part_misc, nbl, 1, ctx->scal + kNum, st));
+  TRY(build_rowtable(ctx, up, ctx->h_real, Uref, nB, ctx->TH, st));
+  TRY(run_pass(ctx, up, kModeLS, st));
+  CK(launch_reduce_partials(ctx->part_pass, n_wg(*up.L), 3, ctx->scal + kTmp, st));
+  CK(launch_eta(ctx->scal + kNum, ctx->scal + kTmp, up.L->nobs_dev, ctx->scal + kEta, ctx->flags,
+                flags_user, eta_user, st));
+  CK(launch_update(ctx->dtype, cores[k], ctx->h64, ctx->scal + kEta, Ik * R, st));
+  return TRD_OK;
+}
+
+int check_ctx(trd_ctx* ctx) {
+  if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
+  if (!ctx->has_problem) return fail(ctx, TRD_ESTATE, "call trd_set_problem first");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail(ctx, TRD_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  return TRD_OK;
+}
+
+int check_cores(trd_ctx* ctx, const void* const* cores) {
+  if (!cores) return fail(ctx, TRD_EINVAL, "cores is NULL");
+  for (int j = 0; j < ctx->N; ++j)
+    if (!cores[j]) return fail(ctx, TRD_EINVAL, "cores[" + std::to_string(j) + "] is NULL");
+  return TRD_OK;
+}
+
+int check_sigma(trd_ctx* ctx, double sigma) {
+  if (!(sigma > 0.0)) return fail(ctx, TRD_EINVAL, "sigma must be > 0 (or +inf)");
+  return TRD_OK;
+}
+
+int check_sketch(trd_ctx* ctx, const trd_sketch* sk, int k) {
+  if (!sk) return TRD_OK;
+  for (int j = 0; j < ctx->N; ++j) {
+    if (j == k) continue;
+    if (sk->sizes[j] < 1) return fail(ctx, TRD_EINVAL, "sketch sizes must be >= 1");
+    if (sk->idx && !sk->idx[j]) return fail(ctx, TRD_EINVAL, "sketch idx[j] is NULL");
+  }
+  return TRD_OK;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+
+extern "C" {
+
+int trd_create(trd_ctx** out, int device) {
+  if (!out) return fail(nullptr, TRD_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0)
+    return fail(nullptr, TRD_EDEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+  if (device < 0 || device >= n) return fail(nullptr, TRD_EINVAL, "device index out of range");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return fail(nullptr, TRD_EDEVICE, hipGetErrorString(e));
+  g_lds_max = (int64_t)prop.sharedMemPerBlock;
+  trd_ctx* c = new (std::nothrow) trd_ctx();
+  if (!c) return fail(nullptr, TRD_ENOMEM, "host allocation failed");
+  c->device = device;
+  *out = c;
+  return TRD_OK;
+}
+
+void trd_destroy(trd_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (hipEvent_t ev : ctx->ev_pairs) hipEventDestroy(ev);
+  free_all(ctx);
+  delete ctx;
+}
+
+const char* trd_last_error(const trd_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_free_err.c_str();
+}
+
+int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ranks, int dtype,
+                    const void* X, const uint8_t* mask, void* stream) {
+  if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
+  if (N < 2 || N > kMaxN) return fail(ctx, TRD_EUNSUPPORTED, "N must be in [2, 8]");
+  if (!dims || !ranks || !X || !mask) return fail(ctx, TRD_EINVAL, "NULL argument");
+  if (dtype != TRD_F32 && dtype != TRD_F64) return fail(ctx, TRD_EINVAL, "dtype must be TRD_F32 or TRD_F64");
+  double total = 1.0;
+  for (int j = 0; j < N; ++j) {
+    if (dims[j] < 1) return fail(ctx, TRD_EINVAL, "dims must be >= 1");
+    if (ranks[j] < 1) return fail(ctx, TRD_EINVAL, "ranks must be >= 1");
+    if (ranks[j] > kMaxRank) return fail(ctx, TRD_EUNSUPPORTED, "ranks must be <= 16");
+    total *= (double)dims[j];
+  }
+  if (total >= 4.6e18) return fail(ctx, TRD_EUNSUPPORTED, "prod(dims) must be < 2^62");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return fail(ctx, TRD_EDEVICE, hipGetErrorString(he));
+  hipStream_t st = (hipStream_t)stream;
+  // drop any previous problem
+  CK(hipStreamSynchronize(st));
+  free_all(ctx);
+  const int device = ctx->device;
+  for (hipEvent_t ev : ctx->ev_pairs) hipEventDestroy(ev);
+  *ctx = trd_ctx();
+  ctx->device = device;
+
+  ctx->N = N;
+  ctx->dtype = dtype;
+  ctx->X = X;
+  ctx->mask = mask;
+  int64_t s = 1;
+  for (int j = 0; j < N; ++j) {
+    ctx->dims[j] = dims[j];
+    ctx->ranks[j] = ranks[j];
+    ctx->strides[j] = s;
+    s *= dims[j];
+  }
+  TRY(alloc_n(ctx, &ctx->scal, kScalCount));
+  TRY(alloc_n(ctx, &ctx->flags, 4));
+  TRY(alloc_n(ctx, &ctx->qhist, 2048));
+  TRY(alloc_n(ctx, &ctx->qstate, 4));
+  TRY(alloc_n(ctx, &ctx->eta_hist, N));
+  CK(launch_zero(ctx->flags, 4 * sizeof(uint32_t), st));
+  TRY(ensure_dense(ctx));
+
+  ctx->splits.resize(N);
+  ctx->layouts.resize(N);
+  int64_t needT = 0, needV = 0, needU = 0, needC = 0, needPass = 0, needMisc = 8, needD = 0;
+  for (int k = 0; k < N; ++k) {
+    int64_t nrows, ncols;
+    int ct_w, n_ct;
+    TRY(plan_split(ctx, k, ctx->dims, ctx->splits[k], nrows, ncols, ct_w, n_ct));
+    Layout& L = ctx->layouts[k];
+    L.k = k;
+    layout_dims(L, nrows, ncols, ct_w, n_ct);
+    TRY(alloc_layout_index(ctx, L));
+    TRY(build_layout_head(ctx, ctx->splits[k], ctx->dims, nullptr, L, st));
+    CK(hipMemcpyAsync(&L.slots, L.total_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (L.slots > 0) {
+      TRY(dev_alloc(ctx, &L.vals, (size_t)L.slots * esz(dtype)));
+      TRY(alloc_n(ctx, &L.cols, L.slots));
+    }
+    L.slots_cap = L.slots;
+    CK(launch_fill(L, mask, X, dtype, st));
+    int64_t a, b, c2, d;
+    table_needs(ctx, ctx->splits[k], ctx->dims, nrows, ncols, a, b, c2, d);
+    needT = std::max(needT, a);
+    needV = std::max(needV, b);
+    needU = std::max(needU, c2);
+    needC = std::max(needC, d);
+    needPass = std::max(needPass, n_wg(L) * 3);
+    const Split& sp = ctx->splits[k];
+    int64_t nB = 1;
+    for (int t = 0; t < sp.p; ++t) nB *= ctx->dims[sp.B[t]];
+    const int64_t R = (int64_t)sp.r_k * sp.r_k1;
+    needMisc = std::max(needMisc, (int64_t)contract_chunks(dims[k], nB) * dims[k] * R);
+    needMisc = std::max(needMisc, (dims[k] * R + 255) / 256);
+    needD = std::max(needD, dims[k] * R);
+  }
+  // sweep-end convergence buffers (Alg. 1)
+  {
+    const int64_t IN = dims[N - 1];
+    const int64_t R = (int64_t)ranks[N - 1] * ranks[0];
+    TRY(alloc_n(ctx, &ctx->Dbuf[0], IN * IN));
+    TRY(alloc_n(ctx, &ctx->Dbuf[1], IN * IN));
+    TRY(alloc_n(ctx, &ctx->M, IN * R));
+    needMisc = std::max(needMisc, 2 * ((IN * IN + 255) / 256));
+  }
+  TRY(ensure_tables(ctx, needT, needV, needU, needC));
+  TRY(ensure_part(ctx, needPass, needMisc));
+  TRY(alloc_n(ctx, &ctx->d64, needD));
+  TRY(alloc_n(ctx, &ctx->h64, needD));
+  TRY(dev_alloc(ctx, &ctx->h_real, needD * esz(dtype)));
+  ctx->cap_d = needD;
+  // residual buffer for the kernel-width quantile (layout of core 0)
+  ctx->cap_resid = std::max<int64_t>(ctx->layouts[0].slots, 1);
+  TRY(alloc_n(ctx, &ctx->resid, ctx->cap_resid));
+  CK(launch_max_abs_observed(ctx->layouts[0], dtype, ctx->scal + kMaxAbs, st));
+  CK(hipMemcpyAsync(&ctx->nobs, ctx->layouts[0].nobs_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(&ctx->maxabs, ctx->scal + kMaxAbs, sizeof(double), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  for (int k = 0; k < N; ++k) ctx->layouts[k].nobs = ctx->nobs;
+  ctx->has_problem = true;
+  return TRD_OK;
+}
+
+int trd_problem_info(const trd_ctx* ctx, int64_t* n_obs, size_t* workspace_bytes, int32_t* split) {
+  if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
+  if (!ctx->has_problem) return fail(const_cast<trd_ctx*>(ctx), TRD_ESTATE, "no problem bound");
+  if (n_obs) *n_obs = ctx->nobs;
+  if (workspace_bytes) *workspace_bytes = ctx->ws_bytes;
+  if (split)
+    for (int k = 0; k < ctx->N; ++k) split[k] = ctx->splits[k].p;
+  return TRD_OK;
+}
+
+int trd_reconstruct(trd_ctx* ctx, const void* const* cores, const int64_t* lin_idx, int64_t n,
+                    void* out, void* stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_cores(ctx, cores));
+  if (!out && n > 0) return fail(ctx, TRD_EINVAL, "out is NULL");
+  if (n < 0) return fail(ctx, TRD_EINVAL, "n < 0");
+  if (!lin_idx) {
+    int64_t tot = 1;
+    for (int j = 0; j < ctx->N; ++j) tot *= ctx->dims[j];
+    if (n != tot) return fail(ctx, TRD_EINVAL, "n must equal prod(dims) when lin_idx is NULL");
+  }
+  CK(launch_reconstruct(ctx->dtype, ctx->N, ctx->dims, ctx->ranks, cores, lin_idx, n, out,
+                        (hipStream_t)stream));
+  return TRD_OK;
+}
+
+int trd_weights(const void* resid, int64_t n, int dtype, double sigma, void* w_out, void* stream) {
+  trd_ctx* ctx = nullptr;
+  if (!(sigma > 0.0)) return fail(nullptr, TRD_EINVAL, "sigma must be > 0 (or +inf)");
+  if (dtype != TRD_F32 && dtype != TRD_F64) return fail(nullptr, TRD_EINVAL, "bad dtype");
+  if (n < 0) return fail(nullptr, TRD_EINVAL, "n < 0");
+  if (n > 0 && (!resid || !w_out)) return fail(nullptr, TRD_EINVAL, "NULL buffer");
+  CK(launch_weights(dtype, resid, n, sigma, w_out, (hipStream_t)stream));
+  return TRD_OK;
+}
+
+int trd_grad(trd_ctx* ctx, const void* const* cores, int k, double sigma, const trd_sketch* sketch,
+             void* d_out, double* stats_dev, void* stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_cores(ctx, cores));
+  if (k < 0 || k >= ctx->N) return fail(ctx, TRD_EINVAL, "k out of range");
+  TRY(check_sigma(ctx, sigma));
+  TRY(check_sketch(ctx, sketch, k));
+  if (!d_out) return fail(ctx, TRD_EINVAL, "d_out is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  TRY(set_sigma(ctx, sigma, st));
+  Update up;
+  TRY(prepare_update(ctx, k, sketch, up, st));
+  TRY(do_grad(ctx, up, cores, d_out, 1.0, stats_dev, st, nullptr, nullptr));
+  return TRD_OK;
+}
+
+int trd_fgmc_gram(trd_ctx* ctx, const void* const* cores, int k, double* G_out, void* stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_cores(ctx, cores));
+  if (k < 0 || k >= ctx->N) return fail(ctx, TRD_EINVAL, "k out of range");
+  if (!G_out) return fail(ctx, TRD_EINVAL, "G_out is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  for (int j = 0; j < ctx->N; ++j)
+    if (j != k) TRY(refresh_K(ctx, cores, j, st));
+  TRY(ring_gram(ctx, k, G_out, st));
+  return TRD_OK;
+}
+
+int trd_step(trd_ctx* ctx, void* const* cores, int k, double sigma, double lambda_rel,
+             const trd_sketch* sketch, double* eta_dev, uint32_t* flags_dev, void* stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_cores(ctx, (const void* const*)cores));
+  if (k < 0 || k >= ctx->N) return fail(ctx, TRD_EINVAL, "k out of range");
+  TRY(check_sigma(ctx, sigma));
+  if (!(lambda_rel >= 0.0)) return fail(ctx, TRD_EINVAL, "lambda_rel must be >= 0");
+  TRY(check_sketch(ctx, sketch, k));
+  hipStream_t st = (hipStream_t)stream;
+  TRY(set_sigma(ctx, sigma, st));
+  for (int j = 0; j < ctx->N; ++j)
+    if (j != k) TRY(refresh_K(ctx, (const void* const*)cores, j, st));
+  TRY(do_step(ctx, cores, k, lambda_rel, sketch, eta_dev, flags_dev, st));
+  return TRD_OK;
+}
+
+int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_report* rep,
+            void* stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_cores(ctx, (const void* const*)cores));
+  if (!o) return fail(ctx, TRD_EINVAL, "opts is NULL");
+  if (o->max_sweeps < 1) return fail(ctx, TRD_EINVAL, "max_sweeps must be >= 1");
+  if (!(o->lambda_rel >= 0.0)) return fail(ctx, TRD_EINVAL, "lambda_rel must be >= 0");
+  if (o->precision != TRD_PREC_NATIVE)
+    return fail(ctx, TRD_EUNSUPPORTED, "precision mode not available in this build");
+  if (o->sigma_mode == TRD_SIGMA_FIXED) TRY(check_sigma(ctx, o->sigma));
+  else if (o->sigma_mode == TRD_SIGMA_GIVEN) {
+    if (!o->sigma_given) return fail(ctx, TRD_EINVAL, "sigma_given is NULL");
+    for (int t = 0; t < o->max_sweeps; ++t) TRY(check_sigma(ctx, o->sigma_given[t]));
+  } else if (o->sigma_mode == TRD_SIGMA_QUANTILE) {
+    if (!(o->q >= 0.0 && o->q <= 1.0) || !(o->c > 0.0) || !(o->shrink >= 0.0) || !(o->sigma_min_rel >= 0.0))
+      return fail(ctx, TRD_EINVAL, "bad quantile parameters");
+  } else {
+    return fail(ctx, TRD_EINVAL, "unknown sigma_mode");
+  }
+  trd_sketch skb;
+  const trd_sketch* sk = nullptr;
+  if (o->use_sketch) {
+    memset(&skb, 0, sizeof(skb));
+    skb.seed = o->seed;
+    for (int j = 0; j < kMaxN; ++j) skb.sizes[j] = o->sketch_sizes[j];
+    TRY(check_sketch(ctx, &skb, -1));
+    sk = &skb;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int N = ctx->N;
+  for (int j = 0; j < N; ++j) TRY(refresh_K(ctx, (const void* const*)cores, j, st));
+  CK(launch_zero(ctx->flags + 1, sizeof(uint32_t), st));
+  if (o->sigma_mode == TRD_SIGMA_QUANTILE) {
+    CK(launch_set_scalar(ctx->scal + kSigma, INFINITY, st));
+    // sigma_min = sigma_min_rel * max |x| over the observed entries
+    CK(launch_set_scalar(ctx->scal + kSigmaMin, o->sigma_min_rel * ctx->maxabs, st));
+  }
+  if (rep) {
+    rep->sweeps = 0;
+    rep->last_e = INFINITY;
+    rep->last_sigma = 0;
+    rep->flags = 0;
+  }
+  int cur = 0;
+  struct HostRead { double sigma; double conv[2]; uint32_t flags; uint32_t pad; } hr;
+  std::vector<double> etas(N);
+  int status = TRD_OK;
+  for (int t = 0; t < o->max_sweeps; ++t) {
+    if (sk) skb.sweep = t;
+    // kernel width for this sweep
+    if (o->sigma_mode == TRD_SIGMA_FIXED) {
+      TRY(set_sigma(ctx, o->sigma, st));
+    } else if (o->sigma_mode == TRD_SIGMA_GIVEN) {
+      TRY(set_sigma(ctx, o->sigma_given[t], st));
+    } else {
+      Update up;
+      TRY(prepare_update(ctx, 0, sk, up, st));
+      const Layout& L = *up.L;
+      if (L.slots_cap > ctx->cap_resid) {
+        TRY(alloc_n(ctx, &ctx->resid, L.slots_cap));
+        ctx->cap_resid = L.slots_cap;
+      }
+      int64_t needT, needV, needU, needC;
+      table_needs(ctx, up.sp, up.counts, L.nrows, L.ncols, needT, needV, needU, needC);
+      TRY(ensure_tables(ctx, needT, needV, needU, needC));
+      TRY(ensure_part(ctx, n_wg(L) * 3, 8));
+      ItemRef Uref;
+      int64_t nB;
+      TRY(build_U(ctx, up, (const void* const*)cores, Uref, nB, st));
+      TRY(build_rowtable(ctx, up, cores[0], Uref, nB, ctx->T, st));
+      TRY(build_coltable(ctx, up, (const void* const*)cores, st));
+      TRY(run_pass(ctx, up, kModeResid, st));
+      CK(launch_quantile_sigma(ctx->resid, L.slots_cap, L.total_dev, o->q, o->c,
+                               ctx->scal + kSigmaMin, o->shrink, ctx->scal + kSigma, ctx->qhist,
+                               ctx->qstate, L.nobs_dev, st));
+    }
+    for (int k = 0; k < N; ++k) {
+      TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st));
+      TRY(refresh_K(ctx, (const void* const*)cores, k, st));
+    }
+    // convergence matrix with G^{!=N} of the last update (it does not involve core N)
+    {
+      const int64_t IN = ctx->dims[N - 1];
+      const int R = ctx->ranks[N - 1] * ctx->ranks[0];
+      CK(launch_convergence(ctx->dtype, cores[N - 1], ctx->G, IN, R, ctx->M, ctx->Dbuf[cur],
+                            ctx->Dbuf[cur ^ 1], t > 0 ? 1 : 0, ctx->part_misc, st));
+      CK(launch_reduce_partials(ctx->part_misc, (IN * IN + 255) / 256, 2, ctx->scal + kConv, st));
+    }
+    CK(hipMemcpyAsync(&hr.sigma, ctx->scal + kSigma, sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(hr.conv, ctx->scal + kConv, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&hr.flags, ctx->flags + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(etas.data(), ctx->eta_hist, N * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    cur ^= 1;
+    const double e = t > 0 ? sqrt(hr.conv[0]) / sqrt(hr.conv[1]) : INFINITY;
+    if (rep) {
+      rep->sweeps = t + 1;
+      rep->last_e = e;
+      rep->last_sigma = hr.sigma;
+      rep->flags |= hr.flags;
+      if (rep->e_hist) rep->e_hist[t] = e;
+      if (rep->sigma_hist) rep->sigma_hist[t] = hr.sigma;
+      if (rep->eta_hist)
+        for (int k = 0; k < N; ++k) rep->eta_hist[(int64_t)t * N + k] = etas[k];
+    }
+    if (hr.flags & TRD_FLAG_NOTSPD) {
+      status = fail(ctx, TRD_ENOTSPD, "G + lambda I not positive definite (eq. 10)");
+      break;
+    }
+    if (t > 0 && e < o->tol) break;
+  }
+  return status;
+}
+
+int trd_loss_fwd(trd_ctx* ctx, const void* const* cores, double sigma, double* loss_dev, void* stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_cores(ctx, cores));
+  TRY(check_sigma(ctx, sigma));
+  if (!loss_dev) return fail(ctx, TRD_EINVAL, "loss_dev is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  TRY(set_sigma(ctx, sigma, st));
+  Update up;
+  TRY(prepare_update(ctx, 0, nullptr, up, st));
+  const Layout& L = *up.L;
+  ItemRef Uref;
+  int64_t nB;
+  TRY(build_U(ctx, up, cores, Uref, nB, st));
+  TRY(build_rowtable(ctx, up, cores[0], Uref, nB, ctx->T, st));
+  TRY(build_coltable(ctx, up, cores, st));
+  TRY(run_pass(ctx, up, kModeLoss, st));
+  CK(launch_reduce_partials(ctx->part_pass, n_wg(L), 3, ctx->scal + kTmp, st));
+  CK(hipMemcpyAsync(loss_dev, ctx->scal + kTmp, sizeof(double), hipMemcpyDeviceToDevice, st));
+  return TRD_OK;
+}
+
+int trd_loss_bwd(trd_ctx* ctx, const void* const* cores, double sigma, double grad_scale,
+                 void* const* grads_out, void* stream) {
+  TRY(check_ctx(ctx));
+  TRY(check_cores(ctx, cores));
+  TRY(check_sigma(ctx, sigma));
+  if (!grads_out) return fail(ctx, TRD_EINVAL, "grads_out is NULL");
+  for (int j = 0; j < ctx->N; ++j)
+    if (!grads_out[j]) return fail(ctx, TRD_EINVAL, "grads_out[j] is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  TRY(set_sigma(ctx, sigma, st));
+  for (int k = 0; k < ctx->N; ++k) {
+    Update up;
+    TRY(prepare_update(ctx, k, nullptr, up, st));
+    TRY(do_grad(ctx, up, cores, grads_out[k], -grad_scale, nullptr, st, nullptr, nullptr));
+  }
+  return TRD_OK;
+}
+
+int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, const int32_t* sizes,
+                      int32_t* const* idx_out, void* stream) {
+  trd_ctx* ctx = nullptr;
+  if (N < 2 || N > kMaxN) return fail(nullptr, TRD_EINVAL, "N must be in [2, 8]");
+  if (!dims || !sizes || !idx_out) return fail(nullptr, TRD_EINVAL, "NULL argument");
+  if (k < 0 || k >= N) return fail(nullptr, TRD_EINVAL, "k out of range");
+  int32_t s[kMaxN];
+  for (int j = 0; j < N; ++j) {
+    if (dims[j] < 1 || dims[j] > 0x7FFFFFFF) return fail(nullptr, TRD_EINVAL, "bad dims");
+    if (j != k && sizes[j] < 1) return fail(nullptr, TRD_EINVAL, "sizes must be >= 1");
+    if (!idx_out[j]) return fail(nullptr, TRD_EINVAL, "idx_out[j] is NULL");
+    s[j] = (int32_t)std::min<int64_t>(j == k ? dims[j] : sizes[j], dims[j]);
+  }
+  CK(launch_sample(seed, t, k, N, dims, s, idx_out, (hipStream_t)stream));
+  return TRD_OK;
+}
+
+int trd_profile(trd_ctx* ctx, int enable) {
+  if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
+  ctx->prof = enable != 0;
+  return TRD_OK;
+}
+
+int trd_profile_read(trd_ctx* ctx, int64_t* launches, double* total_ms, int64_t* slots,
+                     int64_t* entries) {
+  if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
+  hipSetDevice(ctx->device);
+  double ms = 0.0;
+  const int64_t n = (int64_t)ctx->ev_pairs.size() / 2;
+  for (int64_t i = 0; i < n; ++i) {
+    hipEvent_t a = ctx->ev_pairs[2 * i], b = ctx->ev_pairs[2 * i + 1];
+    hipError_t e = hipEventSynchronize(b);
+    if (e != hipSuccess) return fail(ctx, TRD_EDEVICE, hipGetErrorString(e));
+    float f = 0.f;
+    e = hipEventElapsedTime(&f, a, b);
+    if (e != hipSuccess) return fail(ctx, TRD_EDEVICE, hipGetErrorString(e));
+    ms += f;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+  }
+  ctx->ev_pairs.clear();
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
+  if (slots) *slots = ctx->prof_slots;
+  if (entries) *entries = ctx->prof_entries;
+  ctx->prof_slots = 0;
+  ctx->prof_entries = 0;
+  return TRD_OK;
+}
+
+}  // extern "C"

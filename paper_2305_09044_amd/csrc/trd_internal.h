@@ -1,0 +1,156 @@
+// Internal declarations shared by the host orchestration and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace trd {
+
+constexpr int kMaxN = 8;
+constexpr int kMaxRank = 16;
+constexpr int kMaxRR = 128;        // r_k * r_s of the fused pass
+constexpr int kRowsPerWG = 256;    // rows of one work-group tile (4 waves x 64 lanes)
+constexpr int kWave = 64;
+constexpr uint16_t kPad = 0xFFFF;  // padding marker in the sliced-ELL column array
+constexpr int kPassThreads = 256;
+constexpr uint32_t TRD_FLAG_EMPTY_BIT = 1u;     // mirrors TRD_FLAG_EMPTY
+constexpr uint32_t TRD_FLAG_ZERO_DEN_BIT = 2u;  // mirrors TRD_FLAG_ZERO_DEN
+constexpr uint32_t TRD_FLAG_NOTSPD_BIT = 4u;    // mirrors TRD_FLAG_NOTSPD
+
+// largest dynamic LDS a work-group may request (set from the device at context creation)
+extern int64_t g_lds_max;
+
+// A table of small column-major matrices ("items"), item t at ptr + idx(t) * stride.
+struct ItemRef {
+  const void* ptr = nullptr;
+  int64_t stride = 0;              // elements between items
+  const int32_t* list = nullptr;   // optional device index list (item t -> list[t])
+};
+
+// Mode description for index decoding of rows / columns of a core-k matrix.
+struct ModeSet {
+  int n = 0;
+  int mode[kMaxN];
+  int64_t count[kMaxN];            // number of indices of this mode in the set
+  int64_t stride[kMaxN];           // stride of the mode in the column-major tensor
+  const int32_t* list[kMaxN];      // index list (nullptr = identity)
+};
+
+// The observed entries of one core update, grouped as a matrix (rows x cols) and
+// stored as 64-row sliced ELL inside 256-row x ct_w-column tiles.
+struct Layout {
+  int k = -1;
+  int64_t nrows = 0, ncols = 0;
+  int ct_w = 0, n_ct = 0;          // column tile width and count
+  int64_t n_rg = 0;                // 256-row groups
+  int64_t n_slices = 0;            // n_ct * n_rg * 4
+  int64_t slots = 0;               // host copy of the total slot count (full path)
+  int64_t slots_cap = 0;           // capacity of vals/cols
+  int64_t* rowoff = nullptr;       // [nrows] tensor offset of each row
+  int64_t* coloff = nullptr;       // [ncols] tensor offset of each column
+  int32_t* counts = nullptr;       // [n_ct][n_rg*256]
+  int32_t* slice_len = nullptr;    // [n_slices]
+  int64_t* slice_off = nullptr;    // [n_slices + 1]
+  void* vals = nullptr;            // [slots] problem dtype
+  uint16_t* cols = nullptr;        // [slots]
+  int64_t* total_dev = nullptr;    // device copy of slots
+  int64_t* nobs_dev = nullptr;     // device observed count in this layout
+  int64_t nobs = 0;                // host copy (full path)
+};
+
+// Split of the cyclic subchain for core k: rows = (k, B modes), cols = C modes.
+struct Split {
+  int k = 0, p = 0, q = 0;
+  int B[kMaxN], C[kMaxN];
+  int r_k = 0, r_k1 = 0, r_s = 0;  // r_s = rank between the B and C groups
+  int RR = 0, RRP = 0;             // r_k * r_s and its padded width
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return a hipError_t from the launch.
+
+// layout building
+hipError_t launch_offsets(const ModeSet& ms, int64_t n, int64_t* out, hipStream_t st);
+hipError_t launch_count(const Layout& L, const uint8_t* mask, hipStream_t st);
+hipError_t launch_slices(const Layout& L, hipStream_t st);
+hipError_t launch_scan(const Layout& L, hipStream_t st);
+hipError_t launch_fill(const Layout& L, const uint8_t* mask, const void* X, int dtype,
+                       hipStream_t st);
+hipError_t launch_sample(uint64_t seed, int t, int k, int N, const int64_t* dims,
+                         const int32_t* sizes, int32_t* const* out, hipStream_t st);
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
+hipError_t launch_copy_clamp(const int32_t* in, int64_t n, int64_t dim, int32_t* out,
+                             uint32_t* bad, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// tables (Def. 2 merges)
+hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRef R, int64_t nR,
+                        int rC, void* out, int64_t out_stride, int transpose_out, hipStream_t st);
+hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* out,
+                       int64_t out_stride, int transpose_out, hipStream_t st);
+hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t st);
+hipError_t launch_contract(int dtype, const void* S, int RRP, int64_t Ik, int64_t nB, int r_k,
+                           int r_s, int r_k1, ItemRef U, double* part, int nchunk, hipStream_t st);
+hipError_t launch_contract_finish(int dtype, const double* part, int nchunk, int64_t Ik, int RRk,
+                                  double* d64, void* d_out, double scale, hipStream_t st);
+
+// fused entry pass
+enum PassMode { kModeGrad = 0, kModeLS = 1, kModeResid = 2, kModeLoss = 3 };
+struct PassArgs {
+  const void* T;        // [nrows][RRP]
+  const void* TH;       // [nrows][RRP] (line search)
+  const void* V;        // [ncols][RRP]
+  void* S;              // [nrows][RRP] gradient accumulators (atomics)
+  const void* vals;
+  const uint16_t* cols;
+  const int64_t* slice_off;
+  const int32_t* slice_len;
+  float* resid;         // kModeResid output, one per slot
+  double* partials;     // [n_wg][3]
+  const double* sigma;  // device scalar
+  int64_t nrows, ncols, n_rg;
+  int ct_w, RR, RRP, n_ct;
+};
+hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st);
+bool pass_supported(int RRP);
+int pass_rrp(int RR);
+int64_t pass_ct_w(int dtype, int prec, int RRP);
+
+// dense FP64 pieces
+hipError_t launch_kron_factor(int dtype, const void* Z, int r0, int64_t I, int r1, double* K,
+                              hipStream_t st);
+hipError_t launch_gemm64(const double* A, const double* B, double* C, int m, int kk, int n,
+                         hipStream_t st);
+hipError_t launch_realign(const double* P, double* G, int r_k, int r_k1, hipStream_t st);
+hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
+                          uint32_t* flags, hipStream_t st);
+hipError_t launch_apply_inverse(const double* d64, const double* Cinv, int64_t Ik, int n,
+                                double* h64, void* h_real, int dtype, double* part_num,
+                                const uint32_t* flags, hipStream_t st);
+hipError_t launch_eta(const double* num, const double* den, const int64_t* nobs, double* eta,
+                      uint32_t* flags, uint32_t* flags_user, double* eta_user, hipStream_t st);
+hipError_t launch_update(int dtype, void* Z, const double* h64, const double* eta, int64_t n,
+                         hipStream_t st);
+hipError_t launch_reduce_partials(const double* part, int64_t n, int width, double* out,
+                                  hipStream_t st);
+hipError_t launch_set_scalar(double* p, double v, hipStream_t st);
+hipError_t launch_convergence(int dtype, const void* ZN, const double* G, int64_t IN, int n,
+                              double* M, double* D, const double* Dprev, int have_prev,
+                              double* part, hipStream_t st);
+hipError_t launch_weights(int dtype, const void* r, int64_t n, double sigma, void* w,
+                          hipStream_t st);
+hipError_t launch_reconstruct(int dtype, int N, const int64_t* dims, const int32_t* ranks,
+                              const void* const* cores, const int64_t* lin, int64_t n, void* out,
+                              hipStream_t st);
+hipError_t launch_max_abs_observed(const Layout& L, int dtype, double* out, hipStream_t st);
+
+// sigma quantile by radix select over float bit patterns
+hipError_t launch_quantile_sigma(const float* keys, int64_t n_slots_hint, const int64_t* nslots,
+                                 double q, double c, const double* sigma_min, double shrink,
+                                 double* sigma, uint32_t* hist, uint32_t* state,
+                                 const int64_t* nobs, hipStream_t st);
+
+}  // namespace trd
