@@ -1,0 +1,185 @@
+"""Benchmark: observed entries/s per AWRTRD core sweep on one MI355X.
+
+A step is one sweep of Alg. 1 over all cores (sampling, subchain tables, fused
+reconstruct+weight+gradient pass, FGMC Gram, scaled direction, line-search pass,
+update, kernel-width quantile and convergence matrix), with inputs resident in HBM.
+Default workload: 100^4 tensor of TR rank 5 (1e8 entries), 30% observed, N(0,1e-3)
+noise, 20% of the observed entries replaced by +-max|X| salt and pepper, FP32.
+
+Prints one JSON line.  The roofline object covers the dominant kernel (the fused
+gradient pass), timed with HIP events around each of its launches in the timed
+region; cpu_baseline is the FP64 numpy oracle on a bounded sample of the same recipe.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "observed entries/sec per AWRTRD core sweep, BF16 vs FP32, at equal rel. error"
+HBM_PEAK_GBS = 8000.0
+PASS_SRC = os.path.join(ROOT, "paper_2305_09044_amd", "csrc", "kernels_pass.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grad_pass_tr4_100_r5.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash() -> str:
+    return hashlib.sha256(open(PASS_SRC, "rb").read()).hexdigest()[:16]
+
+
+def build_inputs(wname: str, seed: int, dims=None):
+    """Seeded workload on the device: clean tensor from the library's own reconstruction,
+    noise, outliers and mask from synth."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2305_09044_amd as trd
+
+    w = synth.WORKLOADS[wname]
+    dims = tuple(dims or w.dims)
+    std = w.core_std if w.core_std is not None else 1.0 / math.sqrt(w.ranks[0])
+    cores_t = (synth.lowpass_cores(dims, w.ranks, seed, std) if w.lowpass
+               else synth.gaussian_cores(dims, w.ranks, seed, std))
+    shape = trd.Problem(None, None, dims, w.ranks, dtype=torch.float32)
+    ct = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(cores_t, np.float32)]
+    xs = shape.reconstruct(ct)
+    torch.cuda.synchronize()
+    xstar = xs.cpu().numpy().astype(np.float64).reshape(dims, order="F")
+    shape.close()
+    del xs, ct
+    if w.normalise_max:
+        xstar /= float(np.max(np.abs(xstar)))
+    mask = (synth.bernoulli_mask(dims, w.rho, seed) if w.mask_kind == "bernoulli"
+            else synth.block_mask(dims, 16, 1.0 - w.rho, seed))
+    X = synth.assemble(w, xstar, mask, seed)
+    del xstar
+    Xd = torch.from_numpy(X.astype(np.float32).ravel(order="F")).cuda()
+    Pd = torch.from_numpy(mask.ravel(order="F").copy()).cuda()
+    del X
+    return w, dims, Xd, Pd, mask
+
+
+def cpu_baseline(wname: str, seed: int, sample_dims):
+    """FP64 oracle, one sweep (quantile kernel width), on a bounded sample of the recipe."""
+    import numpy as np
+    import synth
+    from oracle import awrtrd as aw
+    from oracle import tr
+
+    w = synth.scaled(synth.WORKLOADS[wname], sample_dims)
+    Zt, xstar, mask, X = synth.make_workload(w, seed, tr.reconstruct)
+    Z0 = synth.init_cores(sample_dims, w.ranks, seed)
+    X32 = X.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    aw.fit(X32, mask, Z0, aw.FitOptions(max_sweeps=1, tol=0.0))
+    dt = time.perf_counter() - t0
+    nobs = int(mask.sum())
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": len(sample_dims) * nobs / dt, "unit": "observed entries/s", "cores": min(cores, threads),
+            "kind": "oracle",
+            "sample": f"one FP64 sweep of the same recipe on a {'x'.join(map(str, sample_dims))} tensor "
+                      f"({nobs} observed entries, {dt:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tr4_100_r5")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", default="100,100,100,20")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the path runs on a single MI355X); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2305_09044_amd as trd
+
+    t_setup = time.perf_counter()
+    w, dims, Xd, Pd, mask_np = build_inputs(args.workload, args.seed)
+    prob = trd.Problem(Xd, Pd, dims, w.ranks)
+    info = prob.info()
+    n_obs = info["n_obs"]
+    import numpy as np
+    import synth
+    Z0 = synth.init_cores(dims, w.ranks, args.seed)
+    cores = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(Z0, np.float32)]
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t_setup:.1f}s n_obs={n_obs} split={info['split']} "
+        f"workspace={info['workspace_bytes'] / 2**20:.0f} MiB")
+
+    if args.warmup > 0:
+        prob.fit(cores, max_sweeps=args.warmup, tol=0.0)
+    torch.cuda.synchronize()
+    prob.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    rep = prob.fit(cores, max_sweeps=args.steps, tol=0.0)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = prob.profile_read()
+    prob.profile(False)
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    elapsed = max(wall, gpu_s)
+    assert rep["sweeps"] == args.steps, rep
+    N = len(dims)
+    value = args.steps * N * n_obs / elapsed
+    log(f"timed {args.steps} sweeps: wall {wall * 1e3:.2f} ms, events {gpu_s * 1e3:.2f} ms, "
+        f"sigma {rep['sigma'][-1]:.4g}, e {rep['e'][-1]:.3g}")
+
+    # roofline of the fused gradient pass: algorithmic bytes = value (4 B) + in-tile
+    # column index (2 B) per observed entry of the update
+    avg_ms = prof["total_ms"] / max(prof["launches"], 1)
+    bytes_per_launch = prof["entries"] / max(prof["launches"], 1) * (4 + 2)
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("src_hash") == src_hash() and tf.get("workload") == args.workload:
+            traffic = tf.get("bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_pass<float,RRP,kModeGrad> (fused reconstruct+weight+gradient)",
+            "avg_launch_ms": round(avg_ms, 5), "launches": prof["launches"],
+            "bytes_per_launch": int(bytes_per_launch)}
+
+    out = {"metric": METRIC, "value": value, "unit": "observed entries/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "dims": list(dims), "tr_ranks": list(w.ranks),
+                      "observed_fraction": w.rho, "n_obs": n_obs, "path": "AWRTRD full sweep, FGMC, "
+                      "quantile kernel width", "precision": "fp32"},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        sample = tuple(int(v) for v in args.cpu_sample.split(","))
+        del prob, Xd, Pd
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

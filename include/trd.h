@@ -113,6 +113,13 @@ void trd_destroy(trd_ctx* ctx);
 const char* trd_last_error(const trd_ctx* ctx);
 
 /*
+ * Bind only the shape (N, dims, TR ranks, dtype) without data: enough for
+ * trd_reconstruct and trd_fgmc_gram.  Drops any previously bound problem and its
+ * workspace.  Synchronizes the device.
+ */
+int trd_set_shape(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ranks, int dtype);
+
+/*
  * Bind a problem (Alg. 1 inputs X, mask P of eq. 2, TR ranks) and build the
  * observed-entry layouts, one per core: for core k the entries are grouped as a
  * matrix whose rows are (i_k, the first modes of the cyclic subchain) and whose
@@ -132,7 +139,7 @@ int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ran
 int trd_problem_info(const trd_ctx* ctx, int64_t* n_obs, size_t* workspace_bytes, int32_t* split);
 
 /*
- * TR reconstruction (Def. 1): out[t] = Tr(Z_0(i_0) ... Z_{N-1}(i_{N-1})) for the
+ * TR reconstruction (Def. 1) (needs trd_set_shape or trd_set_problem): out[t] = Tr(Z_0(i_0) ... Z_{N-1}(i_{N-1})) for the
  * entry at column-major linear index lin_idx[t] (device int64, n entries), or for
  * every entry in column-major order when lin_idx is NULL (then n must equal
  * prod(dims)).  out: device, problem dtype.

@@ -74,6 +74,7 @@ def load() -> C.CDLL:
         "trd_create": (i32, [P(vp), i32]),
         "trd_destroy": (None, [vp]),
         "trd_last_error": (C.c_char_p, [vp]),
+        "trd_set_shape": (i32, [vp, i32, P(i64), P(C.c_int32), i32]),
         "trd_set_problem": (i32, [vp, i32, P(i64), P(C.c_int32), i32, vp, vp, vp]),
         "trd_problem_info": (i32, [vp, P(i64), P(C.c_size_t), P(C.c_int32)]),
         "trd_reconstruct": (i32, [vp, P(vp), vp, i64, vp, vp]),
@@ -174,24 +175,33 @@ def trd_sample_sketch(seed: int, t: int, k: int, dims: Sequence[int], sizes: Seq
 class Problem:
     """One bound problem (trd_create + trd_set_problem).  Keeps X and mask alive."""
 
-    def __init__(self, X: torch.Tensor, mask: torch.Tensor, dims: Sequence[int],
-                 ranks: Sequence[int], device: Optional[int] = None):
+    def __init__(self, X: Optional[torch.Tensor], mask: Optional[torch.Tensor], dims: Sequence[int],
+                 ranks: Sequence[int], device: Optional[int] = None, dtype: torch.dtype = torch.float32):
+        """X/mask None binds only the shape (reconstruction and Gram only)."""
         lib = load()
+        self.dims = [int(v) for v in dims]
+        self.ranks = [int(v) for v in ranks]
+        self.N = len(dims)
+        d = (C.c_int64 * self.N)(*self.dims)
+        r = (C.c_int32 * self.N)(*self.ranks)
+        self._ctx = C.c_void_p()
+        if X is None:
+            self.dtype = dtype
+            self.X = self.mask = None
+            self.device = torch.device("cuda", device or 0)
+            _check(lib.trd_create(C.byref(self._ctx), int(device or 0)))
+            _check(lib.trd_set_shape(self._ctx, self.N, d, r, _dtype_code(dtype)), self._ctx)
+            return
         if X.numel() != math.prod(dims) or mask.numel() != X.numel():
             raise ValueError("X / mask size does not match dims")
         if mask.dtype != torch.uint8:
             raise ValueError("mask must be uint8")
-        self.dims = [int(v) for v in dims]
-        self.ranks = [int(v) for v in ranks]
-        self.N = len(dims)
         self.dtype = X.dtype
         self.X = X.contiguous()
         self.mask = mask.contiguous()
+        self.device = X.device
         dev = X.device.index if device is None else device
-        self._ctx = C.c_void_p()
         _check(lib.trd_create(C.byref(self._ctx), int(dev or 0)))
-        d = (C.c_int64 * self.N)(*self.dims)
-        r = (C.c_int32 * self.N)(*self.ranks)
         _check(lib.trd_set_problem(self._ctx, self.N, d, r, _dtype_code(X.dtype), _ptr(self.X),
                                    _ptr(self.mask), C.c_void_p(_stream())), self._ctx)
 
@@ -220,14 +230,14 @@ class Problem:
     # -- the calls of include/trd.h
     def reconstruct(self, cores, lin_idx: Optional[torch.Tensor] = None) -> torch.Tensor:
         n = lin_idx.numel() if lin_idx is not None else math.prod(self.dims)
-        out = torch.empty(n, dtype=self.dtype, device=self.X.device)
+        out = torch.empty(n, dtype=self.dtype, device=self.device)
         _check(load().trd_reconstruct(self._ctx, _ptr_array(cores), _ptr(lin_idx), n, _ptr(out),
                                       C.c_void_p(_stream())), self._ctx)
         return out
 
     def grad(self, cores, k: int, sigma: float, sketch=None):
-        d = torch.empty(self.core_numel(k), dtype=self.dtype, device=self.X.device)
-        stats = torch.zeros(3, dtype=torch.float64, device=self.X.device)
+        d = torch.empty(self.core_numel(k), dtype=self.dtype, device=self.device)
+        stats = torch.zeros(3, dtype=torch.float64, device=self.device)
         sk = C.byref(sketch) if sketch is not None else None
         _check(load().trd_grad(self._ctx, _ptr_array(cores), int(k), float(sigma), sk, _ptr(d),
                                _ptr(stats), C.c_void_p(_stream())), self._ctx)
@@ -235,14 +245,14 @@ class Problem:
 
     def fgmc_gram(self, cores, k: int) -> torch.Tensor:
         R = self.ranks[k] * self.ranks[(k + 1) % self.N]
-        G = torch.empty(R * R, dtype=torch.float64, device=self.X.device)
+        G = torch.empty(R * R, dtype=torch.float64, device=self.device)
         _check(load().trd_fgmc_gram(self._ctx, _ptr_array(cores), int(k), _ptr(G),
                                     C.c_void_p(_stream())), self._ctx)
         return G.view(R, R)
 
     def step(self, cores, k: int, sigma: float, lambda_rel: float = 1e-9, sketch=None):
-        eta = torch.zeros(1, dtype=torch.float64, device=self.X.device)
-        flags = torch.zeros(1, dtype=torch.int32, device=self.X.device)
+        eta = torch.zeros(1, dtype=torch.float64, device=self.device)
+        flags = torch.zeros(1, dtype=torch.int32, device=self.device)
         sk = C.byref(sketch) if sketch is not None else None
         _check(load().trd_step(self._ctx, _ptr_array(cores), int(k), float(sigma), float(lambda_rel),
                                sk, _ptr(eta), _ptr(flags), C.c_void_p(_stream())), self._ctx)
@@ -287,7 +297,7 @@ class Problem:
         return out
 
     def loss_fwd(self, cores, sigma: float) -> torch.Tensor:
-        out = torch.zeros(1, dtype=torch.float64, device=self.X.device)
+        out = torch.zeros(1, dtype=torch.float64, device=self.device)
         _check(load().trd_loss_fwd(self._ctx, _ptr_array(cores), float(sigma), _ptr(out),
                                    C.c_void_p(_stream())), self._ctx)
         return out

@@ -18,53 +18,63 @@ static int grid_for(int64_t n, int threads, int64_t cap = 1 << 20) {
 // ---------------------------------------------------------------- FGMC
 
 // K[(al*r0 + al2), (be*r1 + be2)] = sum_i Z(i)[al, be] * Z(i)[al2, be2]
+// one wave per output element; lanes stride over i, then a fixed-order wave reduction
 template <typename real>
-__global__ void k_kron(const real* __restrict__ Z, int r0, int64_t I, int r1, double* __restrict__ K) {
+__global__ __launch_bounds__(256) void k_kron(const real* __restrict__ Z, int r0, int64_t I, int r1,
+                                              double* __restrict__ K) {
   const int64_t n = (int64_t)r0 * r0 * r1 * r1;
   const int cols = r1 * r1;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int rr = (int)(t / cols), cc = (int)(t % cols);
-    const int al = rr / r0, al2 = rr % r0, be = cc / r1, be2 = cc % r1;
-    const int64_t sl = (int64_t)r0 * r1;
-    double s = 0.0;
-    for (int64_t i = 0; i < I; ++i) {
-      const real* zi = Z + i * sl;
-      s = fma((double)zi[al + r0 * be], (double)zi[al2 + r0 * be2], s);
-    }
-    K[t] = s;
+  const int lane = threadIdx.x & 63;
+  const int64_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= n) return;
+  const int rr = (int)(t / cols), cc = (int)(t % cols);
+  const int al = rr / r0, al2 = rr % r0, be = cc / r1, be2 = cc % r1;
+  const int64_t sl = (int64_t)r0 * r1;
+  double s = 0.0;
+  for (int64_t i = lane; i < I; i += 64) {
+    const real* zi = Z + i * sl;
+    s = fma((double)zi[al + r0 * be], (double)zi[al2 + r0 * be2], s);
   }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) K[t] = s;
 }
 
 hipError_t launch_kron_factor(int dtype, const void* Z, int r0, int64_t I, int r1, double* K,
                               hipStream_t st) {
   const int64_t n = (int64_t)r0 * r0 * r1 * r1;
+  const unsigned nb = (unsigned)((n + 3) / 4);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_kron<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, (const float*)Z,
-                       r0, I, r1, K);
+    hipLaunchKernelGGL(k_kron<float>, dim3(nb), dim3(256), 0, st, (const float*)Z, r0, I, r1, K);
   else
-    hipLaunchKernelGGL(k_kron<double>, dim3(grid_for(n, 256)), dim3(256), 0, st,
-                       (const double*)Z, r0, I, r1, K);
+    hipLaunchKernelGGL(k_kron<double>, dim3(nb), dim3(256), 0, st, (const double*)Z, r0, I, r1, K);
   return hipGetLastError();
 }
 
-// C = A (m x kk) @ B (kk x n), row-major FP64
+// C = A (m x kk) @ B (kk x n), row-major FP64.  With r_k > 0 the product is the last
+// factor of the FGMC ring (m = r_k1^2, n = r_k^2) and is stored realigned as G:
+// element (b r_k1 + b2, a r_k + a2) goes to G[(a + b r_k), (a2 + b2 r_k)].
 __global__ void k_gemm64(const double* __restrict__ A, const double* __restrict__ B,
-                         double* __restrict__ C, int m, int kk, int n) {
+                         double* __restrict__ C, int m, int kk, int n, int r_k, int r_k1) {
   const int64_t total = (int64_t)m * n;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(t / n), j = (int)(t % n);
     double s = 0.0;
     for (int l = 0; l < kk; ++l) s = fma(A[(int64_t)i * kk + l], B[(int64_t)l * n + j], s);
-    C[t] = s;
+    if (r_k > 0) {
+      const int b = i / r_k1, b2 = i % r_k1, a = j / r_k, a2 = j % r_k;
+      const int R = r_k * r_k1;
+      C[(int64_t)(a + b * r_k) * R + (a2 + b2 * r_k)] = s;
+    } else {
+      C[t] = s;
+    }
   }
 }
 
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int m, int kk, int n,
-                         hipStream_t st) {
+                         hipStream_t st, int r_k, int r_k1) {
   hipLaunchKernelGGL(k_gemm64, dim3(grid_for((int64_t)m * n, 256)), dim3(256), 0, st, A, B, C, m,
-                     kk, n);
+                     kk, n, r_k, r_k1);
   return hipGetLastError();
 }
 
@@ -102,11 +112,13 @@ __global__ __launch_bounds__(1024) void k_inverse(const double* __restrict__ G,
   __shared__ int s_bad;
   double* A = kLDS ? lds : Cinv;
   const int nn = n * n;
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) A[t] = G[t];
+  __syncthreads();
   if (threadIdx.x == 0) {
     double tr = 0.0, mx = 0.0;
     for (int i = 0; i < n; ++i) {
-      tr += G[(int64_t)i * n + i];
-      mx = fmax(mx, G[(int64_t)i * n + i]);
+      tr += A[i * n + i];
+      mx = fmax(mx, A[i * n + i]);
     }
     const double lam = lambda_rel * tr / n;
     s_lam = lam;
@@ -114,11 +126,9 @@ __global__ __launch_bounds__(1024) void k_inverse(const double* __restrict__ G,
     s_bad = 0;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-    const int i = t / n, j = t % n;
-    A[t] = G[t] + (i == j ? s_lam : 0.0);
-  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) A[i * n + i] += s_lam;
   __syncthreads();
+  const int my_t = threadIdx.x, my_i = my_t / n, my_j = my_t % n;
   for (int k = 0; k < n; ++k) {
     const double piv = A[k * n + k];
     if (!(piv > s_thr) || !isfinite(piv)) {
@@ -130,9 +140,13 @@ __global__ __launch_bounds__(1024) void k_inverse(const double* __restrict__ G,
     const double inv = 1.0 / piv;
     for (int j = threadIdx.x; j < n; j += blockDim.x) A[k * n + j] = (j == k ? 1.0 : A[k * n + j]) * inv;
     __syncthreads();
-    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-      const int i = t / n, j = t % n;
-      if (i != k) A[t] = (j == k ? 0.0 : A[t]) - f[i] * A[k * n + j];
+    if (nn <= (int)blockDim.x) {
+      if (my_t < nn && my_i != k) A[my_t] = (my_j == k ? 0.0 : A[my_t]) - f[my_i] * A[k * n + my_j];
+    } else {
+      for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+        const int i = t / n, j = t % n;
+        if (i != k) A[t] = (j == k ? 0.0 : A[t]) - f[i] * A[k * n + j];
+      }
     }
     __syncthreads();
   }
@@ -144,8 +158,11 @@ __global__ __launch_bounds__(1024) void k_inverse(const double* __restrict__ G,
 
 hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
                           uint32_t* flags, hipStream_t st) {
+  // small systems run in one or a few waves: fewer barrier participants per step
+  int threads = ((n * n + 63) / 64) * 64;
+  if (threads > 1024) threads = 1024;
   if ((int64_t)n * n * (int64_t)sizeof(double) + 4096 <= g_lds_max) {
-    hipLaunchKernelGGL(k_inverse<true>, dim3(1), dim3(1024), (size_t)n * n * sizeof(double), st,
+    hipLaunchKernelGGL(k_inverse<true>, dim3(1), dim3(threads), (size_t)n * n * sizeof(double), st,
                        G, Cinv, n, lambda_rel, flags);
   } else {
     hipLaunchKernelGGL(k_inverse<false>, dim3(1), dim3(1024), 0, st, G, Cinv, n, lambda_rel,
@@ -253,6 +270,64 @@ hipError_t launch_eta(const double* num, const double* den, const int64_t* nobs,
   return hipGetLastError();
 }
 
+// One work-group: num = sum of <d,h> partials, den = sum of the line-search pass
+// partials (column 0 of [n_den][3]), eta of eq. (12) with its flags, then the update
+// Z_k <- Z_k + eta h (eq. 11, '+' reading).  Fixed-order reductions.
+template <typename real>
+__global__ __launch_bounds__(1024) void k_finish_step(const double* __restrict__ pnum, int64_t n_num,
+                                                      const double* __restrict__ pden, int64_t n_den,
+                                                      const int64_t* nobs, uint32_t* flags,
+                                                      uint32_t* flags_user, double* eta_out,
+                                                      double* eta_user, real* __restrict__ Z,
+                                                      const double* __restrict__ h, int64_t nz) {
+  __shared__ double bn[1024], bd[1024];
+  __shared__ double s_eta;
+  double a = 0.0, b = 0.0;
+  for (int64_t r = threadIdx.x; r < n_num; r += 1024) a += pnum[r];
+  for (int64_t r = threadIdx.x; r < n_den; r += 1024) b += pden[r * 3];
+  bn[threadIdx.x] = a;
+  bd[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      bn[threadIdx.x] += bn[threadIdx.x + o];
+      bd[threadIdx.x] += bd[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double num = bn[0], den = bd[0];
+    uint32_t f = *flags;
+    double e = 0.0;
+    if (*nobs == 0) f |= TRD_FLAG_EMPTY_BIT;
+    if (!(den > 0.0) || !isfinite(den) || !isfinite(num)) f |= TRD_FLAG_ZERO_DEN_BIT;
+    else e = num / den;
+    if (f & TRD_FLAG_NOTSPD_BIT) e = 0.0;
+    *eta_out = e;
+    *flags = f;
+    if (eta_user) *eta_user = e;
+    if (flags_user) *flags_user |= f;
+    s_eta = e;
+  }
+  __syncthreads();
+  const double e = s_eta;
+  if (e != 0.0)
+    for (int64_t t = threadIdx.x; t < nz; t += 1024) Z[t] = (real)fma(e, h[t], (double)Z[t]);
+}
+
+hipError_t launch_finish_step(int dtype, const double* pnum, int64_t n_num, const double* pden,
+                              int64_t n_den, const int64_t* nobs, uint32_t* flags,
+                              uint32_t* flags_user, double* eta, double* eta_user, void* Z,
+                              const double* h, int64_t nz, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_finish_step<float>, dim3(1), dim3(1024), 0, st, pnum, n_num, pden, n_den,
+                       nobs, flags, flags_user, eta, eta_user, (float*)Z, h, nz);
+  else
+    hipLaunchKernelGGL(k_finish_step<double>, dim3(1), dim3(1024), 0, st, pnum, n_num, pden, n_den,
+                       nobs, flags, flags_user, eta, eta_user, (double*)Z, h, nz);
+  return hipGetLastError();
+}
+
 // Z_k <- Z_k + eta * h (eq. 11 with the '+' reading)
 template <typename real>
 __global__ void k_update(real* __restrict__ Z, const double* __restrict__ h, const double* eta,
@@ -272,6 +347,24 @@ hipError_t launch_update(int dtype, void* Z, const double* h64, const double* et
   else
     hipLaunchKernelGGL(k_update<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, (double*)Z,
                        h64, eta, n);
+  return hipGetLastError();
+}
+
+// Gather the per-sweep host-visible values into mapped pinned host memory:
+// out = {sigma, conv[0], conv[1], (double)flags, eta[0..N)}
+__global__ void k_pack_report(const double* sigma, const double* conv, const uint32_t* flags,
+                              const double* eta, int N, double* out) {
+  out[0] = *sigma;
+  out[1] = conv[0];
+  out[2] = conv[1];
+  out[3] = (double)*flags;
+  for (int k = 0; k < N; ++k) out[4 + k] = eta[k];
+  __threadfence_system();
+}
+
+hipError_t launch_pack_report(const double* sigma, const double* conv, const uint32_t* flags,
+                              const double* eta, int N, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_report, dim3(1), dim3(1), 0, st, sigma, conv, flags, eta, N, out);
   return hipGetLastError();
 }
 
@@ -496,21 +589,38 @@ __global__ void k_qinit(const int64_t* nobs, double q, uint32_t* state, uint32_t
   for (int i = 0; i < 2048; ++i) hist[i] = 0u;
 }
 
-__global__ void k_qpick(int bits, uint32_t* state, uint32_t* hist) {
+__global__ __launch_bounds__(1024) void k_qpick(int bits, uint32_t* state, uint32_t* hist) {
+  __shared__ unsigned long long sc[2048];
+  __shared__ int found;
   const uint32_t nb = 1u << bits;
-  uint64_t rank = (uint64_t)state[1] | ((uint64_t)state[2] << 32);
-  uint64_t cum = 0;
-  uint32_t b = 0;
-  for (; b < nb; ++b) {
-    if (cum + hist[b] > rank) break;
-    cum += hist[b];
+  const uint64_t rank = (uint64_t)state[1] | ((uint64_t)state[2] << 32);
+  for (int i = threadIdx.x; i < 2048; i += 1024) sc[i] = (uint32_t)i < nb ? hist[i] : 0ull;
+  if (threadIdx.x == 0) found = -1;
+  __syncthreads();
+  // inclusive scan, two elements per thread
+  for (int o = 1; o < 2048; o <<= 1) {
+    const int i0 = threadIdx.x, i1 = threadIdx.x + 1024;
+    const unsigned long long a0 = i0 >= o ? sc[i0 - o] : 0ull;
+    const unsigned long long a1 = i1 >= o ? sc[i1 - o] : 0ull;
+    __syncthreads();
+    sc[i0] += a0;
+    sc[i1] += a1;
+    __syncthreads();
   }
-  if (b == nb) b = nb - 1u;  // only when nothing matched (no observed entries)
-  rank -= cum;
-  state[0] = (state[0] << bits) | b;
-  state[1] = (uint32_t)(rank & 0xFFFFFFFFu);
-  state[2] = (uint32_t)(rank >> 32);
-  for (uint32_t i = 0; i < nb; ++i) hist[i] = 0u;
+  for (int i = threadIdx.x; i < (int)nb; i += 1024) {
+    const unsigned long long excl = i ? sc[i - 1] : 0ull;
+    if (excl <= rank && rank < sc[i]) found = i;  // exactly one bin qualifies
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t b = found >= 0 ? (uint32_t)found : nb - 1u;  // none: nothing observed
+    const uint64_t excl = (found > 0) ? sc[found - 1] : 0ull;
+    const uint64_t r = found >= 0 ? rank - excl : rank;
+    state[0] = (state[0] << bits) | b;
+    state[1] = (uint32_t)(r & 0xFFFFFFFFu);
+    state[2] = (uint32_t)(r >> 32);
+  }
+  for (int i = threadIdx.x; i < (int)nb; i += 1024) hist[i] = 0u;
 }
 
 __global__ void k_qsigma(const uint32_t* state, double c, const double* sigma_min, double shrink,
@@ -539,7 +649,7 @@ hipError_t launch_quantile_sigma(const float* keys, int64_t n_slots_hint, const 
   for (int r = 0; r < 3; ++r) {
     hipLaunchKernelGGL(k_qhist, dim3(g), dim3(256), 0, st, keys, nslots, shifts[r], bitsv[r],
                        state, hist);
-    hipLaunchKernelGGL(k_qpick, dim3(1), dim3(1), 0, st, bitsv[r], state, hist);
+    hipLaunchKernelGGL(k_qpick, dim3(1), dim3(1024), 0, st, bitsv[r], state, hist);
   }
   hipLaunchKernelGGL(k_qsigma, dim3(1), dim3(1), 0, st, state, c, sigma_min, shrink, sigma);
   return hipGetLastError();

@@ -140,7 +140,7 @@ __global__ void k_slices(LayoutArgs a) {
     mx = max(mx, c[l]);
     sum += c[l];
   }
-  a.slice_len[s] = mx;
+  a.slice_len[s] = (mx + kGroup - 1) / kGroup * kGroup;
   if (sum) atomicAdd((unsigned long long*)a.nobs, (unsigned long long)sum);
 }
 
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_fill(LayoutArgs a, const uint8_t* __res
   const int64_t nct = min((int64_t)a.ct_w, a.ncols - col0);
   const int64_t sid = w * 4 + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const int64_t base = a.slice_off[sid] + lane;
+  const int64_t base = a.slice_off[sid];
   const int len = a.slice_len[sid];
   int t = 0;
   if (row < a.nrows) {
@@ -202,15 +202,17 @@ __global__ __launch_bounds__(256) void k_fill(LayoutArgs a, const uint8_t* __res
     for (int64_t c = 0; c < nct; ++c) {
       const int64_t off = ro + a.coloff[col0 + c];
       if (mask[off]) {
-        vals[base + (int64_t)t * kWave] = X[off];
-        cols[base + (int64_t)t * kWave] = (uint16_t)c;
+        const int64_t slot = slot_of(base, t, lane);
+        vals[slot] = X[off];
+        cols[slot] = (uint16_t)c;
         ++t;
       }
     }
   }
   for (; t < len; ++t) {
-    vals[base + (int64_t)t * kWave] = real(0);
-    cols[base + (int64_t)t * kWave] = kPad;
+    const int64_t slot = slot_of(base, t, lane);
+    vals[slot] = real(0);
+    cols[slot] = kPad;
   }
 }
 

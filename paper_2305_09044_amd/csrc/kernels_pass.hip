@@ -7,8 +7,9 @@
 // flat in the same a + r_k*c order, zero padded to RRP).  One lane owns one row of a
 // 64-row slice and walks that row's entries inside the work-group's column tile,
 // whose V^T items sit in LDS.  Modes:
-//   kModeGrad : e = x - xhat, w = exp(-e^2/2s^2) (eq. 7), S(row) += w e V^T(col)
-//               (the row factor of d in eq. 9), plus loss / weighted-LS / count sums.
+//   kModeGrad : e = x - xhat, w = exp(-e^2/2s^2) (eq. 7), S_ct(row) = sum w e V^T(col) over
+//               the tile ct (the row factor of d in eq. 9, one partial per column tile),
+//               plus loss / weighted-LS / count sums.
 //   kModeLS   : q = <TH(row), V^T(col)> with TH = H(i_k) U(m_B), sum w q^2 (eq. 12).
 //   kModeResid: |e| per slot for the kernel-width quantile (padding -> +inf).
 //   kModeLoss : sum of sigma^2 (1 - w) (eq. 4 as a loss).
@@ -100,18 +101,14 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
   }
 
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  const real* __restrict__ vals = static_cast<const real*>(a.vals);
-  const uint16_t* __restrict__ cols = a.cols;
+  // this lane's entries: groups of kGroup values / columns, one wide load each
+  const real* __restrict__ vbase = static_cast<const real*>(a.vals) + off + lane * kGroup;
+  const uint16_t* __restrict__ cbase = a.cols + off + lane * kGroup;
+  constexpr int kGroupStride = kWave * kGroup;
+  const int ngroups = len / kGroup;
 
-  for (int it = 0; it < len; ++it) {
-    const int64_t slot = off + (int64_t)it * kWave + lane;
-    const uint16_t c = cols[slot];
-    if (c == kPad) {
-      if constexpr (MODE == kModeResid) a.resid[slot] = __int_as_float(0x7f800000);
-      continue;
-    }
-    const real x = vals[slot];
-    const V* vp = reinterpret_cast<const V*>(Vs + (int)c * RRP);
+  auto process = [&](const real x, const int c, const int64_t slot) {
+    const V* vp = reinterpret_cast<const V*>(Vs + c * RRP);
     real vr[kHoldV ? RRP : 1];
     real xh0 = real(0), xh1 = real(0);
     real q0 = real(0), q1 = real(0);
@@ -160,14 +157,53 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
       s0 += (double)l;
       s2 += 1.0;
     }
+  };
+
+  struct Grp {
+    V x[kGroup / VW];
+    uint4 c;
+  };
+  auto load_group = [&](int g) {
+    Grp r;
+    const V* xp = reinterpret_cast<const V*>(vbase + (int64_t)g * kGroupStride);
+#pragma unroll
+    for (int i = 0; i < kGroup / VW; ++i) r.x[i] = xp[i];
+    r.c = *reinterpret_cast<const uint4*>(cbase + (int64_t)g * kGroupStride);
+    return r;
+  };
+
+  Grp cur;
+  if (ngroups > 0) cur = load_group(0);
+  for (int g = 0; g < ngroups; ++g) {
+    Grp nxt;
+    if (g + 1 < ngroups) nxt = load_group(g + 1);  // prefetch one group ahead
+    const real* xs = reinterpret_cast<const real*>(cur.x);
+    const uint32_t cw[4] = {cur.c.x, cur.c.y, cur.c.z, cur.c.w};
+#pragma unroll
+    for (int i = 0; i < kGroup; ++i) {
+      const int c = (int)((cw[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu);
+      const int64_t slot = off + (int64_t)g * kGroupStride + lane * kGroup + i;
+      if (c == kPad) {
+        if constexpr (MODE == kModeResid) a.resid[slot] = __int_as_float(0x7f800000);
+        continue;
+      }
+      process(xs[i], c, slot);
+    }
+    cur = nxt;
   }
 
   if constexpr (MODE == kModeGrad) {
-    if (row_ok && len > 0) {
-      real* sp = static_cast<real*>(a.S) + row * RRP;
+    // per-column-tile partial of the row factor, plain stores (summed in fixed order later)
+    if (row_ok) {
+      V* sp = reinterpret_cast<V*>(static_cast<real*>(a.S) + (ct * a.nrows + row) * RRP);
 #pragma unroll
-      for (int j = 0; j < RRP; ++j)
-        if (j < a.RR) atomicAdd(sp + j, u[j]);
+      for (int v = 0; v < NV; ++v) {
+        V q;
+        real* qs = reinterpret_cast<real*>(&q);
+#pragma unroll
+        for (int w = 0; w < VW; ++w) qs[w] = u[v * VW + w];
+        sp[v] = q;
+      }
     }
   }
 

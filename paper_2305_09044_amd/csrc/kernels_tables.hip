@@ -108,12 +108,35 @@ hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t
   return hipGetLastError();
 }
 
+// S[row][j] = sum over column tiles c of Spart[c][row][j], fixed order (in place into tile 0)
+template <typename real>
+__global__ void k_sum_tiles(real* __restrict__ S, int n_ct, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    real acc = S[t];
+    for (int c = 1; c < n_ct; ++c) acc += S[(int64_t)c * n + t];
+    S[t] = acc;
+  }
+}
+
+hipError_t launch_sum_tiles(int dtype, void* S, int n_ct, int64_t n, hipStream_t st) {
+  if (n_ct <= 1 || n <= 0) return hipSuccess;
+  dim3 g(grid_for(n, 256, 4096)), b(256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_sum_tiles<float>, g, b, 0, st, (float*)S, n_ct, n);
+  else
+    hipLaunchKernelGGL(k_sum_tiles<double>, g, b, 0, st, (double*)S, n_ct, n);
+  return hipGetLastError();
+}
+
 // D(i_k)[a, b] = sum_{m_B} sum_c St(i_k + I_k m_B)[a + r_k c] * U(m_B)[b + r_k1 c]
-// (St^T U^T of the two-factor split of the gradient).  U.ptr == nullptr: no B modes,
+// (St^T U^T of the two-factor split of the gradient); St(row) is the fixed-order sum of
+// the n_ct column-tile partials written by the gradient pass.  U.ptr == nullptr: no B modes,
 // U = identity (r_s = r_k1) and D(i_k) = St(i_k).
 // grid: (I_k, nchunk); block 256 threads, thread e < r_k*r_k1 owns one output.
 template <typename real>
-__global__ __launch_bounds__(256) void k_contract(const real* __restrict__ S, int RRP, int64_t Ik,
+__global__ __launch_bounds__(256) void k_contract(const real* __restrict__ S, int RRP, int n_ct,
+                                                  int64_t nrows, int64_t Ik,
                                                   int64_t nB, int r_k, int r_s, int r_k1,
                                                   const real* __restrict__ U, int64_t Us,
                                                   const int32_t* __restrict__ Ulist,
@@ -131,7 +154,11 @@ __global__ __launch_bounds__(256) void k_contract(const real* __restrict__ S, in
   for (int64_t m = m0; m < m1; ++m) {
     const real* sp = S + (ik + Ik * m) * RRP;
     __syncthreads();
-    if (threadIdx.x < r_k * r_s) srow[threadIdx.x] = sp[threadIdx.x];
+    if (threadIdx.x < r_k * r_s) {
+      real acc_s = real(0);
+      for (int c = 0; c < n_ct; ++c) acc_s += sp[(int64_t)c * nrows * RRP + threadIdx.x];
+      srow[threadIdx.x] = acc_s;
+    }
     if (U && threadIdx.x < r_k1 * r_s) {
       const real* up = U + (Ulist ? (int64_t)Ulist[m] : m) * Us;
       urow[threadIdx.x] = up[threadIdx.x];
@@ -150,16 +177,16 @@ __global__ __launch_bounds__(256) void k_contract(const real* __restrict__ S, in
   if (e < RRk) part[((int64_t)chunk * Ik + ik) * RRk + e] = acc;
 }
 
-hipError_t launch_contract(int dtype, const void* S, int RRP, int64_t Ik, int64_t nB, int r_k,
-                           int r_s, int r_k1, ItemRef U, double* part, int nchunk,
-                           hipStream_t st) {
+hipError_t launch_contract(int dtype, const void* S, int RRP, int n_ct, int64_t nrows, int64_t Ik,
+                           int64_t nB, int r_k, int r_s, int r_k1, ItemRef U, double* part,
+                           int nchunk, hipStream_t st) {
   dim3 g((unsigned)Ik, (unsigned)nchunk), b(256);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_contract<float>, g, b, 0, st, (const float*)S, RRP, Ik, nB, r_k, r_s,
-                       r_k1, (const float*)U.ptr, U.stride, U.list, part, nchunk);
+    hipLaunchKernelGGL(k_contract<float>, g, b, 0, st, (const float*)S, RRP, n_ct, nrows, Ik, nB,
+                       r_k, r_s, r_k1, (const float*)U.ptr, U.stride, U.list, part, nchunk);
   else
-    hipLaunchKernelGGL(k_contract<double>, g, b, 0, st, (const double*)S, RRP, Ik, nB, r_k, r_s,
-                       r_k1, (const double*)U.ptr, U.stride, U.list, part, nchunk);
+    hipLaunchKernelGGL(k_contract<double>, g, b, 0, st, (const double*)S, RRP, n_ct, nrows, Ik, nB,
+                       r_k, r_s, r_k1, (const double*)U.ptr, U.stride, U.list, part, nchunk);
   return hipGetLastError();
 }
 

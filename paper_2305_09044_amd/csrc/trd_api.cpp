@@ -40,6 +40,7 @@ struct trd_ctx {
   size_t ws_bytes = 0;
 
   bool has_problem = false;
+  bool has_shape = false;
   int N = 0;
   int64_t dims[kMaxN] = {0};
   int32_t ranks[kMaxN] = {0};
@@ -55,7 +56,7 @@ struct trd_ctx {
   // tables and work buffers (sized for the largest core and sketch)
   void* T = nullptr; void* TH = nullptr; void* V = nullptr; void* S = nullptr;
   void* U = nullptr; void* chainA = nullptr; void* chainB = nullptr;
-  int64_t cap_T = 0, cap_V = 0, cap_U = 0, cap_chain = 0;
+  int64_t cap_T = 0, cap_V = 0, cap_U = 0, cap_chain = 0, cap_S = 0;
   double* K[kMaxN] = {nullptr};
   double* P0 = nullptr; double* P1 = nullptr; double* G = nullptr; double* Cinv = nullptr;
   double* d64 = nullptr; double* h64 = nullptr; void* h_real = nullptr;
@@ -68,6 +69,8 @@ struct trd_ctx {
   uint32_t* qhist = nullptr; uint32_t* qstate = nullptr;
   double* Dbuf[2] = {nullptr, nullptr}; double* M = nullptr;
   double* eta_hist = nullptr;     // [N] per sweep
+  double* host_rep = nullptr;     // mapped pinned host memory for the per-sweep report
+  double* host_rep_dev = nullptr; // its device address
   SketchWS sk;
 
   // profiling of the fused gradient pass
@@ -123,6 +126,9 @@ void free_all(trd_ctx* ctx) {
   for (void* p : ctx->allocs) hipFree(p);
   ctx->allocs.clear();
   ctx->ws_bytes = 0;
+  if (ctx->host_rep) hipHostFree(ctx->host_rep);
+  ctx->host_rep = nullptr;
+  ctx->host_rep_dev = nullptr;
 }
 
 size_t esz(int dtype) { return dtype == 0 ? 4 : 8; }
@@ -250,7 +256,6 @@ int ensure_tables(trd_ctx* ctx, int64_t needT, int64_t needV, int64_t needU, int
   if (needT > ctx->cap_T) {
     TRY(dev_alloc(ctx, &ctx->T, needT * e));
     TRY(dev_alloc(ctx, &ctx->TH, needT * e));
-    TRY(dev_alloc(ctx, &ctx->S, needT * e));
     ctx->cap_T = needT;
   }
   if (needV > ctx->cap_V) {
@@ -265,6 +270,14 @@ int ensure_tables(trd_ctx* ctx, int64_t needT, int64_t needV, int64_t needU, int
     TRY(dev_alloc(ctx, &ctx->chainA, needChain * e));
     TRY(dev_alloc(ctx, &ctx->chainB, needChain * e));
     ctx->cap_chain = needChain;
+  }
+  return TRD_OK;
+}
+
+int ensure_S(trd_ctx* ctx, int64_t need) {
+  if (need > ctx->cap_S) {
+    TRY(dev_alloc(ctx, &ctx->S, need * esz(ctx->dtype)));
+    ctx->cap_S = need;
   }
   return TRD_OK;
 }
@@ -535,12 +548,12 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   TRY(build_U(ctx, up, cores, Uref, nB, st));
   TRY(build_rowtable(ctx, up, cores[sp.k], Uref, nB, ctx->T, st));
   TRY(build_coltable(ctx, up, cores, st));
-  CK(launch_zero(ctx->S, (size_t)L.nrows * sp.RRP * esz(ctx->dtype), st));
+  TRY(ensure_S(ctx, (int64_t)L.n_ct * L.nrows * sp.RRP));
   TRY(run_pass(ctx, up, kModeGrad, st));
-  CK(launch_reduce_partials(ctx->part_pass, n_wg(L), 3, stats_dev ? stats_dev : ctx->scal + kStats,
-                            st));
-  CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, Ik, nB, sp.r_k, sp.r_s, sp.r_k1, Uref,
-                     ctx->part_misc, nchunk, st));
+  if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, n_wg(L), 3, stats_dev, st));
+  CK(launch_sum_tiles(ctx->dtype, ctx->S, L.n_ct, L.nrows * sp.RRP, st));
+  CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, 1, L.nrows, Ik, nB, sp.r_k, sp.r_s, sp.r_k1,
+                     Uref, ctx->part_misc, nchunk, st));
   CK(launch_contract_finish(ctx->dtype, ctx->part_misc, nchunk, Ik, sp.r_k * sp.r_k1, ctx->d64,
                             d_out, scale, st));
   if (Uout) *Uout = Uref;
@@ -580,15 +593,22 @@ int ring_gram(trd_ctx* ctx, int k, double* G_out, hipStream_t st) {
   int inner = ctx->ranks[(s1 + 1) % N] * ctx->ranks[(s1 + 1) % N];
   double* bufs[2] = {ctx->P0, ctx->P1};
   int which = 0;
+  if (N == 2) {
+    CK(launch_realign(cur, G_out, ctx->ranks[k], ctx->ranks[s1], st));
+    return TRD_OK;
+  }
   for (int t = 2; t <= N - 1; ++t) {
     const int m = (k + t) % N;
     const int cols = ctx->ranks[(m + 1) % N] * ctx->ranks[(m + 1) % N];
-    CK(launch_gemm64(cur, ctx->K[m], bufs[which], rows, inner, cols, st));
-    cur = bufs[which];
-    which ^= 1;
+    if (t == N - 1) {  // last factor: write G realigned
+      CK(launch_gemm64(cur, ctx->K[m], G_out, rows, inner, cols, st, ctx->ranks[k], ctx->ranks[s1]));
+    } else {
+      CK(launch_gemm64(cur, ctx->K[m], bufs[which], rows, inner, cols, st));
+      cur = bufs[which];
+      which ^= 1;
+    }
     inner = cols;
   }
-  CK(launch_realign(cur, G_out, ctx->ranks[k], ctx->ranks[s1], st));
   return TRD_OK;
 }
 
@@ -615,19 +635,18 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
   TRY(ensure_part(ctx, 0, nbl));
   CK(launch_apply_inverse(ctx->d64, ctx->Cinv, Ik, R, ctx->h64, ctx->h_real, ctx->dtype,
                           ctx->part_misc, ctx->flags, st));
-  CK(launch_reduce_partials(ctx->part_misc, nbl, 1, ctx->scal + kNum, st));
   TRY(build_rowtable(ctx, up, ctx->h_real, Uref, nB, ctx->TH, st));
   TRY(run_pass(ctx, up, kModeLS, st));
-  CK(launch_reduce_partials(ctx->part_pass, n_wg(*up.L), 3, ctx->scal + kTmp, st));
-  CK(launch_eta(ctx->scal + kNum, ctx->scal + kTmp, up.L->nobs_dev, ctx->scal + kEta, ctx->flags,
-                flags_user, eta_user, st));
-  CK(launch_update(ctx->dtype, cores[k], ctx->h64, ctx->scal + kEta, Ik * R, st));
+  CK(launch_finish_step(ctx->dtype, ctx->part_misc, nbl, ctx->part_pass, n_wg(*up.L),
+                        up.L->nobs_dev, ctx->flags, flags_user, ctx->scal + kEta, eta_user, cores[k],
+                        ctx->h64, Ik * R, st));
   return TRD_OK;
 }
 
-int check_ctx(trd_ctx* ctx) {
+int check_ctx(trd_ctx* ctx, bool need_problem = true) {
   if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
-  if (!ctx->has_problem) return fail(ctx, TRD_ESTATE, "call trd_set_problem first");
+  if (need_problem && !ctx->has_problem) return fail(ctx, TRD_ESTATE, "call trd_set_problem first");
+  if (!ctx->has_shape) return fail(ctx, TRD_ESTATE, "call trd_set_shape or trd_set_problem first");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail(ctx, TRD_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
   return TRD_OK;
@@ -693,6 +712,43 @@ const char* trd_last_error(const trd_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_free_err.c_str();
 }
 
+int trd_set_shape(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ranks, int dtype) {
+  if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
+  if (N < 2 || N > kMaxN) return fail(ctx, TRD_EUNSUPPORTED, "N must be in [2, 8]");
+  if (!dims || !ranks) return fail(ctx, TRD_EINVAL, "NULL argument");
+  if (dtype != TRD_F32 && dtype != TRD_F64) return fail(ctx, TRD_EINVAL, "dtype must be TRD_F32 or TRD_F64");
+  double total = 1.0;
+  for (int j = 0; j < N; ++j) {
+    if (dims[j] < 1) return fail(ctx, TRD_EINVAL, "dims must be >= 1");
+    if (ranks[j] < 1) return fail(ctx, TRD_EINVAL, "ranks must be >= 1");
+    if (ranks[j] > kMaxRank) return fail(ctx, TRD_EUNSUPPORTED, "ranks must be <= 16");
+    total *= (double)dims[j];
+  }
+  if (total >= 4.6e18) return fail(ctx, TRD_EUNSUPPORTED, "prod(dims) must be < 2^62");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return fail(ctx, TRD_EDEVICE, hipGetErrorString(he));
+  CK(hipDeviceSynchronize());
+  free_all(ctx);
+  const int device = ctx->device;
+  for (hipEvent_t ev : ctx->ev_pairs) hipEventDestroy(ev);
+  *ctx = trd_ctx();
+  ctx->device = device;
+  ctx->N = N;
+  ctx->dtype = dtype;
+  int64_t s = 1;
+  for (int j = 0; j < N; ++j) {
+    ctx->dims[j] = dims[j];
+    ctx->ranks[j] = ranks[j];
+    ctx->strides[j] = s;
+    s *= dims[j];
+  }
+  TRY(alloc_n(ctx, &ctx->scal, kScalCount));
+  TRY(alloc_n(ctx, &ctx->flags, 4));
+  TRY(ensure_dense(ctx));
+  ctx->has_shape = true;
+  return TRD_OK;
+}
+
 int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ranks, int dtype,
                     const void* X, const uint8_t* mask, void* stream) {
   if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
@@ -707,35 +763,16 @@ int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ran
     total *= (double)dims[j];
   }
   if (total >= 4.6e18) return fail(ctx, TRD_EUNSUPPORTED, "prod(dims) must be < 2^62");
-  hipError_t he = hipSetDevice(ctx->device);
-  if (he != hipSuccess) return fail(ctx, TRD_EDEVICE, hipGetErrorString(he));
   hipStream_t st = (hipStream_t)stream;
-  // drop any previous problem
-  CK(hipStreamSynchronize(st));
-  free_all(ctx);
-  const int device = ctx->device;
-  for (hipEvent_t ev : ctx->ev_pairs) hipEventDestroy(ev);
-  *ctx = trd_ctx();
-  ctx->device = device;
-
-  ctx->N = N;
-  ctx->dtype = dtype;
+  TRY(trd_set_shape(ctx, N, dims, ranks, dtype));  // drops any previous problem
   ctx->X = X;
   ctx->mask = mask;
-  int64_t s = 1;
-  for (int j = 0; j < N; ++j) {
-    ctx->dims[j] = dims[j];
-    ctx->ranks[j] = ranks[j];
-    ctx->strides[j] = s;
-    s *= dims[j];
-  }
-  TRY(alloc_n(ctx, &ctx->scal, kScalCount));
-  TRY(alloc_n(ctx, &ctx->flags, 4));
   TRY(alloc_n(ctx, &ctx->qhist, 2048));
   TRY(alloc_n(ctx, &ctx->qstate, 4));
   TRY(alloc_n(ctx, &ctx->eta_hist, N));
+  CK(hipHostMalloc((void**)&ctx->host_rep, 64 * sizeof(double), hipHostMallocMapped));
+  CK(hipHostGetDevicePointer((void**)&ctx->host_rep_dev, ctx->host_rep, 0));
   CK(launch_zero(ctx->flags, 4 * sizeof(uint32_t), st));
-  TRY(ensure_dense(ctx));
 
   ctx->splits.resize(N);
   ctx->layouts.resize(N);
@@ -811,7 +848,7 @@ int trd_problem_info(const trd_ctx* ctx, int64_t* n_obs, size_t* workspace_bytes
 
 int trd_reconstruct(trd_ctx* ctx, const void* const* cores, const int64_t* lin_idx, int64_t n,
                     void* out, void* stream) {
-  TRY(check_ctx(ctx));
+  TRY(check_ctx(ctx, false));
   TRY(check_cores(ctx, cores));
   if (!out && n > 0) return fail(ctx, TRD_EINVAL, "out is NULL");
   if (n < 0) return fail(ctx, TRD_EINVAL, "n < 0");
@@ -852,7 +889,7 @@ int trd_grad(trd_ctx* ctx, const void* const* cores, int k, double sigma, const 
 }
 
 int trd_fgmc_gram(trd_ctx* ctx, const void* const* cores, int k, double* G_out, void* stream) {
-  TRY(check_ctx(ctx));
+  TRY(check_ctx(ctx, false));
   TRY(check_cores(ctx, cores));
   if (k < 0 || k >= ctx->N) return fail(ctx, TRD_EINVAL, "k out of range");
   if (!G_out) return fail(ctx, TRD_EINVAL, "G_out is NULL");
@@ -967,11 +1004,14 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
                             ctx->Dbuf[cur ^ 1], t > 0 ? 1 : 0, ctx->part_misc, st));
       CK(launch_reduce_partials(ctx->part_misc, (IN * IN + 255) / 256, 2, ctx->scal + kConv, st));
     }
-    CK(hipMemcpyAsync(&hr.sigma, ctx->scal + kSigma, sizeof(double), hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(hr.conv, ctx->scal + kConv, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(&hr.flags, ctx->flags + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(etas.data(), ctx->eta_hist, N * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(launch_pack_report(ctx->scal + kSigma, ctx->scal + kConv, ctx->flags + 1, ctx->eta_hist, N,
+                          ctx->host_rep_dev, st));
     CK(hipStreamSynchronize(st));
+    hr.sigma = ctx->host_rep[0];
+    hr.conv[0] = ctx->host_rep[1];
+    hr.conv[1] = ctx->host_rep[2];
+    hr.flags = (uint32_t)ctx->host_rep[3];
+    for (int k = 0; k < N; ++k) etas[k] = ctx->host_rep[4 + k];
     cur ^= 1;
     const double e = t > 0 ? sqrt(hr.conv[0]) / sqrt(hr.conv[1]) : INFINITY;
     if (rep) {

@@ -16,6 +16,14 @@ constexpr int kRowsPerWG = 256;    // rows of one work-group tile (4 waves x 64 
 constexpr int kWave = 64;
 constexpr uint16_t kPad = 0xFFFF;  // padding marker in the sliced-ELL column array
 constexpr int kPassThreads = 256;
+// Entries of a slice are stored in groups of kGroup per lane: entry t of lane l sits at
+// slice_base + (t / kGroup) * (64 * kGroup) + l * kGroup + t % kGroup, so that one lane
+// reads its next kGroup values and columns with wide loads.  Slice lengths are
+// multiples of kGroup.
+constexpr int kGroup = 8;
+__host__ __device__ inline int64_t slot_of(int64_t base, int t, int lane) {
+  return base + (int64_t)(t / kGroup) * (kWave * kGroup) + lane * kGroup + (t % kGroup);
+}
 constexpr uint32_t TRD_FLAG_EMPTY_BIT = 1u;     // mirrors TRD_FLAG_EMPTY
 constexpr uint32_t TRD_FLAG_ZERO_DEN_BIT = 2u;  // mirrors TRD_FLAG_ZERO_DEN
 constexpr uint32_t TRD_FLAG_NOTSPD_BIT = 4u;    // mirrors TRD_FLAG_NOTSPD
@@ -92,8 +100,10 @@ hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRe
 hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* out,
                        int64_t out_stride, int transpose_out, hipStream_t st);
 hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t st);
-hipError_t launch_contract(int dtype, const void* S, int RRP, int64_t Ik, int64_t nB, int r_k,
-                           int r_s, int r_k1, ItemRef U, double* part, int nchunk, hipStream_t st);
+hipError_t launch_contract(int dtype, const void* S, int RRP, int n_ct, int64_t nrows, int64_t Ik,
+                           int64_t nB, int r_k, int r_s, int r_k1, ItemRef U, double* part,
+                           int nchunk, hipStream_t st);
+hipError_t launch_sum_tiles(int dtype, void* S, int n_ct, int64_t n, hipStream_t st);
 hipError_t launch_contract_finish(int dtype, const double* part, int nchunk, int64_t Ik, int RRk,
                                   double* d64, void* d_out, double scale, hipStream_t st);
 
@@ -103,7 +113,7 @@ struct PassArgs {
   const void* T;        // [nrows][RRP]
   const void* TH;       // [nrows][RRP] (line search)
   const void* V;        // [ncols][RRP]
-  void* S;              // [nrows][RRP] gradient accumulators (atomics)
+  void* S;              // [n_ct][nrows][RRP] per-column-tile gradient partials
   const void* vals;
   const uint16_t* cols;
   const int64_t* slice_off;
@@ -123,7 +133,11 @@ int64_t pass_ct_w(int dtype, int prec, int RRP);
 hipError_t launch_kron_factor(int dtype, const void* Z, int r0, int64_t I, int r1, double* K,
                               hipStream_t st);
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int m, int kk, int n,
-                         hipStream_t st);
+                         hipStream_t st, int r_k = 0, int r_k1 = 0);
+hipError_t launch_finish_step(int dtype, const double* pnum, int64_t n_num, const double* pden,
+                              int64_t n_den, const int64_t* nobs, uint32_t* flags,
+                              uint32_t* flags_user, double* eta, double* eta_user, void* Z,
+                              const double* h, int64_t nz, hipStream_t st);
 hipError_t launch_realign(const double* P, double* G, int r_k, int r_k1, hipStream_t st);
 hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
                           uint32_t* flags, hipStream_t st);
@@ -137,6 +151,8 @@ hipError_t launch_update(int dtype, void* Z, const double* h64, const double* et
 hipError_t launch_reduce_partials(const double* part, int64_t n, int width, double* out,
                                   hipStream_t st);
 hipError_t launch_set_scalar(double* p, double v, hipStream_t st);
+hipError_t launch_pack_report(const double* sigma, const double* conv, const uint32_t* flags,
+                              const double* eta, int N, double* out, hipStream_t st);
 hipError_t launch_convergence(int dtype, const void* ZN, const double* G, int64_t IN, int n,
                               double* M, double* D, const double* Dprev, int have_prev,
                               double* part, hipStream_t st);
