@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="100,100,100,20")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the path runs on a single MI355X); got --gpus {args.gpus}",
@@ -113,6 +115,15 @@ def main():
     import torch
     import paper_2305_09044_amd as trd
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
+        del src, dst
     t_setup = time.perf_counter()
     w, dims, Xd, Pd, mask_np = build_inputs(args.workload, args.seed)
     prob = trd.Problem(Xd, Pd, dims, w.ranks)

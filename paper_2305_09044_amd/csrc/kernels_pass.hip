@@ -38,14 +38,16 @@ __device__ __forceinline__ float one_minus_exp_neg(float u, float w) {
 }
 __device__ __forceinline__ double one_minus_exp_neg(double u, double w) { return -expm1(-u); }
 
-template <typename real, int RRP, int MODE>
+template <typename real, int RC, int MODE>
 __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   real* Vs = reinterpret_cast<real*>(smem_raw);
   using V = typename VecOf<real>::T;
   constexpr int VW = VecOf<real>::W;
+  constexpr int RRP = (RC + 3) / 4 * 4;   // storage stride of one table item
   constexpr int NV = RRP / VW;
   constexpr bool kHoldV = RRP <= 64;
+  constexpr bool kGrad = MODE == kModeGrad || MODE == kModeGradFast;
 
   const int64_t wg = blockIdx.x;
   const int64_t ct = wg / a.n_rg, g = wg % a.n_rg;
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
   const bool ls_limit = isinf(sig);
 
   real t[RRP];
-  real u[(MODE == kModeGrad || MODE == kModeLS) ? RRP : 1];
+  real u[(kGrad || MODE == kModeLS) ? RRP : 1];
 #pragma unroll
   for (int j = 0; j < RRP; ++j) t[j] = real(0);
 #pragma unroll
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
   }
 
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  real f0 = real(0);  // per-lane line-search sum (converted to double once per lane)
   // this lane's entries: groups of kGroup values / columns, one wide load each
   const real* __restrict__ vbase = static_cast<const real*>(a.vals) + off + lane * kGroup;
   const uint16_t* __restrict__ cbase = a.cols + off + lane * kGroup;
@@ -119,9 +122,11 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
 #pragma unroll
       for (int w = 0; w < VW; ++w) {
         const int j = v * VW + w;
-        if (j & 1) xh1 = fma(t[j], qs[w], xh1); else xh0 = fma(t[j], qs[w], xh0);
-        if constexpr (MODE == kModeLS) {
-          if (j & 1) q1 = fma(u[j], qs[w], q1); else q0 = fma(u[j], qs[w], q0);
+        if (j < RC) {
+          if (j & 1) xh1 = fma(t[j], qs[w], xh1); else xh0 = fma(t[j], qs[w], xh0);
+          if constexpr (MODE == kModeLS) {
+            if (j & 1) q1 = fma(u[j], qs[w], q1); else q0 = fma(u[j], qs[w], q0);
+          }
         }
         if constexpr (kHoldV) vr[j] = qs[w];
       }
@@ -129,27 +134,30 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
     const real e = x - (xh0 + xh1);
     const real uu = e * e * inv2s2;
     const real w = ls_limit ? real(1) : fast_exp_neg(uu);
-    if constexpr (MODE == kModeGrad) {
+    if constexpr (kGrad) {
       const real y = w * e;
       if constexpr (kHoldV) {
 #pragma unroll
-        for (int j = 0; j < RRP; ++j) u[j] = fma(y, vr[j], u[j]);
+        for (int j = 0; j < RC; ++j) u[j] = fma(y, vr[j], u[j]);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           V q = vp[v];
           const real* qs = reinterpret_cast<const real*>(&q);
 #pragma unroll
-          for (int ww = 0; ww < VW; ++ww) u[v * VW + ww] = fma(y, qs[ww], u[v * VW + ww]);
+          for (int ww = 0; ww < VW; ++ww)
+            if (v * VW + ww < RC) u[v * VW + ww] = fma(y, qs[ww], u[v * VW + ww]);
         }
       }
-      const real l = ls_limit ? real(0.5) * e * e : sig2 * one_minus_exp_neg(uu, w);
-      s0 += (double)l;
-      s1 += (double)(w * e * e);
-      s2 += 1.0;
+      if constexpr (MODE == kModeGrad) {
+        const real l = ls_limit ? real(0.5) * e * e : sig2 * one_minus_exp_neg(uu, w);
+        s0 += (double)l;
+        s1 += (double)(w * e * e);
+        s2 += 1.0;
+      }
     } else if constexpr (MODE == kModeLS) {
       const real q = q0 + q1;
-      s0 += (double)(w * q * q);
+      f0 = fma(w * q, q, f0);
     } else if constexpr (MODE == kModeResid) {
       a.resid[slot] = (float)fabs(e);
     } else {
@@ -192,7 +200,8 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
     cur = nxt;
   }
 
-  if constexpr (MODE == kModeGrad) {
+  if constexpr (MODE == kModeLS) s0 = (double)f0;
+  if constexpr (kGrad) {
     // per-column-tile partial of the row factor, plain stores (summed in fixed order later)
     if (row_ok) {
       V* sp = reinterpret_cast<V*>(static_cast<real*>(a.S) + (ct * a.nrows + row) * RRP);
@@ -226,19 +235,23 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
   }
 }
 
-static const int kRRPs[] = {4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 48, 56, 64, 80, 100, 128};
+// compute lengths with their own kernels; other r_k * r_s use the next larger one (the
+// table items are zero padded, so the extra terms add nothing)
+static const int kRCs[] = {4, 8, 9, 12, 16, 20, 24, 25, 28, 32, 36, 40, 48, 49, 56, 64, 80, 81, 100,
+                           112, 128};
 
-int pass_rrp(int RR) {
-  for (int v : kRRPs)
+int pass_rc(int RR) {
+  for (int v : kRCs)
     if (v >= RR) return v;
   return -1;
 }
 
-bool pass_supported(int RRP) {
-  for (int v : kRRPs)
-    if (v == RRP) return true;
-  return false;
+int pass_rrp(int RR) {
+  const int rc = pass_rc(RR);
+  return rc < 0 ? -1 : (rc + 3) / 4 * 4;
 }
+
+bool pass_supported(int RR) { return pass_rc(RR) > 0; }
 
 int64_t pass_ct_w(int dtype, int prec, int RRP) {
   (void)prec;
@@ -252,27 +265,29 @@ int64_t pass_ct_w(int dtype, int prec, int RRP) {
   return w;
 }
 
-template <typename real, int RRP>
-static hipError_t launch_rrp(int mode, const PassArgs& a, hipStream_t st) {
+template <typename real, int RC>
+static hipError_t launch_rc(int mode, const PassArgs& a, hipStream_t st) {
+  constexpr int RRP = (RC + 3) / 4 * 4;
   const int64_t nwg = a.n_rg * a.n_ct;
   const size_t lds = (size_t)a.ct_w * RRP * sizeof(real);
   dim3 g((unsigned)nwg), b(kPassThreads);
   switch (mode) {
-    case kModeGrad: hipLaunchKernelGGL((k_pass<real, RRP, kModeGrad>), g, b, lds, st, a); break;
-    case kModeLS: hipLaunchKernelGGL((k_pass<real, RRP, kModeLS>), g, b, lds, st, a); break;
-    case kModeResid: hipLaunchKernelGGL((k_pass<real, RRP, kModeResid>), g, b, lds, st, a); break;
-    default: hipLaunchKernelGGL((k_pass<real, RRP, kModeLoss>), g, b, lds, st, a); break;
+    case kModeGrad: hipLaunchKernelGGL((k_pass<real, RC, kModeGrad>), g, b, lds, st, a); break;
+    case kModeGradFast: hipLaunchKernelGGL((k_pass<real, RC, kModeGradFast>), g, b, lds, st, a); break;
+    case kModeLS: hipLaunchKernelGGL((k_pass<real, RC, kModeLS>), g, b, lds, st, a); break;
+    case kModeResid: hipLaunchKernelGGL((k_pass<real, RC, kModeResid>), g, b, lds, st, a); break;
+    default: hipLaunchKernelGGL((k_pass<real, RC, kModeLoss>), g, b, lds, st, a); break;
   }
   return hipGetLastError();
 }
 
 template <typename real>
 static hipError_t launch_real(int mode, const PassArgs& a, hipStream_t st) {
-  switch (a.RRP) {
-#define TRD_CASE(R) case R: return launch_rrp<real, R>(mode, a, st);
-    TRD_CASE(4) TRD_CASE(8) TRD_CASE(12) TRD_CASE(16) TRD_CASE(20) TRD_CASE(24) TRD_CASE(28)
-    TRD_CASE(32) TRD_CASE(36) TRD_CASE(40) TRD_CASE(48) TRD_CASE(56) TRD_CASE(64) TRD_CASE(80)
-    TRD_CASE(100) TRD_CASE(128)
+  switch (pass_rc(a.RR)) {
+#define TRD_CASE(R) case R: return launch_rc<real, R>(mode, a, st);
+    TRD_CASE(4) TRD_CASE(8) TRD_CASE(9) TRD_CASE(12) TRD_CASE(16) TRD_CASE(20) TRD_CASE(24)
+    TRD_CASE(25) TRD_CASE(28) TRD_CASE(32) TRD_CASE(36) TRD_CASE(40) TRD_CASE(48) TRD_CASE(49)
+    TRD_CASE(56) TRD_CASE(64) TRD_CASE(80) TRD_CASE(81) TRD_CASE(100) TRD_CASE(112) TRD_CASE(128)
 #undef TRD_CASE
     default: return hipErrorInvalidValue;
   }
@@ -281,6 +296,7 @@ static hipError_t launch_real(int mode, const PassArgs& a, hipStream_t st) {
 hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st) {
   (void)prec;
   if (a.n_rg * a.n_ct <= 0) return hipSuccess;
+  if (pass_rrp(a.RR) != a.RRP) return hipErrorInvalidValue;
   return dtype == 0 ? launch_real<float>(mode, a, st) : launch_real<double>(mode, a, st);
 }
 

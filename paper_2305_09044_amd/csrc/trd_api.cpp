@@ -506,7 +506,7 @@ int64_t n_wg(const Layout& L) { return L.n_rg * L.n_ct; }
 
 int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   PassArgs a = pass_args(ctx, up);
-  const bool timed = ctx->prof && mode == kModeGrad;
+  const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     CK(hipEventCreate(&e0));
@@ -549,7 +549,7 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   TRY(build_rowtable(ctx, up, cores[sp.k], Uref, nB, ctx->T, st));
   TRY(build_coltable(ctx, up, cores, st));
   TRY(ensure_S(ctx, (int64_t)L.n_ct * L.nrows * sp.RRP));
-  TRY(run_pass(ctx, up, kModeGrad, st));
+  TRY(run_pass(ctx, up, stats_dev ? kModeGrad : kModeGradFast, st));
   if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, n_wg(L), 3, stats_dev, st));
   CK(launch_sum_tiles(ctx->dtype, ctx->S, L.n_ct, L.nrows * sp.RRP, st));
   CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, 1, L.nrows, Ik, nB, sp.r_k, sp.r_s, sp.r_k1,

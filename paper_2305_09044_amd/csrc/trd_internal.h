@@ -108,7 +108,7 @@ hipError_t launch_contract_finish(int dtype, const double* part, int nchunk, int
                                   double* d64, void* d_out, double scale, hipStream_t st);
 
 // fused entry pass
-enum PassMode { kModeGrad = 0, kModeLS = 1, kModeResid = 2, kModeLoss = 3 };
+enum PassMode { kModeGrad = 0, kModeLS = 1, kModeResid = 2, kModeLoss = 3, kModeGradFast = 4 };
 struct PassArgs {
   const void* T;        // [nrows][RRP]
   const void* TH;       // [nrows][RRP] (line search)
@@ -125,7 +125,8 @@ struct PassArgs {
   int ct_w, RR, RRP, n_ct;
 };
 hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st);
-bool pass_supported(int RRP);
+bool pass_supported(int RR);
+int pass_rc(int RR);
 int pass_rrp(int RR);
 int64_t pass_ct_w(int dtype, int prec, int RRP);
 
