@@ -50,8 +50,10 @@ def build_inputs(wname: str, seed: int, dims=None):
     std = w.core_std if w.core_std is not None else 1.0 / math.sqrt(w.ranks[0])
     cores_t = (synth.lowpass_cores(dims, w.ranks, seed, std) if w.lowpass
                else synth.gaussian_cores(dims, w.ranks, seed, std))
-    shape = trd.Problem(None, None, dims, w.ranks, dtype=torch.float32)
-    ct = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(cores_t, np.float32)]
+    npdt = np.float64 if w.dtype == "f64" else np.float32
+    tdt = torch.float64 if w.dtype == "f64" else torch.float32
+    shape = trd.Problem(None, None, dims, w.ranks, dtype=tdt)
+    ct = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(cores_t, npdt)]
     xs = shape.reconstruct(ct)
     torch.cuda.synchronize()
     xstar = xs.cpu().numpy().astype(np.float64).reshape(dims, order="F")
@@ -63,7 +65,7 @@ def build_inputs(wname: str, seed: int, dims=None):
             else synth.block_mask(dims, 16, 1.0 - w.rho, seed))
     X = synth.assemble(w, xstar, mask, seed)
     del xstar
-    Xd = torch.from_numpy(X.astype(np.float32).ravel(order="F")).cuda()
+    Xd = torch.from_numpy(X.astype(npdt).ravel(order="F")).cuda()
     Pd = torch.from_numpy(mask.ravel(order="F").copy()).cuda()
     del X
     return w, dims, Xd, Pd, mask
@@ -103,7 +105,10 @@ def main():
     ap.add_argument("--workload", default="tr4_100_r5")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", default="100,100,100,20")
+    ap.add_argument("--cpu-sample", default=None,
+                    help="dims of the oracle's bounded sample (default: the workload with its last "
+                         "mode cut so the sample has at most 2e7 entries)")
+    ap.add_argument("--sketch", action="store_true", help="RStS path with the workload's sample sizes")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -132,13 +137,15 @@ def main():
     import numpy as np
     import synth
     Z0 = synth.init_cores(dims, w.ranks, args.seed)
-    cores = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(Z0, np.float32)]
+    npdt = np.float64 if w.dtype == "f64" else np.float32
+    cores = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(Z0, npdt)]
+    sk = list(w.sketch) if (args.sketch and w.sketch) else None
     torch.cuda.synchronize()
     log(f"setup {time.perf_counter() - t_setup:.1f}s n_obs={n_obs} split={info['split']} "
         f"workspace={info['workspace_bytes'] / 2**20:.0f} MiB")
 
     if args.warmup > 0:
-        prob.fit(cores, max_sweeps=args.warmup, tol=0.0)
+        prob.fit(cores, max_sweeps=args.warmup, tol=0.0, sketch_sizes=sk)
     torch.cuda.synchronize()
     prob.profile(True)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -146,7 +153,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    rep = prob.fit(cores, max_sweeps=args.steps, tol=0.0)
+    rep = prob.fit(cores, max_sweeps=args.steps, tol=0.0, sketch_sizes=sk, seed=args.seed)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -156,7 +163,9 @@ def main():
     elapsed = max(wall, gpu_s)
     assert rep["sweeps"] == args.steps, rep
     N = len(dims)
-    value = args.steps * N * n_obs / elapsed
+    # observed entries touched per sweep: all of them on the full path, the sketches' on RStS
+    per_sweep = N * n_obs if sk is None else prof["entries"] / args.steps
+    value = args.steps * per_sweep / elapsed
     log(f"timed {args.steps} sweeps: wall {wall * 1e3:.2f} ms, events {gpu_s * 1e3:.2f} ms, "
         f"sigma {rep['sigma'][-1]:.4g}, e {rep['e'][-1]:.3g}")
 
@@ -178,14 +187,18 @@ def main():
 
     out = {"metric": METRIC, "value": value, "unit": "observed entries/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w.dtype == "f64" else "f32",
            "data": "synthetic",
            "config": {"workload": args.workload, "dims": list(dims), "tr_ranks": list(w.ranks),
                       "observed_fraction": w.rho, "n_obs": n_obs, "path": "AWRTRD full sweep, FGMC, "
                       "quantile kernel width", "precision": "fp32"},
            "roofline": roof}
     if not args.no_cpu_baseline:
-        sample = tuple(int(v) for v in args.cpu_sample.split(","))
+        if args.cpu_sample:
+            sample = tuple(int(v) for v in args.cpu_sample.split(","))
+        else:
+            rest = math.prod(dims[:-1])
+            sample = tuple(dims[:-1]) + (max(1, min(dims[-1], int(2e7 // rest))),)
         del prob, Xd, Pd
         torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, sample)

@@ -65,7 +65,7 @@ extern "C" {
 typedef struct trd_ctx trd_ctx;
 
 /*
- * Randomized subtensor sketch (RStS, Sec. 4.2.2, eq. 14, Alg. 1): for update k
+ * Randomized subtensor sketch (RStS, Sec. 4.3.2, eq. 14, Alg. 1): for update k
  * every mode j != k keeps sizes[j] lateral slices chosen uniformly without
  * replacement (sorted ascending), mode k keeps all I_k.  When `idx` is NULL the
  * library draws the sets itself from (seed, sweep, k, j) with the counter-based

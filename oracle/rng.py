@@ -1,6 +1,6 @@
 """Counter-based index sampling for randomized subtensor sketching (oracle side).
 
-RStS (Sec. 4.2.2 and Alg. 1) draws, for every core update k of sweep t and every
+RStS (Sec. 4.3.2 and Alg. 1) draws, for every core update k of sweep t and every
 mode j != k, an index set I_j of s_j lateral slices uniformly at random; I_k is the
 whole range.  The paper does not fix the sampling law or generator.  Reading used
 here (and by the library, which implements the same published generator on its

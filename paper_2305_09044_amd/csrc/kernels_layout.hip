@@ -51,6 +51,13 @@ hipError_t launch_copy_clamp(const int32_t* in, int64_t n, int64_t dim, int32_t*
   return hipGetLastError();
 }
 
+__global__ void k_accum_i64(int64_t* dst, const int64_t* src) { *dst += *src; }
+
+hipError_t launch_accum_i64(int64_t* dst, const int64_t* src, hipStream_t st) {
+  hipLaunchKernelGGL(k_accum_i64, dim3(1), dim3(1), 0, st, dst, src);
+  return hipGetLastError();
+}
+
 // Zero a buffer with a kernel (no memset node, so it is safe inside captured graphs).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   if (bytes == 0) return hipSuccess;
@@ -108,23 +115,28 @@ static LayoutArgs largs(const Layout& L) {
   return a;
 }
 
+// One wave per (column tile, row): lanes stride over the tile's columns, so 64 mask
+// reads are in flight per step; counts in fixed column order.
 __global__ __launch_bounds__(256) void k_count(LayoutArgs a, const uint8_t* __restrict__ mask) {
-  const int64_t w = blockIdx.x;
-  const int64_t ct = w / a.n_rg, g = w % a.n_rg;
-  const int64_t row = g * kRowsPerWG + threadIdx.x;
-  const int64_t col0 = ct * a.ct_w;
-  const int64_t nct = min((int64_t)a.ct_w, a.ncols - col0);
+  const int64_t gw = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;  // global wave
+  const int lane = threadIdx.x & 63;
+  const int64_t nrows_pad = a.n_rg * kRowsPerWG;
+  if (gw >= nrows_pad * a.n_ct) return;
+  const int64_t ct = gw / nrows_pad, row = gw % nrows_pad;
   int cnt = 0;
   if (row < a.nrows) {
+    const int64_t col0 = ct * a.ct_w;
+    const int64_t nct = min((int64_t)a.ct_w, a.ncols - col0);
     const int64_t ro = a.rowoff[row];
-    for (int64_t c = 0; c < nct; ++c) cnt += mask[ro + a.coloff[col0 + c]] != 0;
+    for (int64_t c = lane; c < nct; c += 64) cnt += mask[ro + a.coloff[col0 + c]] != 0;
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
   }
-  a.counts[ct * (a.n_rg * kRowsPerWG) + row] = cnt;
+  if (lane == 0) a.counts[ct * nrows_pad + row] = cnt;
 }
 
 hipError_t launch_count(const Layout& L, const uint8_t* mask, hipStream_t st) {
-  int64_t nwg = L.n_rg * L.n_ct;
-  hipLaunchKernelGGL(k_count, dim3((unsigned)nwg), dim3(kRowsPerWG), 0, st, largs(L), mask);
+  const int64_t waves = L.n_rg * kRowsPerWG * L.n_ct;
+  hipLaunchKernelGGL(k_count, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, largs(L), mask);
   return hipGetLastError();
 }
 
@@ -183,34 +195,47 @@ hipError_t launch_scan(const Layout& L, hipStream_t st) {
   return hipGetLastError();
 }
 
+// One wave per (column tile, row): the row's observed entries are written in column
+// order to the row's ELL lane (row % 64) of its slice, then padded to the slice length.
 template <typename real>
 __global__ __launch_bounds__(256) void k_fill(LayoutArgs a, const uint8_t* __restrict__ mask,
                                               const real* __restrict__ X, real* __restrict__ vals,
                                               uint16_t* __restrict__ cols) {
-  const int64_t w = blockIdx.x;
-  const int64_t ct = w / a.n_rg, g = w % a.n_rg;
-  const int64_t row = g * kRowsPerWG + threadIdx.x;
-  const int64_t col0 = ct * a.ct_w;
-  const int64_t nct = min((int64_t)a.ct_w, a.ncols - col0);
-  const int64_t sid = w * 4 + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
+  const int64_t gw = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t nrows_pad = a.n_rg * kRowsPerWG;
+  if (gw >= nrows_pad * a.n_ct) return;
+  const int64_t ct = gw / nrows_pad, row = gw % nrows_pad;
+  const int64_t g = row / kRowsPerWG, in_g = row % kRowsPerWG;
+  const int64_t sid = (ct * a.n_rg + g) * 4 + in_g / kWave;
+  const int ell_lane = (int)(in_g % kWave);
   const int64_t base = a.slice_off[sid];
   const int len = a.slice_len[sid];
-  int t = 0;
+  int t = 0;  // entries written so far (wave uniform)
   if (row < a.nrows) {
+    const int64_t col0 = ct * a.ct_w;
+    const int64_t nct = min((int64_t)a.ct_w, a.ncols - col0);
     const int64_t ro = a.rowoff[row];
-    for (int64_t c = 0; c < nct; ++c) {
-      const int64_t off = ro + a.coloff[col0 + c];
-      if (mask[off]) {
-        const int64_t slot = slot_of(base, t, lane);
+    for (int64_t c0 = 0; c0 < nct; c0 += 64) {
+      const int64_t c = c0 + lane;
+      int64_t off = 0;
+      bool obs = false;
+      if (c < nct) {
+        off = ro + a.coloff[col0 + c];
+        obs = mask[off] != 0;
+      }
+      const unsigned long long bal = __ballot(obs);
+      if (obs) {
+        const int pos = t + __popcll(bal & ((1ull << lane) - 1ull));
+        const int64_t slot = slot_of(base, pos, ell_lane);
         vals[slot] = X[off];
         cols[slot] = (uint16_t)c;
-        ++t;
       }
+      t += __popcll(bal);
     }
   }
-  for (; t < len; ++t) {
-    const int64_t slot = slot_of(base, t, lane);
+  for (int p = t + lane; p < len; p += 64) {
+    const int64_t slot = slot_of(base, p, ell_lane);
     vals[slot] = real(0);
     cols[slot] = kPad;
   }
@@ -218,13 +243,14 @@ __global__ __launch_bounds__(256) void k_fill(LayoutArgs a, const uint8_t* __res
 
 hipError_t launch_fill(const Layout& L, const uint8_t* mask, const void* X, int dtype,
                        hipStream_t st) {
-  int64_t nwg = L.n_rg * L.n_ct;
+  const int64_t waves = L.n_rg * kRowsPerWG * L.n_ct;
+  const unsigned nb = (unsigned)((waves + 3) / 4);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)nwg), dim3(kRowsPerWG), 0, st, largs(L),
-                       mask, (const float*)X, (float*)L.vals, L.cols);
+    hipLaunchKernelGGL(k_fill<float>, dim3(nb), dim3(256), 0, st, largs(L), mask, (const float*)X,
+                       (float*)L.vals, L.cols);
   else
-    hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)nwg), dim3(kRowsPerWG), 0, st, largs(L),
-                       mask, (const double*)X, (double*)L.vals, L.cols);
+    hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(256), 0, st, largs(L), mask, (const double*)X,
+                       (double*)L.vals, L.cols);
   return hipGetLastError();
 }
 

@@ -77,6 +77,7 @@ struct trd_ctx {
   bool prof = false;
   std::vector<hipEvent_t> ev_free, ev_pairs;
   int64_t prof_slots = 0, prof_entries = 0;
+  int64_t* prof_nobs_dev = nullptr;  // device sum of sketch observed counts while profiling
 };
 
 namespace {
@@ -519,7 +520,15 @@ int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
     ctx->ev_pairs.push_back(e0);
     ctx->ev_pairs.push_back(e1);
     ctx->prof_slots += up.L->slots;
-    ctx->prof_entries += up.L->nobs;
+    if (up.lists) {  // sketch: count known on the device only
+      if (!ctx->prof_nobs_dev) {
+        TRY(alloc_n(ctx, &ctx->prof_nobs_dev, 1));
+        CK(launch_zero(ctx->prof_nobs_dev, sizeof(int64_t), st));
+      }
+      CK(launch_accum_i64(ctx->prof_nobs_dev, up.L->nobs_dev, st));
+    } else {
+      ctx->prof_entries += up.L->nobs;
+    }
   }
   return TRD_OK;
 }
@@ -1113,10 +1122,17 @@ int trd_profile_read(trd_ctx* ctx, int64_t* launches, double* total_ms, int64_t*
     hipEventDestroy(b);
   }
   ctx->ev_pairs.clear();
+  int64_t dev_entries = 0;
+  if (ctx->prof_nobs_dev) {
+    hipError_t e = hipMemcpy(&dev_entries, ctx->prof_nobs_dev, sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(ctx, TRD_EDEVICE, hipGetErrorString(e));
+    e = hipMemset(ctx->prof_nobs_dev, 0, sizeof(int64_t));
+    if (e != hipSuccess) return fail(ctx, TRD_EDEVICE, hipGetErrorString(e));
+  }
   if (launches) *launches = n;
   if (total_ms) *total_ms = ms;
   if (slots) *slots = ctx->prof_slots;
-  if (entries) *entries = ctx->prof_entries;
+  if (entries) *entries = ctx->prof_entries + dev_entries;
   ctx->prof_slots = 0;
   ctx->prof_entries = 0;
   return TRD_OK;

@@ -93,6 +93,7 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t launch_copy_clamp(const int32_t* in, int64_t n, int64_t dim, int32_t* out,
                              uint32_t* bad, hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_accum_i64(int64_t* dst, const int64_t* src, hipStream_t st);
 
 // tables (Def. 2 merges)
 hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRef R, int64_t nR,
