@@ -33,8 +33,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def src_hash() -> str:
-    return hashlib.sha256(open(PASS_SRC, "rb").read()).hexdigest()[:16]
+def src_hash(precision: str = "fp32") -> str:
+    src = PASS_SRC if precision == "fp32" else PASS_SRC.replace("kernels_pass", "kernels_tile")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
 def build_inputs(wname: str, seed: int, dims=None):
@@ -58,9 +59,11 @@ def build_inputs(wname: str, seed: int, dims=None):
     torch.cuda.synchronize()
     xstar = xs.cpu().numpy().astype(np.float64).reshape(dims, order="F")
     shape.close()
-    del xs, ct
+    del ct
     if w.normalise_max:
-        xstar /= float(np.max(np.abs(xstar)))
+        mx = float(np.max(np.abs(xstar)))
+        xstar /= mx
+        xs /= mx
     mask = (synth.bernoulli_mask(dims, w.rho, seed) if w.mask_kind == "bernoulli"
             else synth.block_mask(dims, 16, 1.0 - w.rho, seed))
     X = synth.assemble(w, xstar, mask, seed)
@@ -68,7 +71,50 @@ def build_inputs(wname: str, seed: int, dims=None):
     Xd = torch.from_numpy(X.astype(npdt).ravel(order="F")).cuda()
     Pd = torch.from_numpy(mask.ravel(order="F").copy()).cuda()
     del X
-    return w, dims, Xd, Pd, mask
+    return w, dims, Xd, Pd, mask, xs
+
+
+def recovery_error(prob, cores, xstar_d) -> float:
+    """||Xhat - X*||_F / ||X*||_F over every entry (measurement only)."""
+    import torch
+    xh = prob.reconstruct(cores)
+    num = torch.linalg.vector_norm((xh - xstar_d).double())
+    den = torch.linalg.vector_norm(xstar_d.double())
+    return float(num / den)
+
+
+def equal_accuracy(prob, Z0_flat, xstar_d, sweeps, checkpoints):
+    """FP32 vs BF16 sweeps from the same start: recovery error after c sweeps for each
+    checkpoint c (each run from scratch, so the timed c sweeps are exactly those of a
+    c-sweep fit), the BF16 plateau e* = its error after the last checkpoint, and the
+    sweeps / time each precision needs to reach e*."""
+    import torch
+    res = {}
+    for prec in ("native", "bf16"):
+        # one untimed sweep builds any layout this precision needs before the timed fits
+        prob.fit([z.clone() for z in Z0_flat], max_sweeps=1, tol=0.0, precision=prec)
+        rows = []
+        for c in checkpoints:
+            cores = [z.clone() for z in Z0_flat]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prob.fit(cores, max_sweeps=c, tol=0.0, precision=prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rows.append((c, dt, recovery_error(prob, cores, xstar_d)))
+        res[prec] = rows
+    e_star = res["bf16"][-1][2]
+    out = {"target_rel_error": e_star, "sweeps_max": sweeps}
+    for prec, name in (("native", "fp32"), ("bf16", "bf16")):
+        hit = next((r for r in res[prec] if r[2] <= e_star * (1 + 1e-9)), None)
+        out[name] = {"trace": [{"sweeps": c, "ms": round(dt * 1e3, 3), "rel_error": err}
+                               for c, dt, err in res[prec]],
+                     "sweeps_to_target": hit[0] if hit else None,
+                     "ms_to_target": round(hit[1] * 1e3, 3) if hit else None}
+    if out["fp32"]["ms_to_target"] and out["bf16"]["ms_to_target"]:
+        out["bf16_speedup_at_equal_error"] = round(out["fp32"]["ms_to_target"] /
+                                                   out["bf16"]["ms_to_target"], 3)
+    return out
 
 
 def cpu_baseline(wname: str, seed: int, sample_dims):
@@ -109,6 +155,11 @@ def main():
                     help="dims of the oracle's bounded sample (default: the workload with its last "
                          "mode cut so the sample has at most 2e7 entries)")
     ap.add_argument("--sketch", action="store_true", help="RStS path with the workload's sample sizes")
+    ap.add_argument("--no-equal-accuracy", action="store_true",
+                    help="skip the FP32-vs-BF16 time-to-equal-recovery-error comparison")
+    ap.add_argument("--accuracy-sweeps", type=int, default=30)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
+                    help="bf16: matrix-core passes with bf16 subchain tables (FP32 residuals)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -130,7 +181,7 @@ def main():
         log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
         del src, dst
     t_setup = time.perf_counter()
-    w, dims, Xd, Pd, mask_np = build_inputs(args.workload, args.seed)
+    w, dims, Xd, Pd, mask_np, xstar_d = build_inputs(args.workload, args.seed)
     prob = trd.Problem(Xd, Pd, dims, w.ranks)
     info = prob.info()
     n_obs = info["n_obs"]
@@ -144,8 +195,9 @@ def main():
     log(f"setup {time.perf_counter() - t_setup:.1f}s n_obs={n_obs} split={info['split']} "
         f"workspace={info['workspace_bytes'] / 2**20:.0f} MiB")
 
+    prec = "bf16" if args.precision == "bf16" else "native"
     if args.warmup > 0:
-        prob.fit(cores, max_sweeps=args.warmup, tol=0.0, sketch_sizes=sk)
+        prob.fit(cores, max_sweeps=args.warmup, tol=0.0, sketch_sizes=sk, precision=prec)
     torch.cuda.synchronize()
     prob.profile(True)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -153,7 +205,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    rep = prob.fit(cores, max_sweeps=args.steps, tol=0.0, sketch_sizes=sk, seed=args.seed)
+    rep = prob.fit(cores, max_sweeps=args.steps, tol=0.0, sketch_sizes=sk, seed=args.seed,
+                   precision=prec)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -169,37 +222,51 @@ def main():
     log(f"timed {args.steps} sweeps: wall {wall * 1e3:.2f} ms, events {gpu_s * 1e3:.2f} ms, "
         f"sigma {rep['sigma'][-1]:.4g}, e {rep['e'][-1]:.3g}")
 
-    # roofline of the fused gradient pass: algorithmic bytes = value (4 B) + in-tile
-    # column index (2 B) per observed entry of the update
+    # roofline of the fused gradient pass.  Algorithmic bytes per launch: FP32 sliced-ELL
+    # passes read a 4 B value and a 2 B in-tile column per observed entry; the BF16
+    # matrix-core passes read the 4 B value plus one mask bit per tensor position.
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
-    bytes_per_launch = prof["entries"] / max(prof["launches"], 1) * (4 + 2)
+    ent = prof["entries"] / max(prof["launches"], 1)
+    if prec == "bf16" and sk is None:
+        bytes_per_launch = ent * 4 + math.prod(dims) / 8
+    else:
+        bytes_per_launch = ent * (4 + 2)
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
-        tf = json.load(open(TRAFFIC_FILE))
-        if tf.get("src_hash") == src_hash() and tf.get("workload") == args.workload:
+        tf = json.load(open(TRAFFIC_FILE)).get(args.precision, {})
+        if tf.get("src_hash") == src_hash(args.precision) and tf.get("workload") == args.workload \
+                and sk is None:
             traffic = tf.get("bytes_per_launch")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_pass<float,RRP,kModeGrad> (fused reconstruct+weight+gradient)",
+            "kernel": ("k_tpass<K,GradFast> (MFMA bf16 reconstruct+weight+gradient)" if prec == "bf16"
+                       else "k_pass<float,RC,GradFast> (fused reconstruct+weight+gradient)"),
             "avg_launch_ms": round(avg_ms, 5), "launches": prof["launches"],
             "bytes_per_launch": int(bytes_per_launch)}
 
     out = {"metric": METRIC, "value": value, "unit": "observed entries/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w.dtype == "f64" else "f32",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w.dtype == "f64" else ("bf16" if prec == "bf16" else "f32"),
            "data": "synthetic",
            "config": {"workload": args.workload, "dims": list(dims), "tr_ranks": list(w.ranks),
                       "observed_fraction": w.rho, "n_obs": n_obs, "path": "AWRTRD full sweep, FGMC, "
-                      "quantile kernel width", "precision": "fp32"},
+                      "quantile kernel width", "precision": args.precision},
            "roofline": roof}
+    if not args.no_equal_accuracy and sk is None and w.dtype != "f64":
+        C = args.accuracy_sweeps
+        cps = sorted(set([1, 2, 3, 4, 6, 8, 10, 12, 15, 20, 25, C]) & set(range(1, C + 1)))
+        Z0_flat = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(Z0, np.float32)]
+        out["equal_accuracy"] = equal_accuracy(prob, Z0_flat, xstar_d, C, cps)
+        log("equal accuracy:", json.dumps({k: v for k, v in out["equal_accuracy"].items()
+                                           if k not in ("fp32", "bf16")}))
     if not args.no_cpu_baseline:
         if args.cpu_sample:
             sample = tuple(int(v) for v in args.cpu_sample.split(","))
         else:
             rest = math.prod(dims[:-1])
             sample = tuple(dims[:-1]) + (max(1, min(dims[-1], int(2e7 // rest))),)
-        del prob, Xd, Pd
+        del prob, Xd, Pd, xstar_d
         torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, sample)
     print(json.dumps(out), flush=True)

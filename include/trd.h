@@ -223,6 +223,16 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
                       int32_t* const* idx_out, void* stream);
 
 /*
+ * Precision of the entry-wise passes of later trd_grad / trd_step / trd_loss_* calls
+ * (trd_fit uses its own opts.precision).  TRD_PREC_BF16 (FP32 problems only): the
+ * subchain tables are rounded to bf16 and the reconstruction and gradient contractions
+ * run on the matrix cores (BF16 operands, FP32 accumulation); residuals, weights and the
+ * FGMC Gram / scaled step stay in FP32 / FP64.  RStS sketches always use the native passes.
+ * The first BF16 use of a core builds its bitmask-tile layout (synchronizes the stream).
+ */
+int trd_set_precision(trd_ctx* ctx, int precision);
+
+/*
  * Per-launch timing of the fused reconstruct+weight+gradient pass, for measurement:
  * enable != 0 records HIP events around every launch of that kernel on its stream;
  * trd_profile_read returns the number of launches and their summed duration (ms) and

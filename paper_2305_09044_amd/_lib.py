@@ -86,6 +86,7 @@ def load() -> C.CDLL:
         "trd_loss_fwd": (i32, [vp, P(vp), dbl, vp, vp]),
         "trd_loss_bwd": (i32, [vp, P(vp), dbl, dbl, P(vp), vp]),
         "trd_sample_sketch": (i32, [C.c_uint64, i32, i32, i32, P(i64), P(C.c_int32), P(vp), vp]),
+        "trd_set_precision": (i32, [vp, i32]),
         "trd_profile": (i32, [vp, i32]),
         "trd_profile_read": (i32, [vp, P(i64), P(dbl), P(i64), P(i64)]),
     }
@@ -307,6 +308,10 @@ class Problem:
         _check(load().trd_loss_bwd(self._ctx, _ptr_array(cores), float(sigma), float(grad_scale),
                                    _ptr_array(grads), C.c_void_p(_stream())), self._ctx)
         return grads
+
+    def set_precision(self, precision: str):
+        code = {"native": TRD_PREC_NATIVE, "bf16": TRD_PREC_BF16}[precision]
+        _check(load().trd_set_precision(self._ctx, code), self._ctx)
 
     def profile(self, enable: bool):
         _check(load().trd_profile(self._ctx, 1 if enable else 0), self._ctx)

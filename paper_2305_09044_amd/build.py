@@ -30,7 +30,7 @@ FLAGS = [
 ]
 
 SOURCES = ["kernels_layout.hip", "kernels_tables.hip", "kernels_pass.hip", "kernels_dense.hip",
-           "trd_api.cpp"]
+           "kernels_tile.hip", "trd_api.cpp"]
 
 
 def _compile(src: str) -> str:

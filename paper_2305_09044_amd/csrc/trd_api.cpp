@@ -52,6 +52,10 @@ struct trd_ctx {
   double maxabs = 0.0;            // max |x| over the observed entries
   std::vector<Split> splits;      // full-path split per core
   std::vector<Layout> layouts;    // full-path layout per core
+  std::vector<TLayout> tlayouts;  // bitmask-tile layout per core (BF16 form, built on demand)
+  int prec = TRD_PREC_NATIVE;     // precision of the entry passes
+  uint16_t* Tb = nullptr; uint16_t* THb = nullptr; uint16_t* Vb = nullptr;
+  int64_t cap_Tb = 0, cap_Vb = 0;
 
   // tables and work buffers (sized for the largest core and sketch)
   void* T = nullptr; void* TH = nullptr; void* V = nullptr; void* S = nullptr;
@@ -306,6 +310,7 @@ int contract_chunks(int64_t Ik, int64_t nB) {
 struct Update {
   Split sp;
   Layout* L = nullptr;
+  TLayout* TL = nullptr;                  // non-null: matrix-core (BF16) passes
   const int64_t* counts = nullptr;        // per-mode counts of this update
   const int32_t* const* lists = nullptr;  // per-mode device lists (nullptr = full)
   int64_t cnt[kMaxN];
@@ -373,8 +378,44 @@ int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStr
   return TRD_OK;
 }
 
+// bitmask-tile layout of core k (same split as the ELL layout), built once on first use
+int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
+  TLayout& T = ctx->tlayouts[k];
+  if (T.ready) return TRD_OK;
+  const Split& sp = ctx->splits[k];
+  const Layout& L = ctx->layouts[k];
+  T.nrows = L.nrows;
+  T.ncols = L.ncols;
+  T.K = tile_k(sp.RR);
+  const int64_t cwmax = tile_cw(T.K);
+  T.n_ct = (int)((T.ncols + cwmax - 1) / cwmax);
+  T.CW = (int)(((T.ncols + T.n_ct - 1) / T.n_ct + 31) / 32 * 32);
+  T.n_ch = T.CW / 32;
+  T.n_rg = (T.nrows + kRowsPerWG - 1) / kRowsPerWG;
+  T.n_blocks = (int64_t)T.n_ct * T.n_rg * 4 * T.n_ch;
+  T.rowoff = L.rowoff;
+  T.coloff = L.coloff;
+  TRY(alloc_n(ctx, &T.masks, T.n_blocks * 64));
+  TRY(alloc_n(ctx, &T.bcnt, T.n_blocks));
+  TRY(alloc_n(ctx, &T.boff, T.n_blocks + 1));
+  TRY(alloc_n(ctx, &T.total_dev, 1));
+  CK(launch_tile_build(T, ctx->mask, ctx->X, ctx->dtype, false, st));
+  CK(hipMemcpyAsync(&T.nobs, T.total_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  // slack: the MFMA pass prefetches 1024 values per chunk without bounds branches
+  TRY(alloc_n(ctx, &T.vals, T.nobs + 2048));
+  CK(launch_zero(T.vals, (size_t)(T.nobs + 2048) * sizeof(float), st));
+  CK(launch_tile_build(T, ctx->mask, ctx->X, ctx->dtype, true, st));
+  T.ready = true;
+  return TRD_OK;
+}
+
 int prepare_update(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
-  if (sk) return prepare_sketch(ctx, k, sk, up, st);
+  if (sk) return prepare_sketch(ctx, k, sk, up, st);  // sketches use the ELL passes
+  if (ctx->prec == TRD_PREC_BF16) {
+    TRY(ensure_tile_layout(ctx, k, st));
+    up.TL = &ctx->tlayouts[k];
+  }
   up.sp = ctx->splits[k];
   up.L = &ctx->layouts[k];
   for (int j = 0; j < ctx->N; ++j) {
@@ -504,9 +545,64 @@ PassArgs pass_args(trd_ctx* ctx, const Update& up) {
 }
 
 int64_t n_wg(const Layout& L) { return L.n_rg * L.n_ct; }
+int64_t up_nwg(const Update& up) { return up.TL ? up.TL->n_rg * up.TL->n_ct : n_wg(*up.L); }
+int up_nct(const Update& up) { return up.TL ? up.TL->n_ct : up.L->n_ct; }
+const int64_t* up_nobs_dev(const Update& up) { return up.TL ? up.TL->total_dev : up.L->nobs_dev; }
+
+int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStream_t st) {
+  if (nrows * K > ctx->cap_Tb) {
+    TRY(alloc_n(ctx, &ctx->Tb, nrows * K));
+    TRY(alloc_n(ctx, &ctx->THb, nrows * K));
+    ctx->cap_Tb = nrows * K;
+  }
+  if (ncols * K > ctx->cap_Vb) {
+    // slack of one column tile past the last column: the MFMA pass reads whole tiles;
+    // zero filled once (later tables leave only finite values behind)
+    const int64_t n = ncols * K + tile_cw(K) * (int64_t)K + 64 * K;
+    TRY(alloc_n(ctx, &ctx->Vb, n));
+    CK(launch_zero(ctx->Vb, (size_t)n * sizeof(uint16_t), st));
+    ctx->cap_Vb = ncols * K;
+  }
+  return TRD_OK;
+}
+
+// matrix-core pass: bf16 copies of the FP32 tables, then the MFMA kernel
+int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
+  const TLayout& TL = *up.TL;
+  const Split& sp = up.sp;
+  TRY(ensure_bf16_tables(ctx, TL.nrows, TL.ncols, TL.K, st));
+  if (mode == kModeLS) {
+    CK(launch_table_bf16((const float*)ctx->TH, TL.nrows, sp.RRP, TL.K, ctx->THb, st));
+  } else {
+    CK(launch_table_bf16((const float*)ctx->T, TL.nrows, sp.RRP, TL.K, ctx->Tb, st));
+    CK(launch_table_bf16((const float*)ctx->V, TL.ncols, sp.RRP, TL.K, ctx->Vb, st));
+  }
+  TPassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.T = ctx->Tb;
+  a.TH = ctx->THb;
+  a.V = ctx->Vb;
+  a.S = (float*)ctx->S;
+  a.masks = TL.masks;
+  a.boff = TL.boff;
+  a.vals = TL.vals;
+  a.resid = ctx->resid;
+  a.partials = ctx->part_pass;
+  a.sigma = ctx->scal + kSigma;
+  a.nrows = TL.nrows;
+  a.ncols = TL.ncols;
+  a.n_rbp = TL.n_rg * 4;
+  a.n_rg = TL.n_rg;
+  a.CW = TL.CW;
+  a.n_ch = TL.n_ch;
+  a.n_ct = TL.n_ct;
+  a.RR = sp.RR;
+  a.RRP = sp.RRP;
+  CK(launch_tpass(mode, TL.K, a, st));
+  return TRD_OK;
+}
 
 int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
-  PassArgs a = pass_args(ctx, up);
   const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
@@ -514,12 +610,17 @@ int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
     CK(hipEventCreate(&e1));
     CK(hipEventRecord(e0, st));
   }
-  CK(launch_pass(ctx->dtype, 0, mode, a, st));
+  if (up.TL) {
+    TRY(launch_tile_pass(ctx, up, mode, st));
+  } else {
+    PassArgs a = pass_args(ctx, up);
+    CK(launch_pass(ctx->dtype, 0, mode, a, st));
+  }
   if (timed) {
     CK(hipEventRecord(e1, st));
     ctx->ev_pairs.push_back(e0);
     ctx->ev_pairs.push_back(e1);
-    ctx->prof_slots += up.L->slots;
+    ctx->prof_slots += up.TL ? up.TL->nobs : up.L->slots;
     if (up.lists) {  // sketch: count known on the device only
       if (!ctx->prof_nobs_dev) {
         TRY(alloc_n(ctx, &ctx->prof_nobs_dev, 1));
@@ -545,7 +646,7 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   int64_t nB = 1;
   for (int t = 0; t < sp.p; ++t) nB *= up.counts[sp.B[t]];
   const int nchunk = contract_chunks(Ik, nB);
-  TRY(ensure_part(ctx, n_wg(L) * 3, std::max<int64_t>((int64_t)nchunk * Ik * sp.r_k * sp.r_k1, 8)));
+  TRY(ensure_part(ctx, up_nwg(up) * 3, std::max<int64_t>((int64_t)nchunk * Ik * sp.r_k * sp.r_k1, 8)));
   const int64_t nd = Ik * sp.r_k * sp.r_k1;
   if (nd > ctx->cap_d) {
     TRY(alloc_n(ctx, &ctx->d64, nd));
@@ -557,10 +658,10 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   TRY(build_U(ctx, up, cores, Uref, nB, st));
   TRY(build_rowtable(ctx, up, cores[sp.k], Uref, nB, ctx->T, st));
   TRY(build_coltable(ctx, up, cores, st));
-  TRY(ensure_S(ctx, (int64_t)L.n_ct * L.nrows * sp.RRP));
+  TRY(ensure_S(ctx, (int64_t)up_nct(up) * L.nrows * sp.RRP));
   TRY(run_pass(ctx, up, stats_dev ? kModeGrad : kModeGradFast, st));
-  if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, n_wg(L), 3, stats_dev, st));
-  CK(launch_sum_tiles(ctx->dtype, ctx->S, L.n_ct, L.nrows * sp.RRP, st));
+  if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, stats_dev, st));
+  CK(launch_sum_tiles(ctx->dtype, ctx->S, up_nct(up), L.nrows * sp.RRP, st));
   CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, 1, L.nrows, Ik, nB, sp.r_k, sp.r_s, sp.r_k1,
                      Uref, ctx->part_misc, nchunk, st));
   CK(launch_contract_finish(ctx->dtype, ctx->part_misc, nchunk, Ik, sp.r_k * sp.r_k1, ctx->d64,
@@ -646,8 +747,8 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
                           ctx->part_misc, ctx->flags, st));
   TRY(build_rowtable(ctx, up, ctx->h_real, Uref, nB, ctx->TH, st));
   TRY(run_pass(ctx, up, kModeLS, st));
-  CK(launch_finish_step(ctx->dtype, ctx->part_misc, nbl, ctx->part_pass, n_wg(*up.L),
-                        up.L->nobs_dev, ctx->flags, flags_user, ctx->scal + kEta, eta_user, cores[k],
+  CK(launch_finish_step(ctx->dtype, ctx->part_misc, nbl, ctx->part_pass, up_nwg(up),
+                        up_nobs_dev(up), ctx->flags, flags_user, ctx->scal + kEta, eta_user, cores[k],
                         ctx->h64, Ik * R, st));
   return TRD_OK;
 }
@@ -785,6 +886,7 @@ int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ran
 
   ctx->splits.resize(N);
   ctx->layouts.resize(N);
+  ctx->tlayouts.assign(N, TLayout());
   int64_t needT = 0, needV = 0, needU = 0, needC = 0, needPass = 0, needMisc = 8, needD = 0;
   for (int k = 0; k < N; ++k) {
     int64_t nrows, ncols;
@@ -932,8 +1034,10 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
   if (!o) return fail(ctx, TRD_EINVAL, "opts is NULL");
   if (o->max_sweeps < 1) return fail(ctx, TRD_EINVAL, "max_sweeps must be >= 1");
   if (!(o->lambda_rel >= 0.0)) return fail(ctx, TRD_EINVAL, "lambda_rel must be >= 0");
-  if (o->precision != TRD_PREC_NATIVE)
-    return fail(ctx, TRD_EUNSUPPORTED, "precision mode not available in this build");
+  if (o->precision != TRD_PREC_NATIVE && o->precision != TRD_PREC_BF16)
+    return fail(ctx, TRD_EINVAL, "unknown precision");
+  if (o->precision == TRD_PREC_BF16 && ctx->dtype != TRD_F32)
+    return fail(ctx, TRD_EUNSUPPORTED, "the BF16 form needs an FP32 problem");
   if (o->sigma_mode == TRD_SIGMA_FIXED) TRY(check_sigma(ctx, o->sigma));
   else if (o->sigma_mode == TRD_SIGMA_GIVEN) {
     if (!o->sigma_given) return fail(ctx, TRD_EINVAL, "sigma_given is NULL");
@@ -968,6 +1072,11 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
     rep->last_sigma = 0;
     rep->flags = 0;
   }
+  struct PrecGuard {
+    trd_ctx* c; int saved;
+    ~PrecGuard() { c->prec = saved; }
+  } guard{ctx, ctx->prec};
+  ctx->prec = o->precision;
   int cur = 0;
   struct HostRead { double sigma; double conv[2]; uint32_t flags; uint32_t pad; } hr;
   std::vector<double> etas(N);
@@ -983,23 +1092,26 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
       Update up;
       TRY(prepare_update(ctx, 0, sk, up, st));
       const Layout& L = *up.L;
-      if (L.slots_cap > ctx->cap_resid) {
-        TRY(alloc_n(ctx, &ctx->resid, L.slots_cap));
-        ctx->cap_resid = L.slots_cap;
+      // residual slots: ELL slots (padding holds +inf) or exactly the observed entries
+      const int64_t nkeys = up.TL ? up.TL->nobs : L.slots_cap;
+      const int64_t* nkeys_dev = up.TL ? up.TL->total_dev : L.total_dev;
+      if (nkeys > ctx->cap_resid) {
+        TRY(alloc_n(ctx, &ctx->resid, nkeys));
+        ctx->cap_resid = nkeys;
       }
       int64_t needT, needV, needU, needC;
       table_needs(ctx, up.sp, up.counts, L.nrows, L.ncols, needT, needV, needU, needC);
       TRY(ensure_tables(ctx, needT, needV, needU, needC));
-      TRY(ensure_part(ctx, n_wg(L) * 3, 8));
+      TRY(ensure_part(ctx, up_nwg(up) * 3, 8));
       ItemRef Uref;
       int64_t nB;
       TRY(build_U(ctx, up, (const void* const*)cores, Uref, nB, st));
       TRY(build_rowtable(ctx, up, cores[0], Uref, nB, ctx->T, st));
       TRY(build_coltable(ctx, up, (const void* const*)cores, st));
       TRY(run_pass(ctx, up, kModeResid, st));
-      CK(launch_quantile_sigma(ctx->resid, L.slots_cap, L.total_dev, o->q, o->c,
-                               ctx->scal + kSigmaMin, o->shrink, ctx->scal + kSigma, ctx->qhist,
-                               ctx->qstate, L.nobs_dev, st));
+      CK(launch_quantile_sigma(ctx->resid, nkeys, nkeys_dev, o->q, o->c, ctx->scal + kSigmaMin,
+                               o->shrink, ctx->scal + kSigma, ctx->qhist, ctx->qstate,
+                               up_nobs_dev(up), st));
     }
     for (int k = 0; k < N; ++k) {
       TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st));
@@ -1057,8 +1169,9 @@ int trd_loss_fwd(trd_ctx* ctx, const void* const* cores, double sigma, double* l
   TRY(build_U(ctx, up, cores, Uref, nB, st));
   TRY(build_rowtable(ctx, up, cores[0], Uref, nB, ctx->T, st));
   TRY(build_coltable(ctx, up, cores, st));
+  TRY(ensure_part(ctx, up_nwg(up) * 3, 8));
   TRY(run_pass(ctx, up, kModeLoss, st));
-  CK(launch_reduce_partials(ctx->part_pass, n_wg(L), 3, ctx->scal + kTmp, st));
+  CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, ctx->scal + kTmp, st));
   CK(hipMemcpyAsync(loss_dev, ctx->scal + kTmp, sizeof(double), hipMemcpyDeviceToDevice, st));
   return TRD_OK;
 }
@@ -1095,6 +1208,18 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
     s[j] = (int32_t)std::min<int64_t>(j == k ? dims[j] : sizes[j], dims[j]);
   }
   CK(launch_sample(seed, t, k, N, dims, s, idx_out, (hipStream_t)stream));
+  return TRD_OK;
+}
+
+int trd_set_precision(trd_ctx* ctx, int precision) {
+  if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
+  if (precision != TRD_PREC_NATIVE && precision != TRD_PREC_BF16)
+    return fail(ctx, TRD_EINVAL, "unknown precision");
+  if (precision == TRD_PREC_BF16) {
+    if (!ctx->has_problem) return fail(ctx, TRD_ESTATE, "call trd_set_problem first");
+    if (ctx->dtype != TRD_F32) return fail(ctx, TRD_EUNSUPPORTED, "the BF16 form needs an FP32 problem");
+  }
+  ctx->prec = precision;
   return TRD_OK;
 }
 

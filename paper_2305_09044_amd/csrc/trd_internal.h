@@ -165,6 +165,49 @@ hipError_t launch_reconstruct(int dtype, int N, const int64_t* dims, const int32
                               hipStream_t st);
 hipError_t launch_max_abs_observed(const Layout& L, int dtype, double* out, hipStream_t st);
 
+// ---------------------------------------------------------------- matrix-core (BF16) form
+// Bitmask tiles of one core-k matrix: per (64-row x 32-column block, lane) a 32-bit mask
+// and the block's observed values compacted in (lane, bit) order.
+struct TLayout {
+  int64_t nrows = 0, ncols = 0;
+  int K = 0;                       // padded contraction width (multiple of 32)
+  int CW = 0, n_ct = 0, n_ch = 0;  // column tile width, tiles, 32-column chunks per tile
+  int64_t n_rg = 0;                // 256-row groups (4 row blocks of 64)
+  int64_t n_blocks = 0;
+  const int64_t* rowoff = nullptr; // shared with the ELL layout of the same split
+  const int64_t* coloff = nullptr;
+  uint32_t* masks = nullptr;       // [n_blocks][64]
+  int32_t* bcnt = nullptr;         // [n_blocks]
+  int64_t* boff = nullptr;         // [n_blocks + 1]
+  int64_t* total_dev = nullptr;
+  float* vals = nullptr;           // [nobs]
+  int64_t nobs = 0;
+  bool ready = false;
+};
+
+struct TPassArgs {
+  const uint16_t* T;     // [nrows][K] bf16
+  const uint16_t* TH;    // [nrows][K] bf16 (line search)
+  const uint16_t* V;     // [ncols][K] bf16
+  float* S;              // [n_ct][nrows][RRP] per-column-tile partials
+  const uint32_t* masks;
+  const int64_t* boff;
+  const float* vals;
+  float* resid;          // kModeResid: |e| per observed entry, in value order
+  double* partials;      // [n_wg][3]
+  const double* sigma;
+  int64_t nrows, ncols, n_rbp, n_rg;
+  int CW, n_ch, n_ct, RR, RRP;
+};
+
+int tile_k(int RR);
+int64_t tile_cw(int K);
+hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* X, int dtype,
+                             bool fill, hipStream_t st);
+hipError_t launch_table_bf16(const float* in, int64_t n, int in_stride, int K, uint16_t* out,
+                             hipStream_t st);
+hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st);
+
 // sigma quantile by radix select over float bit patterns
 hipError_t launch_quantile_sigma(const float* keys, int64_t n_slots_hint, const int64_t* nslots,
                                  double q, double c, const double* sigma_min, double shrink,
