@@ -83,11 +83,13 @@ def recovery_error(prob, cores, xstar_d) -> float:
     return float(num / den)
 
 
-def equal_accuracy(prob, Z0_flat, xstar_d, sweeps, checkpoints):
+def equal_accuracy(prob, Z0_flat, xstar_d, sweeps, checkpoints, band=0.03):
     """FP32 vs BF16 sweeps from the same start: recovery error after c sweeps for each
     checkpoint c (each run from scratch, so the timed c sweeps are exactly those of a
     c-sweep fit), the BF16 plateau e* = its error after the last checkpoint, and the
-    sweeps / time each precision needs to reach e*."""
+    sweeps / time each precision needs to reach e*.  On its plateau the BF16 error
+    wanders by about a percent from sweep to sweep (rounding of the direction), so
+    reaching e* means an error within (1 + band) e*."""
     import torch
     res = {}
     for prec in ("native", "bf16"):
@@ -104,9 +106,9 @@ def equal_accuracy(prob, Z0_flat, xstar_d, sweeps, checkpoints):
             rows.append((c, dt, recovery_error(prob, cores, xstar_d)))
         res[prec] = rows
     e_star = res["bf16"][-1][2]
-    out = {"target_rel_error": e_star, "sweeps_max": sweeps}
+    out = {"target_rel_error": e_star, "band": band, "sweeps_max": sweeps}
     for prec, name in (("native", "fp32"), ("bf16", "bf16")):
-        hit = next((r for r in res[prec] if r[2] <= e_star * (1 + 1e-9)), None)
+        hit = next((r for r in res[prec] if r[2] <= e_star * (1 + band)), None)
         out[name] = {"trace": [{"sweeps": c, "ms": round(dt * 1e3, 3), "rel_error": err}
                                for c, dt, err in res[prec]],
                      "sweeps_to_target": hit[0] if hit else None,

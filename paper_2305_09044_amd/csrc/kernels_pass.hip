@@ -38,6 +38,11 @@ __device__ __forceinline__ float one_minus_exp_neg(float u, float w) {
 }
 __device__ __forceinline__ double one_minus_exp_neg(double u, double w) { return -expm1(-u); }
 
+// elements per staged item in LDS: RRP rounded up to an odd number of 16-byte units
+__host__ __device__ constexpr int lds_item_stride(int RRP, int esize) {
+  return ((RRP * esize / 16) % 2 == 1) ? RRP : RRP + 16 / esize;
+}
+
 template <typename real, int RC, int MODE>
 __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -46,27 +51,21 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
   constexpr int VW = VecOf<real>::W;
   constexpr int RRP = (RC + 3) / 4 * 4;   // storage stride of one table item
   constexpr int NV = RRP / VW;
+  // LDS stride of one staged item: an odd number of 16-byte units, so that lanes reading
+  // items of different columns at the same offset fall in different banks
+  constexpr int SP = lds_item_stride(RRP, (int)sizeof(real));
+  constexpr int NVS = SP / VW;
   constexpr bool kHoldV = RRP <= 64;
   constexpr bool kGrad = MODE == kModeGrad || MODE == kModeGradFast;
 
+  // work-group = (column group cg, 256-row group g); it walks the column tiles of its
+  // group, restaging V^T items per tile, and keeps the row factor in registers throughout
   const int64_t wg = blockIdx.x;
-  const int64_t ct = wg / a.n_rg, g = wg % a.n_rg;
-  const int64_t col0 = ct * a.ct_w;
-  const int nct = (int)min((int64_t)a.ct_w, a.ncols - col0);
-
-  // stage the column tile's V^T items in LDS
-  {
-    const V* src = reinterpret_cast<const V*>(static_cast<const real*>(a.V) + col0 * RRP);
-    V* dst = reinterpret_cast<V*>(Vs);
-    const int n = nct * NV;
-    for (int i = threadIdx.x; i < n; i += kPassThreads) dst[i] = src[i];
-  }
-  __syncthreads();
+  const int64_t cg = wg / a.n_rg, g = wg % a.n_rg;
+  const int64_t ct_beg = cg * a.cpg;
+  const int64_t ct_end = min((int64_t)a.n_ct, ct_beg + a.cpg);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t sid = wg * 4 + wave;
-  const int64_t off = a.slice_off[sid];
-  const int len = a.slice_len[sid];
   const int64_t row = g * kRowsPerWG + threadIdx.x;
   const bool row_ok = row < a.nrows;
 
@@ -81,7 +80,7 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
   for (int j = 0; j < RRP; ++j) t[j] = real(0);
 #pragma unroll
   for (int j = 0; j < (int)(sizeof(u) / sizeof(real)); ++j) u[j] = real(0);
-  if (row_ok && len > 0) {
+  if (row_ok) {
     const V* tp = reinterpret_cast<const V*>(static_cast<const real*>(a.T) + row * RRP);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -104,14 +103,29 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
 
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   real f0 = real(0);  // per-lane line-search sum (converted to double once per lane)
+  constexpr int kGroupStride = kWave * kGroup;
+  for (int64_t ct = ct_beg; ct < ct_end; ++ct) {
+  const int64_t col0 = ct * a.ct_w;
+  const int nct = (int)min((int64_t)a.ct_w, a.ncols - col0);
+  if (ct > ct_beg) __syncthreads();  // every wave is done with the previous tile
+  // stage the column tile's V^T items in LDS
+  {
+    const V* src = reinterpret_cast<const V*>(static_cast<const real*>(a.V) + col0 * RRP);
+    V* dst = reinterpret_cast<V*>(Vs);
+    const int n = nct * NV;
+    for (int i = threadIdx.x; i < n; i += kPassThreads) dst[(i / NV) * NVS + i % NV] = src[i];
+  }
+  __syncthreads();
+  const int64_t sid = (ct * a.n_rg + g) * 4 + wave;
+  const int64_t off = a.slice_off[sid];
+  const int len = a.slice_len[sid];
   // this lane's entries: groups of kGroup values / columns, one wide load each
   const real* __restrict__ vbase = static_cast<const real*>(a.vals) + off + lane * kGroup;
   const uint16_t* __restrict__ cbase = a.cols + off + lane * kGroup;
-  constexpr int kGroupStride = kWave * kGroup;
   const int ngroups = len / kGroup;
 
   auto process = [&](const real x, const int c, const int64_t slot) {
-    const V* vp = reinterpret_cast<const V*>(Vs + c * RRP);
+    const V* vp = reinterpret_cast<const V*>(Vs + c * SP);
     real vr[kHoldV ? RRP : 1];
     real xh0 = real(0), xh1 = real(0);
     real q0 = real(0), q1 = real(0);
@@ -199,12 +213,13 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
     }
     cur = nxt;
   }
+  }  // column tiles
 
   if constexpr (MODE == kModeLS) s0 = (double)f0;
   if constexpr (kGrad) {
-    // per-column-tile partial of the row factor, plain stores (summed in fixed order later)
+    // per-column-group partial of the row factor, plain stores (summed in fixed order later)
     if (row_ok) {
-      V* sp = reinterpret_cast<V*>(static_cast<real*>(a.S) + (ct * a.nrows + row) * RRP);
+      V* sp = reinterpret_cast<V*>(static_cast<real*>(a.S) + (cg * a.nrows + row) * RRP);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         V q;
@@ -259,7 +274,7 @@ int64_t pass_ct_w(int dtype, int prec, int RRP) {
   // LDS budget of the column tile: two work-groups per CU when the device allows it
   int64_t budget = g_lds_max >= 2 * 65536 ? 65536 : 61440;
   if (budget > g_lds_max - 1024) budget = g_lds_max - 1024;
-  int64_t w = budget / (RRP * bytes);
+  int64_t w = budget / (lds_item_stride(RRP, (int)bytes) * bytes);
   if (w < 1) w = 1;
   if (w > 65535) w = 65535;
   return w;
@@ -268,8 +283,8 @@ int64_t pass_ct_w(int dtype, int prec, int RRP) {
 template <typename real, int RC>
 static hipError_t launch_rc(int mode, const PassArgs& a, hipStream_t st) {
   constexpr int RRP = (RC + 3) / 4 * 4;
-  const int64_t nwg = a.n_rg * a.n_ct;
-  const size_t lds = (size_t)a.ct_w * RRP * sizeof(real);
+  const int64_t nwg = a.n_rg * a.n_cg;
+  const size_t lds = (size_t)a.ct_w * lds_item_stride(RRP, (int)sizeof(real)) * sizeof(real);
   dim3 g((unsigned)nwg), b(kPassThreads);
   switch (mode) {
     case kModeGrad: hipLaunchKernelGGL((k_pass<real, RC, kModeGrad>), g, b, lds, st, a); break;
@@ -295,8 +310,10 @@ static hipError_t launch_real(int mode, const PassArgs& a, hipStream_t st) {
 
 hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st) {
   (void)prec;
-  if (a.n_rg * a.n_ct <= 0) return hipSuccess;
+  if (a.n_rg * a.n_cg <= 0) return hipSuccess;
   if (pass_rrp(a.RR) != a.RRP) return hipErrorInvalidValue;
+  if (a.cpg < 1 || (int64_t)a.n_cg * a.cpg < a.n_ct || (int64_t)(a.n_cg - 1) * a.cpg >= a.n_ct)
+    return hipErrorInvalidValue;
   return dtype == 0 ? launch_real<float>(mode, a, st) : launch_real<double>(mode, a, st);
 }
 

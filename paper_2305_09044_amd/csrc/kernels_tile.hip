@@ -1,25 +1,25 @@
 // Matrix-core (MFMA) form of the fused entry passes: the BF16 precision form.
 //
 // The observed entries of a core-k matrix (rows = (i_k, first subchain modes), cols =
-// the rest) are stored as bitmask tiles: one 32-bit mask per (64-row x 32-column block,
-// lane) plus the observed values of the block, compacted in (lane, bit) order.  Lane l,
-// bit b = 16 n + v of a block covers
-//     row = 64 rb + 32 n + l % 32,
-//     col = 32 ch + 8 (v / 4) + 4 (l / 32) + v % 4,
-// which is exactly where the 32x32 MFMA output register v of n-tile n of lane l lands
-// when the reconstruction is computed transposed:
-//     Xhat^T (32 cols x 64 rows) = V^T-items (32 x K) . T-items^T (K x 64)    (Thm. 1)
-// so each lane finds xhat of its own positions in its own accumulators.  With the same
-// k ordering, the weighted residuals y = w e of a lane are already the B operand of
-//     S^T (K x 64 rows) += V^T-items^T (K x 32 cols) . Y^T (32 cols x 64 rows)  (eq. 9)
-// so no transpose through LDS is needed.  V^T items are bf16; products accumulate in
-// FP32; e, w, y are FP32 (y is rounded to bf16 as an MFMA operand).
+// the rest) are grouped in blocks of 64 rows x 32 columns.  A block stores its observed
+// values and their in-block positions p = 32 r + c (r < 64, c < 32), in increasing p.
+// One wave owns a 64-row block row and walks its blocks (32-column chunks):
+//   1. Xhat^T (32 cols x 64 rows) = V^T-items (32 x K) . T-items^T (K x 64) on the
+//      matrix cores (Thm. 1): bf16 operands, FP32 accumulation, spilled to LDS;
+//   2. each observed entry of the block (lane-parallel, in value order) reads its xhat,
+//      forms e = x - xhat, w = exp(-e^2/2s^2) (eq. 7) and y = w e in FP32, and scatters
+//      y (rounded to bf16) into a cleared 64 x 32 tile in LDS;
+//   3. S^T (K x 64 rows) += V^T-items^T (K x 32 cols) . Y^T (32 cols x 64 rows) on the
+//      matrix cores: the row factor of the gradient of eq. 9.
+// Matrix-core work covers every position of a block; vector work is per observed entry.
+// A work-group (4 waves = 4 block rows) walks a group of column tiles and keeps its S
+// accumulators in registers; the V^T items of the current tile are staged transposed in
+// LDS as the A operand of step 3.
 #include "trd_internal.h"
 
 namespace trd {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 static int grid_for(int64_t n, int threads, int64_t cap = 1 << 20) {
@@ -34,11 +34,11 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even (f
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// position (row offset in block, column offset in block) of lane l, bit b
-__host__ __device__ inline void tile_pos(int l, int b, int& r, int& c) {
-  const int n = b >> 4, v = b & 15;
-  r = 32 * n + (l & 31);
-  c = 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+// order LDS accesses among the lanes of one wave (the tiles below are per wave)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------- layout builder
@@ -46,49 +46,59 @@ __host__ __device__ inline void tile_pos(int l, int b, int& r, int& c) {
 struct TileArgs {
   const int64_t* rowoff;
   const int64_t* coloff;
-  uint32_t* masks;
   int32_t* bcnt;
-  int64_t* boff;
-  int64_t* total;
-  int64_t nrows, ncols, n_rbp, n_blocks;
-  int CW, n_ch;
+  const int64_t* boff;
+  float* vals;
+  uint16_t* pos;
+  int64_t nrows, ncols, n_chunks, n_blocks;
 };
 
 static TileArgs targs(const TLayout& L) {
   TileArgs a;
-  a.rowoff = L.rowoff; a.coloff = L.coloff; a.masks = L.masks; a.bcnt = L.bcnt; a.boff = L.boff;
-  a.total = L.total_dev; a.nrows = L.nrows; a.ncols = L.ncols; a.n_rbp = L.n_rg * 4;
-  a.n_blocks = L.n_blocks; a.CW = L.CW; a.n_ch = L.n_ch;
+  a.rowoff = L.rowoff; a.coloff = L.coloff; a.bcnt = L.bcnt; a.boff = L.boff;
+  a.vals = L.vals; a.pos = L.pos;
+  a.nrows = L.nrows; a.ncols = L.ncols; a.n_chunks = L.n_chunks; a.n_blocks = L.n_blocks;
   return a;
 }
 
-// block id = ((ct * n_rbp) + rb) * n_ch + ch; one wave per block
-__device__ inline void block_coords(const TileArgs& a, int64_t b, int64_t& ct, int64_t& rb, int64_t& ch) {
-  ch = b % a.n_ch;
-  const int64_t t = b / a.n_ch;
-  rb = t % a.n_rbp;
-  ct = t / a.n_rbp;
-}
-
-__global__ __launch_bounds__(256) void k_tmask(TileArgs a, const uint8_t* __restrict__ mask) {
+// Block b = rb * n_chunks + ch, one wave per block.  Round t covers positions
+// p = 64 t + lane (row 2 t + lane / 32, column lane % 32), so the ballot of a round lists
+// its observed entries in increasing p.  Count pass (FILL = false): per-block counts;
+// fill pass: values and positions at boff[b] onwards.
+template <typename real, bool FILL>
+__global__ __launch_bounds__(256) void k_tblock(TileArgs a, const uint8_t* __restrict__ mask,
+                                                const real* __restrict__ X) {
   const int64_t b = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int l = threadIdx.x & 63;
-  if (b >= a.n_blocks) return;
-  int64_t ct, rb, ch;
-  block_coords(a, b, ct, rb, ch);
-  const int64_t col_lim = min(a.ncols, (ct + 1) * (int64_t)a.CW);
-  uint32_t m = 0;
-#pragma unroll 4
-  for (int bit = 0; bit < 32; ++bit) {
-    int r, c;
-    tile_pos(l, bit, r, c);
-    const int64_t row = rb * 64 + r, col = ct * (int64_t)a.CW + ch * 32 + c;
-    if (row < a.nrows && col < col_lim && mask[a.rowoff[row] + a.coloff[col]]) m |= 1u << bit;
+  if (b >= a.n_blocks) return;  // b is uniform over the wave
+  const int64_t rb = b / a.n_chunks, ch = b % a.n_chunks;
+  const int64_t col = ch * 32 + (l & 31);
+  const bool col_ok = col < a.ncols;
+  const int64_t co = col_ok ? a.coloff[col] : 0;
+  int64_t out = FILL ? a.boff[b] : 0;
+  int cnt = 0;
+  for (int t = 0; t < 32; ++t) {
+    const int p = 64 * t + l;
+    const int64_t row = rb * 64 + (p >> 5);
+    bool obs = false;
+    int64_t off = 0;
+    if (col_ok && row < a.nrows) {
+      off = a.rowoff[row] + co;
+      obs = mask[off] != 0;
+    }
+    const uint64_t bal = __ballot(obs);
+    if constexpr (FILL) {
+      if (obs) {
+        const int pre = __popcll(bal & ((1ull << l) - 1ull));
+        a.vals[out + pre] = (float)X[off];
+        a.pos[out + pre] = (uint16_t)p;
+      }
+      out += __popcll(bal);
+    } else {
+      cnt += __popcll(bal);
+    }
   }
-  a.masks[b * 64 + l] = m;
-  int cnt = __popc(m);
-  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-  if (l == 0) a.bcnt[b] = cnt;
+  if (!FILL && l == 0) a.bcnt[b] = cnt;
 }
 
 // exclusive scan of int32 counts into int64 offsets (one work-group, fixed order)
@@ -120,55 +130,20 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t* __restrict_
   }
 }
 
-// order LDS accesses among the lanes of one wave (the staging area is per wave)
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int wave_excl_scan(int v, int l, int* total) {
-  int incl = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(incl, o);
-    if (l >= o) incl += t;
-  }
-  *total = __shfl(incl, 63);
-  return incl - v;
-}
-
-template <typename real>
-__global__ __launch_bounds__(256) void k_tfill(TileArgs a, const real* __restrict__ X,
-                                               float* __restrict__ vals) {
-  const int64_t b = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  const int l = threadIdx.x & 63;
-  if (b >= a.n_blocks) return;
-  int64_t ct, rb, ch;
-  block_coords(a, b, ct, rb, ch);
-  const uint32_t m = a.masks[b * 64 + l];
-  int total;
-  const int pre = wave_excl_scan(__popc(m), l, &total);
-  int64_t p = a.boff[b] + pre;
-  for (int bit = 0; bit < 32; ++bit) {
-    if (!((m >> bit) & 1u)) continue;
-    int r, c;
-    tile_pos(l, bit, r, c);
-    const int64_t row = rb * 64 + r, col = ct * (int64_t)a.CW + ch * 32 + c;
-    vals[p++] = (float)X[a.rowoff[row] + a.coloff[col]];
-  }
-}
-
 hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* X, int dtype,
                              bool fill, hipStream_t st) {
   const unsigned nb = (unsigned)((L.n_blocks + 3) / 4);
   if (!fill) {
-    hipLaunchKernelGGL(k_tmask, dim3(nb), dim3(256), 0, st, targs(L), mask);
+    hipLaunchKernelGGL((k_tblock<float, false>), dim3(nb), dim3(256), 0, st, targs(L), mask,
+                       (const float*)nullptr);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, L.bcnt, L.n_blocks, L.boff,
                        L.total_dev);
   } else if (dtype == 0) {
-    hipLaunchKernelGGL(k_tfill<float>, dim3(nb), dim3(256), 0, st, targs(L), (const float*)X, L.vals);
+    hipLaunchKernelGGL((k_tblock<float, true>), dim3(nb), dim3(256), 0, st, targs(L), mask,
+                       (const float*)X);
   } else {
-    hipLaunchKernelGGL(k_tfill<double>, dim3(nb), dim3(256), 0, st, targs(L), (const double*)X, L.vals);
+    hipLaunchKernelGGL((k_tblock<double, true>), dim3(nb), dim3(256), 0, st, targs(L), mask,
+                       (const double*)X);
   }
   return hipGetLastError();
 }
@@ -195,36 +170,53 @@ hipError_t launch_table_bf16(const float* in, int64_t n, int in_stride, int K, u
 
 // ---------------------------------------------------------------- the MFMA pass
 
+// Per-wave LDS tiles.  Row strides are odd multiples of 16 bytes, so the 16-byte accesses
+// of eight consecutive rows by eight lanes fall in distinct banks.
+constexpr int kXS = 36;                 // f32 stride of the xhat (and q) tile
+constexpr int kYS = 40;                 // bf16 stride of the y tile
+constexpr int kXTile = 64 * kXS;        // floats
+constexpr int kYTile = 64 * kYS;        // bf16
+constexpr int kXBytes = 4 * kXTile * 4; // four waves
+constexpr int kYBytes = 4 * kYTile * 2;
+
+template <int K> struct TileRounds { static constexpr int v = K <= 32 ? 12 : (K <= 64 ? 8 : 4); };
+
+size_t tpass_lds(int mode, int K, int CW) {
+  if (mode == kModeGrad || mode == kModeGradFast)
+    return (size_t)kXBytes + kYBytes + (size_t)K * (CW + 8) * 2;
+  if (mode == kModeLS) return 2 * (size_t)kXBytes;
+  return (size_t)kXBytes;
+}
+
 template <int K, int MODE>
-__global__ __launch_bounds__(256, 2) void k_tpass(TPassArgs a) {
+__global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   constexpr int KS = K / 16;       // k-steps of the reconstruction MFMA
   constexpr int MT = K / 32;       // m-tiles of the gradient MFMA
+  constexpr int kR = TileRounds<K>::v;  // entry rounds of 64 held in registers per chunk
   constexpr bool kGrad = MODE == kModeGrad || MODE == kModeGradFast;
+  constexpr bool kLS = MODE == kModeLS;
   constexpr bool kStats = MODE == kModeGrad || MODE == kModeLoss;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int CWP = a.CW + 8;
-  uint16_t* Vc = reinterpret_cast<uint16_t*>(smem_raw);                        // [K][CWP]
-  float* stage = reinterpret_cast<float*>(smem_raw + (size_t)K * CWP * 2);     // [4][2048]
+  // the wave index is uniform over the wave: keep it (and everything derived from it:
+  // block row, block offsets, loop bounds) in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = threadIdx.x & 63, h = l >> 5, li = l & 31;
+  float* Xs = reinterpret_cast<float*>(smem_raw) + w * kXTile;
+  float* Qs = reinterpret_cast<float*>(smem_raw + kXBytes) + w * kXTile;             // LS
+  uint16_t* Ys = reinterpret_cast<uint16_t*>(smem_raw + kXBytes) + w * kYTile;       // grad
+  uint16_t* Vc = reinterpret_cast<uint16_t*>(smem_raw + kXBytes + kYBytes);          // grad
 
   const int64_t wg = blockIdx.x;
-  const int64_t ct = wg / a.n_rg, g = wg % a.n_rg;
-  const int64_t col0 = ct * (int64_t)a.CW;
-  const int nct = (int)min((int64_t)a.CW, a.ncols - col0);
-
-  // transposed column table of this tile: Vc[j][c] = V^T-item(col0 + c)[j]
-  for (int i = threadIdx.x; i < a.CW * K; i += 256) {
-    const int c = i / K, j = i % K;
-    Vc[j * CWP + c] = c < nct ? a.V[(col0 + c) * K + j] : (uint16_t)0;
-  }
-  __syncthreads();
-
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, h = l >> 5, li = l & 31;
+  const int64_t cg = wg / a.n_rg, g = wg % a.n_rg;
   const int64_t rb = g * 4 + w;
-  float* st = stage + w * 2048;
+  const bool rb_ok = rb < a.n_rb;
+  const int64_t gc_beg = cg * (int64_t)a.cpg * a.n_chpt;
+  const int64_t gc_end = min(a.n_chunks, gc_beg + (int64_t)a.cpg * a.n_chpt);
 
   // B operand of the reconstruction: this wave's 64 T items (and TH for the line search)
   bf16x8 tb[2][KS];
-  bf16x8 thb[(MODE == kModeLS) ? 2 : 1][(MODE == kModeLS) ? KS : 1];
+  bf16x8 thb[kLS ? 2 : 1][kLS ? KS : 1];
 #pragma unroll
   for (int n = 0; n < 2; ++n) {
     const int64_t row = rb * 64 + 32 * n + li;
@@ -234,7 +226,7 @@ __global__ __launch_bounds__(256, 2) void k_tpass(TPassArgs a) {
       tb[n][s] = z;
       if (row < a.nrows)
         tb[n][s] = *reinterpret_cast<const bf16x8*>(a.T + row * K + s * 16 + h * 8);
-      if constexpr (MODE == kModeLS) {
+      if constexpr (kLS) {
         thb[n][s] = z;
         if (row < a.nrows)
           thb[n][s] = *reinterpret_cast<const bf16x8*>(a.TH + row * K + s * 16 + h * 8);
@@ -246,6 +238,7 @@ __global__ __launch_bounds__(256, 2) void k_tpass(TPassArgs a) {
   const bool ls_limit = isinf(sig);
   const float inv2s2 = ls_limit ? 0.f : (float)(0.5 / (sig * sig));
   const float sig2 = ls_limit ? 0.f : (float)(sig * sig);
+  const float k2 = inv2s2 * 1.4426950408889634f;  // exp(-u) = 2^(-u log2 e)
 
   floatx16 sacc[kGrad ? MT : 1][kGrad ? 2 : 1];
   if constexpr (kGrad) {
@@ -256,137 +249,198 @@ __global__ __launch_bounds__(256, 2) void k_tpass(TPassArgs a) {
   }
   float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 
-  // software pipeline over the tile's 32-column chunks: masks / block offsets two chunks
-  // ahead, the next chunk's values and V^T-item operands one chunk ahead (registers)
-  constexpr int kPV = 16;  // values per lane prefetched per chunk (1024 per wave)
-  const float k2 = inv2s2 * 1.4426950408889634f;  // exp(-u) = 2^(-u log2 e)
-  const int64_t bbase = (ct * a.n_rbp + rb) * a.n_ch;
-  const int nch = a.n_ch;
-  uint32_t m_cur = a.masks[bbase * 64 + l];
-  uint32_t m_nxt = nch > 1 ? a.masks[(bbase + 1) * 64 + l] : 0u;
-  int64_t bo_cur = a.boff[bbase], bo_nxt = a.boff[bbase + 1];
-  int64_t bo_nxt2 = nch > 1 ? a.boff[bbase + 2] : bo_nxt;
-  // The value array and the bf16 column table are allocated with slack (>= 1024 floats,
-  // >= CW items) so these prefetches never need a bounds branch; slots past a chunk's
-  // values are never selected, and column items past the tile are finite.
-  float pv[kPV];
-#pragma unroll
-  for (int i = 0; i < kPV; ++i) pv[i] = a.vals[bo_cur + l + 64 * i];
-  bf16x8 av[KS];
-#pragma unroll
-  for (int s = 0; s < KS; ++s)
-    av[s] = *reinterpret_cast<const bf16x8*>(a.V + (col0 + li) * K + s * 16 + h * 8);
+  // one observed entry: x, in-block position p; `valid` false for lanes past the block's
+  // entries (their p is masked into the tile, their y goes to the tile's padding column
+  // and their sums are dropped).  No branches, so a group of rounds issues its LDS reads
+  // together.  In the least-squares limit k2 = 0 and the weight is exactly 1.
+  auto entry = [&](float x, uint32_t p, bool valid, int64_t idx) {
+    p &= 2047u;
+    const int r = (int)(p >> 5), c = (int)(p & 31u);
+    const float xh = Xs[r * kXS + c];
+    const float e = x - xh;
+    const float wgt = __builtin_amdgcn_exp2f(-(e * e * k2));
+    if constexpr (kGrad)
+      Ys[r * kYS + (valid ? c : 32)] = __builtin_bit_cast(uint16_t, (__bf16)(wgt * e));
+    if constexpr (kLS) {
+      const float q = Qs[r * kXS + c];
+      f0 = fmaf(valid ? wgt * q : 0.f, q, f0);
+    }
+    if constexpr (MODE == kModeResid) {
+      if (valid) a.resid[idx] = fabsf(e);
+    }
+    if constexpr (kStats) {
+      const float uu = e * e * inv2s2;
+      // sigma^2 (1 - exp(-u)), by its series at small u (no cancellation)
+      float q = fmaf(uu, 1.0f / 120.0f, -1.0f / 24.0f);
+      q = fmaf(uu, q, 1.0f / 6.0f);
+      q = fmaf(uu, q, -0.5f);
+      q = fmaf(uu, q, 1.0f);
+      float lo = uu < 0.0625f ? sig2 * uu * q : sig2 * (1.f - wgt);
+      if (ls_limit) lo = 0.5f * e * e;
+      f0 += valid ? lo : 0.f;
+      f1 += valid ? wgt * e * e : 0.f;
+      f2 += valid ? 1.f : 0.f;
+    }
+  };
 
-  for (int ch = 0; ch < nch; ++ch) {
-    const int total = (int)(bo_nxt - bo_cur);
-    // stage this chunk's values (registers, plus a direct copy of any overflow)
+  // Software pipeline over the chunks, unrolled by two so that the two register sets
+  // swap roles without copies: at the top of a chunk the next chunk's entries and
+  // V^T-item operands are loaded into the idle set, so they have a whole chunk to
+  // arrive.  The value / position arrays and the bf16 column table carry slack
+  // (>= 64 kR + 64 entries, >= 64 items) and the offset index is clamped to the walk, so
+  // these loads need no bounds branch; what they read past a block's end is never used.
+  struct Set {
+    float x[kR];
+    uint32_t p[kR];
+    bf16x8 av[KS];
+  };
+  const int64_t bb = rb * a.n_chunks;
+  auto load_set = [&](Set& S, int64_t gc, int64_t bo) {
 #pragma unroll
-    for (int i = 0; i < kPV; ++i) st[l + 64 * i] = pv[i];
-    for (int i = l + 64 * kPV; i < total; i += 64) st[i] = a.vals[bo_cur + i];
-    // Xhat^T (and Q^T) for the 32 columns of this chunk
+    for (int t = 0; t < kR; ++t) {
+      S.x[t] = a.vals[bo + 64 * t + l];
+      S.p[t] = a.pos[bo + 64 * t + l];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      S.av[s] = *reinterpret_cast<const bf16x8*>(a.V + (gc * 32 + li) * K + s * 16 + h * 8);
+  };
+
+  constexpr int KV = K / 8;  // 16-byte vectors per table item
+  // [bo_cur, bo_end): entries of the current chunk; bo_nend: end of the next one
+  int64_t bo_cur = 0, bo_end = 0, bo_nend = 0;
+  auto step = [&](int64_t gc, const Set& C, Set& N) {
+    const int cc = (int)((gc - gc_beg) % a.n_chpt);  // chunk inside the current tile
+    if constexpr (kGrad) {
+      if (cc == 0) {  // new column tile: every wave is past the old one, restage V^T items
+        __syncthreads();
+        const int64_t col0 = gc * 32;
+        const int nct = (int)min((int64_t)a.CW, a.ncols - col0);
+        const int nvec = a.CW * KV;
+        for (int i0 = 0; i0 < nvec; i0 += 4 * 256) {
+          uint4 buf[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 256 * u + threadIdx.x;
+            const int c = i % a.CW, jv = i / a.CW;
+            buf[u] = uint4{0u, 0u, 0u, 0u};
+            if (i < nvec && c < nct)
+              buf[u] = *reinterpret_cast<const uint4*>(a.V + (col0 + c) * K + 8 * jv);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 256 * u + threadIdx.x;
+            if (i < nvec) {
+              const int c = i % a.CW, jv = i / a.CW;
+              const uint32_t wv[4] = {buf[u].x, buf[u].y, buf[u].z, buf[u].w};
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                Vc[(8 * jv + e) * CWP + c] = (uint16_t)(wv[e >> 1] >> ((e & 1) * 16));
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (!rb_ok) return;  // uniform over the wave; it still joins every tile barrier
+
+    // prefetch the next chunk (index gc + 1 <= n_chunks, offset bo_end <= nobs)
+    load_set(N, gc + 1, bo_end);
+    const int64_t bo_nn = a.boff[bb + min(gc + 3, gc_end)];
+
+    // 1. Xhat^T (and Q^T) of this chunk
     floatx16 xacc[2] = {floatx16{}, floatx16{}};
-    floatx16 qacc[(MODE == kModeLS) ? 2 : 1];
-    if constexpr (MODE == kModeLS) { qacc[0] = floatx16{}; qacc[1] = floatx16{}; }
+    floatx16 qacc[kLS ? 2 : 1];
+    if constexpr (kLS) { qacc[0] = floatx16{}; qacc[1] = floatx16{}; }
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
-        xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], tb[n][s], xacc[n], 0, 0, 0);
-        if constexpr (MODE == kModeLS)
-          qacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], thb[n][s], qacc[n], 0, 0, 0);
+        xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(C.av[s], tb[n][s], xacc[n], 0, 0, 0);
+        if constexpr (kLS)
+          qacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(C.av[s], thb[n][s], qacc[n], 0, 0, 0);
       }
     }
-    // prefetch the next chunk
-    uint32_t m_nn = 0u;
-    int64_t bo_nn = bo_nxt2;
-    if (ch + 1 < nch) {
-#pragma unroll
-      for (int i = 0; i < kPV; ++i) pv[i] = a.vals[bo_nxt + l + 64 * i];
-      const int c = (ch + 1) * 32 + li;
-#pragma unroll
-      for (int s = 0; s < KS; ++s)
-        av[s] = *reinterpret_cast<const bf16x8*>(a.V + (col0 + c) * K + s * 16 + h * 8);
-      if (ch + 2 < nch) {
-        m_nn = a.masks[(bbase + ch + 2) * 64 + l];
-        bo_nn = a.boff[bbase + ch + 3];
-      }
-    }
-    const uint32_t m = m_cur;
-    int wtot;
-    const int pre = wave_excl_scan(__popc(m), l, &wtot);
-    const int64_t boff = bo_cur;
-    wave_sync();  // staged values of this wave visible to all its lanes
 
-    bf16x8 yv[kGrad ? 2 : 1][kGrad ? 2 : 1];  // [n][s2]: y of registers v = 8 s2 .. 8 s2 + 7
+    // 2. spill Xhat (and Q) to LDS as [row][col]; clear the y tile
+    // accumulator v of n-tile n: col 8 (v/4) + 4 h + v%4, row 32 n + li
 #pragma unroll
     for (int n = 0; n < 2; ++n) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int bit = n * 16 + v;
-        const bool obs = (m >> bit) & 1u;
-        const float xh = xacc[n][v];
-        float x = xh;
-        // idx <= this wave's value count <= 2048: the read is always in the staging area,
-        // so it is issued unconditionally and the result selected
-        const int idx = pre + __popc(m & ((1u << bit) - 1u));
-        const float ld = st[idx];
-        if (obs) x = ld;
-        const float e = x - xh;
-        const float uu = e * e * inv2s2;
-        const float wgt = ls_limit ? 1.f : __builtin_amdgcn_exp2f(-(e * e * k2));
-        if constexpr (kGrad) yv[n][v >> 3][v & 7] = (__bf16)(wgt * e);
-        if constexpr (MODE == kModeLS) {
-          const float q = qacc[n][v];
-          f0 = fmaf(obs ? wgt * q : 0.f, q, f0);
-        }
-        if constexpr (MODE == kModeResid) {
-          if (obs) a.resid[boff + idx] = fabsf(e);
-        }
-        if constexpr (kStats) {
-          if (obs) {
-            float lo;
-            if (ls_limit) lo = 0.5f * e * e;
-            else if (uu < 0.0625f) {
-              float p = fmaf(uu, 1.0f / 120.0f, -1.0f / 24.0f);
-              p = fmaf(uu, p, 1.0f / 6.0f);
-              p = fmaf(uu, p, -0.5f);
-              p = fmaf(uu, p, 1.0f);
-              lo = sig2 * uu * p;
-            } else {
-              lo = sig2 * (1.f - wgt);
-            }
-            f0 += lo;
-            f1 = fmaf(wgt * e, e, f1);
-            f2 += 1.f;
-          }
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const float4 xv = {xacc[n][4 * q4], xacc[n][4 * q4 + 1], xacc[n][4 * q4 + 2],
+                           xacc[n][4 * q4 + 3]};
+        *reinterpret_cast<float4*>(Xs + (32 * n + li) * kXS + 8 * q4 + 4 * h) = xv;
+        if constexpr (kLS) {
+          const float4 qv = {qacc[n][4 * q4], qacc[n][4 * q4 + 1], qacc[n][4 * q4 + 2],
+                             qacc[n][4 * q4 + 3]};
+          *reinterpret_cast<float4*>(Qs + (32 * n + li) * kXS + 8 * q4 + 4 * h) = qv;
         }
       }
     }
-
     if constexpr (kGrad) {
-      // S^T += V^T-items^T . Y^T; k slots of step s2: columns 16 s2 + 4h + {0..3} and
-      // 16 s2 + 8 + 4h + {0..3}, i.e. this lane's y registers v = 8 s2 .. 8 s2 + 7
+      uint4* yz = reinterpret_cast<uint4*>(Ys);
+#pragma unroll
+      for (int i = 0; i < kYTile * 2 / 16 / 64; ++i) yz[l + 64 * i] = uint4{0u, 0u, 0u, 0u};
+    }
+    wave_sync();
+
+    // 3. the observed entries of the block, four rounds of 64 at a time
+    const int nent = (int)(bo_end - bo_cur);
+#pragma unroll
+    for (int t0 = 0; t0 < kR; t0 += 4) {
+      if (64 * t0 < nent) {
+#pragma unroll
+        for (int t = t0; t < t0 + 4; ++t) {
+          const int i = 64 * t + l;
+          entry(C.x[t], C.p[t], i < nent, bo_cur + i);
+        }
+      }
+    }
+    for (int i0 = 64 * kR; i0 < nent; i0 += 64) {  // dense blocks: remaining rounds
+      const int i = i0 + l;
+      const bool valid = i < nent;
+      const float x = valid ? a.vals[bo_cur + i] : 0.f;
+      const uint32_t p = valid ? (uint32_t)a.pos[bo_cur + i] : 0u;
+      entry(x, p, valid, bo_cur + i);
+    }
+    wave_sync();
+
+    // 4. S^T += V^T-items^T . Y^T over the chunk's 32 columns (two k-steps of 16)
+    if constexpr (kGrad) {
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2) {
+        bf16x8 yb[2];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+          yb[n] = *reinterpret_cast<const bf16x8*>(Ys + (32 * n + li) * kYS + 16 * s2 + 8 * h);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const int j = mt * 32 + li;
-          const int cbase = ch * 32 + 16 * s2 + 4 * h;
-          const bf16x4 lo = *reinterpret_cast<const bf16x4*>(Vc + j * CWP + cbase);
-          const bf16x4 hi = *reinterpret_cast<const bf16x4*>(Vc + j * CWP + cbase + 8);
-          const bf16x8 aw = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+          const bf16x8 aw = *reinterpret_cast<const bf16x8*>(Vc + (32 * mt + li) * CWP + cc * 32 +
+                                                             16 * s2 + 8 * h);
 #pragma unroll
           for (int n = 0; n < 2; ++n)
-            sacc[mt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, yv[n][s2], sacc[mt][n], 0, 0, 0);
+            sacc[mt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, yb[n], sacc[mt][n], 0, 0, 0);
         }
       }
     }
-    wave_sync();  // all lanes done with the staging area before the next chunk refills it
-    m_cur = m_nxt;
-    m_nxt = m_nn;
-    bo_cur = bo_nxt;
-    bo_nxt = bo_nxt2;
-    bo_nxt2 = bo_nn;
+    wave_sync();  // tile reads done before the next chunk overwrites them
+
+    bo_cur = bo_end;
+    bo_end = bo_nend;
+    bo_nend = bo_nn;
+  };
+
+  Set A, B;
+  if (rb_ok && gc_beg < gc_end) {
+    bo_cur = a.boff[bb + gc_beg];
+    bo_end = a.boff[bb + gc_beg + 1];
+    bo_nend = a.boff[bb + min(gc_beg + 2, gc_end)];
+    load_set(A, gc_beg, bo_cur);
+  }
+  for (int64_t gc = gc_beg; gc < gc_end; gc += 2) {
+    step(gc, A, B);
+    if (gc + 1 < gc_end) step(gc + 1, B, A);
   }
 
   if constexpr (kGrad) {
@@ -395,7 +449,7 @@ __global__ __launch_bounds__(256, 2) void k_tpass(TPassArgs a) {
     for (int n = 0; n < 2; ++n) {
       const int64_t row = rb * 64 + 32 * n + li;
       if (row >= a.nrows) continue;
-      float* sp = a.S + (ct * a.nrows + row) * a.RRP;
+      float* sp = a.S + (cg * a.nrows + row) * a.RRP;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -427,11 +481,11 @@ __global__ __launch_bounds__(256, 2) void k_tpass(TPassArgs a) {
 
 int tile_k(int RR) { return (RR + 31) / 32 * 32; }
 
+// column-tile width of the gradient pass: the bf16 V^T tile fills what the per-wave
+// tiles leave of half the CU's LDS (two work-groups per CU)
 int64_t tile_cw(int K) {
-  // LDS: K x (CW + 8) bf16 column table + 4 x 2048 floats of staging; two groups per CU
-  int64_t budget = g_lds_max >= 2 * 65536 ? 65536 : 61440;
-  if (budget > g_lds_max - 1024) budget = g_lds_max - 1024;
-  int64_t cw = (budget - 4 * 2048 * 4) / (2 * K) - 8;
+  int64_t budget = g_lds_max >= 2 * 81920 ? 81920 - 1024 : g_lds_max - 1024;
+  int64_t cw = (budget - kXBytes - kYBytes) / (2 * K) - 8;
   cw = cw / 32 * 32;
   if (cw < 32) cw = 32;
   return cw;
@@ -439,8 +493,9 @@ int64_t tile_cw(int K) {
 
 template <int K>
 static hipError_t launch_k(int mode, const TPassArgs& a, hipStream_t st) {
-  const int64_t nwg = a.n_rg * a.n_ct;
-  const size_t lds = (size_t)K * (a.CW + 8) * 2 + 4 * 2048 * 4;
+  const int64_t nwg = a.n_rg * a.n_cg;
+  const size_t lds = tpass_lds(mode, K, a.CW);
+  if ((int64_t)lds > g_lds_max) return hipErrorInvalidConfiguration;
   dim3 g((unsigned)nwg), b(256);
   switch (mode) {
     case kModeGrad: hipLaunchKernelGGL((k_tpass<K, kModeGrad>), g, b, lds, st, a); break;
@@ -453,7 +508,13 @@ static hipError_t launch_k(int mode, const TPassArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {
-  if (a.n_rg * a.n_ct <= 0) return hipSuccess;
+  if (a.n_rg * a.n_cg <= 0 || a.n_chunks <= 0) return hipSuccess;
+  // the grid and chunk walk must cover exactly the layout the pass indexes
+  if (a.CW % 32 != 0 || a.n_chpt != a.CW / 32 || a.cpg < 1 || a.n_rb > 4 * a.n_rg ||
+      (int64_t)a.n_cg * a.cpg * a.n_chpt < a.n_chunks ||
+      (int64_t)(a.n_cg - 1) * a.cpg * a.n_chpt >= a.n_chunks || a.n_chunks * 32 < a.ncols ||
+      a.n_rb * 64 < a.nrows || a.RRP > K)
+    return hipErrorInvalidValue;
   switch (K) {
     case 32: return launch_k<32>(mode, a, st);
     case 64: return launch_k<64>(mode, a, st);

@@ -14,6 +14,7 @@
 
 namespace trd {
 int64_t g_lds_max = 65536;
+int g_num_cu = 256;
 }
 
 using namespace trd;
@@ -156,8 +157,17 @@ int plan_split(trd_ctx* ctx, int k, const int64_t* counts, Split& sp, int64_t& n
     for (int t = p + 1; t <= N - 1; ++t) nc *= counts[(k + t) % N];
     const int64_t wmax = pass_ct_w(ctx->dtype, 0, RRP);
     const int64_t nct = (nc + wmax - 1) / wmax;
-    // bytes of the two tables plus the gradient accumulator traffic of the tiles
-    const double cost = (double)(nr + nc) * RRP * esz(ctx->dtype) + (double)nct * nr * RR * 4.0;
+    const int64_t nrg = (nr + kRowsPerWG - 1) / kRowsPerWG;
+    int ncg, cpg;
+    column_groups(nrg, (int)std::min<int64_t>(nct, 1 << 30), ncg, cpg);
+    // bytes: the two tables (written, then read), the gradient partials of the column
+    // groups (written, then read), and the column-table reads of every row group (from
+    // L2, weighted 1/4, when the column table fits a fraction of one XCD's L2)
+    const double esb = (double)esz(ctx->dtype);
+    const double vbytes = (double)nc * RRP * esb;
+    const double vw = vbytes <= 2.0 * (1 << 20) ? 0.25 : 1.0;
+    const double cost = 2.0 * (double)(nr + nc) * RRP * esb + 2.0 * (double)ncg * nr * RRP * esb +
+                        vw * (double)nrg * vbytes;
     if (bestp < 0 || cost < best) {
       best = cost;
       bestp = p;
@@ -193,6 +203,7 @@ void layout_dims(Layout& L, int64_t nrows, int64_t ncols, int ct_w, int n_ct) {
   L.n_ct = n_ct;
   L.n_rg = (nrows + kRowsPerWG - 1) / kRowsPerWG;
   L.n_slices = L.n_rg * n_ct * 4;
+  column_groups(L.n_rg, n_ct, L.n_cg, L.cpg);
 }
 
 ModeSet rows_set(trd_ctx* ctx, const Split& sp, const int64_t* counts, const int32_t* const* lists) {
@@ -387,24 +398,31 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   T.nrows = L.nrows;
   T.ncols = L.ncols;
   T.K = tile_k(sp.RR);
+  T.n_chunks = (T.ncols + 31) / 32;
   const int64_t cwmax = tile_cw(T.K);
-  T.n_ct = (int)((T.ncols + cwmax - 1) / cwmax);
-  T.CW = (int)(((T.ncols + T.n_ct - 1) / T.n_ct + 31) / 32 * 32);
-  T.n_ch = T.CW / 32;
-  T.n_rg = (T.nrows + kRowsPerWG - 1) / kRowsPerWG;
-  T.n_blocks = (int64_t)T.n_ct * T.n_rg * 4 * T.n_ch;
+  T.n_ct = (int)((T.n_chunks * 32 + cwmax - 1) / cwmax);
+  T.n_chpt = (int)((T.n_chunks + T.n_ct - 1) / T.n_ct);
+  T.CW = T.n_chpt * 32;
+  T.n_ct = (int)((T.n_chunks + T.n_chpt - 1) / T.n_chpt);
+  T.n_rb = (T.nrows + 63) / 64;
+  T.n_rg = (T.n_rb + 3) / 4;
+  column_groups(T.n_rg, T.n_ct, T.n_cg, T.cpg);
+  T.n_blocks = T.n_rb * T.n_chunks;
+  if ((int64_t)tpass_lds(kModeGradFast, T.K, T.CW) > g_lds_max)
+    return fail(ctx, TRD_EUNSUPPORTED, "matrix-core pass does not fit the device LDS");
   T.rowoff = L.rowoff;
   T.coloff = L.coloff;
-  TRY(alloc_n(ctx, &T.masks, T.n_blocks * 64));
   TRY(alloc_n(ctx, &T.bcnt, T.n_blocks));
   TRY(alloc_n(ctx, &T.boff, T.n_blocks + 1));
   TRY(alloc_n(ctx, &T.total_dev, 1));
   CK(launch_tile_build(T, ctx->mask, ctx->X, ctx->dtype, false, st));
   CK(hipMemcpyAsync(&T.nobs, T.total_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  // slack: the MFMA pass prefetches 1024 values per chunk without bounds branches
-  TRY(alloc_n(ctx, &T.vals, T.nobs + 2048));
-  CK(launch_zero(T.vals, (size_t)(T.nobs + 2048) * sizeof(float), st));
+  // slack: the pass prefetches up to 16 rounds of 64 entries without bounds branches
+  TRY(alloc_n(ctx, &T.vals, T.nobs + kTileSlack));
+  TRY(alloc_n(ctx, &T.pos, T.nobs + kTileSlack));
+  CK(launch_zero(T.vals, (size_t)(T.nobs + kTileSlack) * sizeof(float), st));
+  CK(launch_zero(T.pos, (size_t)(T.nobs + kTileSlack) * sizeof(uint16_t), st));
   CK(launch_tile_build(T, ctx->mask, ctx->X, ctx->dtype, true, st));
   T.ready = true;
   return TRD_OK;
@@ -541,12 +559,15 @@ PassArgs pass_args(trd_ctx* ctx, const Update& up) {
   a.RR = up.sp.RR;
   a.RRP = up.sp.RRP;
   a.n_ct = L.n_ct;
+  a.n_cg = L.n_cg;
+  a.cpg = L.cpg;
   return a;
 }
 
-int64_t n_wg(const Layout& L) { return L.n_rg * L.n_ct; }
-int64_t up_nwg(const Update& up) { return up.TL ? up.TL->n_rg * up.TL->n_ct : n_wg(*up.L); }
-int up_nct(const Update& up) { return up.TL ? up.TL->n_ct : up.L->n_ct; }
+int64_t n_wg(const Layout& L) { return L.n_rg * L.n_cg; }
+int64_t up_nwg(const Update& up) { return up.TL ? up.TL->n_rg * up.TL->n_cg : n_wg(*up.L); }
+// number of gradient partials of a pass (one per column group)
+int up_nct(const Update& up) { return up.TL ? up.TL->n_cg : up.L->n_cg; }
 const int64_t* up_nobs_dev(const Update& up) { return up.TL ? up.TL->total_dev : up.L->nobs_dev; }
 
 int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStream_t st) {
@@ -566,8 +587,9 @@ int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStr
   return TRD_OK;
 }
 
-// matrix-core pass: bf16 copies of the FP32 tables, then the MFMA kernel
-int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
+// matrix-core pass: bf16 copies of the FP32 tables (before the timed kernel), then the
+// MFMA kernel
+int prepare_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   const TLayout& TL = *up.TL;
   const Split& sp = up.sp;
   TRY(ensure_bf16_tables(ctx, TL.nrows, TL.ncols, TL.K, st));
@@ -577,25 +599,33 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
     CK(launch_table_bf16((const float*)ctx->T, TL.nrows, sp.RRP, TL.K, ctx->Tb, st));
     CK(launch_table_bf16((const float*)ctx->V, TL.ncols, sp.RRP, TL.K, ctx->Vb, st));
   }
+  return TRD_OK;
+}
+
+int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
+  const TLayout& TL = *up.TL;
+  const Split& sp = up.sp;
   TPassArgs a;
   memset(&a, 0, sizeof(a));
   a.T = ctx->Tb;
   a.TH = ctx->THb;
   a.V = ctx->Vb;
   a.S = (float*)ctx->S;
-  a.masks = TL.masks;
   a.boff = TL.boff;
   a.vals = TL.vals;
+  a.pos = TL.pos;
   a.resid = ctx->resid;
   a.partials = ctx->part_pass;
   a.sigma = ctx->scal + kSigma;
   a.nrows = TL.nrows;
   a.ncols = TL.ncols;
-  a.n_rbp = TL.n_rg * 4;
+  a.n_chunks = TL.n_chunks;
+  a.n_rb = TL.n_rb;
   a.n_rg = TL.n_rg;
   a.CW = TL.CW;
-  a.n_ch = TL.n_ch;
-  a.n_ct = TL.n_ct;
+  a.n_chpt = TL.n_chpt;
+  a.cpg = TL.cpg;
+  a.n_cg = TL.n_cg;
   a.RR = sp.RR;
   a.RRP = sp.RRP;
   CK(launch_tpass(mode, TL.K, a, st));
@@ -604,6 +634,7 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
 
 int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
+  if (up.TL) TRY(prepare_tile_pass(ctx, up, mode, st));  // outside the timed interval
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     CK(hipEventCreate(&e0));
@@ -802,6 +833,7 @@ int trd_create(trd_ctx** out, int device) {
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) return fail(nullptr, TRD_EDEVICE, hipGetErrorString(e));
   g_lds_max = (int64_t)prop.sharedMemPerBlock;
+  if (prop.multiProcessorCount > 0) g_num_cu = prop.multiProcessorCount;
   trd_ctx* c = new (std::nothrow) trd_ctx();
   if (!c) return fail(nullptr, TRD_ENOMEM, "host allocation failed");
   c->device = device;

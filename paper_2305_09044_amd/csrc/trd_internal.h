@@ -28,8 +28,21 @@ constexpr uint32_t TRD_FLAG_EMPTY_BIT = 1u;     // mirrors TRD_FLAG_EMPTY
 constexpr uint32_t TRD_FLAG_ZERO_DEN_BIT = 2u;  // mirrors TRD_FLAG_ZERO_DEN
 constexpr uint32_t TRD_FLAG_NOTSPD_BIT = 4u;    // mirrors TRD_FLAG_NOTSPD
 
-// largest dynamic LDS a work-group may request (set from the device at context creation)
+// largest dynamic LDS a work-group may request, and the compute-unit count (both set from
+// the device at context creation)
 extern int64_t g_lds_max;
+extern int g_num_cu;
+// work-groups a pass launch aims for: enough resident groups per CU to balance the tail
+inline int64_t wg_target() { return (int64_t)g_num_cu * 8; }
+// column groups for a row-group count and tile count: as few as give wg_target() groups
+inline void column_groups(int64_t n_rg, int n_ct, int& n_cg, int& cpg) {
+  int64_t want = (wg_target() + n_rg - 1) / (n_rg > 0 ? n_rg : 1);
+  if (want < 1) want = 1;
+  if (want > n_ct) want = n_ct;
+  cpg = (int)((n_ct + want - 1) / want);
+  if (cpg < 1) cpg = 1;
+  n_cg = (n_ct + cpg - 1) / cpg;
+}
 
 // A table of small column-major matrices ("items"), item t at ptr + idx(t) * stride.
 struct ItemRef {
@@ -53,6 +66,7 @@ struct Layout {
   int k = -1;
   int64_t nrows = 0, ncols = 0;
   int ct_w = 0, n_ct = 0;          // column tile width and count
+  int n_cg = 0, cpg = 0;           // column groups walked by one work-group, tiles per group
   int64_t n_rg = 0;                // 256-row groups
   int64_t n_slices = 0;            // n_ct * n_rg * 4
   int64_t slots = 0;               // host copy of the total slot count (full path)
@@ -114,7 +128,7 @@ struct PassArgs {
   const void* T;        // [nrows][RRP]
   const void* TH;       // [nrows][RRP] (line search)
   const void* V;        // [ncols][RRP]
-  void* S;              // [n_ct][nrows][RRP] per-column-tile gradient partials
+  void* S;              // [n_cg][nrows][RRP] per-column-group gradient partials
   const void* vals;
   const uint16_t* cols;
   const int64_t* slice_off;
@@ -124,6 +138,7 @@ struct PassArgs {
   const double* sigma;  // device scalar
   int64_t nrows, ncols, n_rg;
   int ct_w, RR, RRP, n_ct;
+  int n_cg, cpg;        // column groups (one work-group each per row group), tiles per group
 };
 hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st);
 bool pass_supported(int RR);
@@ -166,21 +181,23 @@ hipError_t launch_reconstruct(int dtype, int N, const int64_t* dims, const int32
 hipError_t launch_max_abs_observed(const Layout& L, int dtype, double* out, hipStream_t st);
 
 // ---------------------------------------------------------------- matrix-core (BF16) form
-// Bitmask tiles of one core-k matrix: per (64-row x 32-column block, lane) a 32-bit mask
-// and the block's observed values compacted in (lane, bit) order.
+// Block tiles of one core-k matrix: 64-row x 32-column blocks, block b = rb * n_chunks + ch,
+// each holding its observed values and in-block positions 32 r + c in increasing order.
 struct TLayout {
   int64_t nrows = 0, ncols = 0;
   int K = 0;                       // padded contraction width (multiple of 32)
-  int CW = 0, n_ct = 0, n_ch = 0;  // column tile width, tiles, 32-column chunks per tile
-  int64_t n_rg = 0;                // 256-row groups (4 row blocks of 64)
-  int64_t n_blocks = 0;
+  int CW = 0, n_chpt = 0;          // column tile width (multiple of 32), chunks per tile
+  int n_ct = 0, n_cg = 0, cpg = 0; // column tiles, column groups, tiles per group
+  int64_t n_chunks = 0;            // 32-column chunks
+  int64_t n_rb = 0, n_rg = 0;      // 64-row blocks, 256-row groups
+  int64_t n_blocks = 0;            // n_rb * n_chunks
   const int64_t* rowoff = nullptr; // shared with the ELL layout of the same split
   const int64_t* coloff = nullptr;
-  uint32_t* masks = nullptr;       // [n_blocks][64]
   int32_t* bcnt = nullptr;         // [n_blocks]
   int64_t* boff = nullptr;         // [n_blocks + 1]
   int64_t* total_dev = nullptr;
-  float* vals = nullptr;           // [nobs]
+  float* vals = nullptr;           // [nobs + slack]
+  uint16_t* pos = nullptr;         // [nobs + slack]
   int64_t nobs = 0;
   bool ready = false;
 };
@@ -189,19 +206,22 @@ struct TPassArgs {
   const uint16_t* T;     // [nrows][K] bf16
   const uint16_t* TH;    // [nrows][K] bf16 (line search)
   const uint16_t* V;     // [ncols][K] bf16
-  float* S;              // [n_ct][nrows][RRP] per-column-tile partials
-  const uint32_t* masks;
+  float* S;              // [n_cg][nrows][RRP] per-column-group partials
   const int64_t* boff;
   const float* vals;
+  const uint16_t* pos;
   float* resid;          // kModeResid: |e| per observed entry, in value order
   double* partials;      // [n_wg][3]
   const double* sigma;
-  int64_t nrows, ncols, n_rbp, n_rg;
-  int CW, n_ch, n_ct, RR, RRP;
+  int64_t nrows, ncols, n_chunks, n_rb, n_rg;
+  int CW, n_chpt, cpg, n_cg, RR, RRP;
 };
 
+// entries of slack after the value / position arrays of a tile layout
+constexpr int64_t kTileSlack = 64 * 16 + 64;
 int tile_k(int RR);
 int64_t tile_cw(int K);
+size_t tpass_lds(int mode, int K, int CW);
 hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* X, int dtype,
                              bool fill, hipStream_t st);
 hipError_t launch_table_bf16(const float* in, int64_t n, int in_stride, int K, uint16_t* out,
