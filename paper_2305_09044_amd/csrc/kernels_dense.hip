@@ -96,6 +96,66 @@ hipError_t launch_realign(const double* P, double* G, int r_k, int r_k1, hipStre
   return hipGetLastError();
 }
 
+// The whole ring product of eq. 13 for factor sides <= 64 in one work-group: running
+// product and next factor in LDS, the last product realigned into G as above.
+__global__ __launch_bounds__(1024) void k_ring(RingArgs a) {
+  extern __shared__ double sm[];
+  double* X = sm;
+  double* Y = sm + 4096;
+  double* Z = sm + 8192;
+  const int rows = a.rows[0];
+  int inner = a.cols[0];
+  for (int t = threadIdx.x; t < rows * inner; t += blockDim.x) X[t] = a.K[0][t];
+  __syncthreads();
+  for (int f = 1; f < a.nf; ++f) {
+    const int cols = a.cols[f];
+    for (int t = threadIdx.x; t < inner * cols; t += blockDim.x) Y[t] = a.K[f][t];
+    __syncthreads();
+    // up to four outputs per thread (rows * cols <= 4096), accumulated side by side
+    int oi[4], oj[4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = threadIdx.x + 1024 * q;
+      oi[q] = t < rows * cols ? t / cols : 0;
+      oj[q] = t < rows * cols ? t % cols : 0;
+    }
+    const int nq = (rows * cols + 1023) / 1024;
+    for (int l = 0; l < inner; ++l) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nq) acc[q] = fma(X[oi[q] * inner + l], Y[l * cols + oj[q]], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = threadIdx.x + 1024 * q;
+      if (t < rows * cols) Z[t] = acc[q];
+    }
+    __syncthreads();
+    double* tmp = X;
+    X = Z;
+    Z = tmp;
+    inner = cols;
+  }
+  const int r_k = a.r_k, r_k1 = a.r_k1, R = r_k * r_k1;
+  for (int t = threadIdx.x; t < rows * inner; t += blockDim.x) {
+    const int i = t / inner, j = t % inner;
+    const int b = i / r_k1, b2 = i % r_k1, al = j / r_k, a2 = j % r_k;
+    a.G[(int64_t)(al + b * r_k) * R + (a2 + b2 * r_k)] = X[t];
+  }
+}
+
+hipError_t launch_ring(const RingArgs& a, hipStream_t st) {
+  if (a.nf < 1 || a.nf > kMaxN) return hipErrorInvalidValue;
+  for (int f = 0; f < a.nf; ++f) {
+    if (a.rows[f] > 64 || a.cols[f] > 64) return hipErrorInvalidValue;
+    if (f > 0 && a.rows[f] != a.cols[f - 1]) return hipErrorInvalidValue;
+  }
+  if (a.rows[0] != a.r_k1 * a.r_k1 || a.cols[a.nf - 1] != a.r_k * a.r_k) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ring, dim3(1), dim3(1024), 3 * 4096 * sizeof(double), st, a);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- scaled direction
 
 // Cinv = (G + lambda I)^{-1}, lambda = lambda_rel * tr(G) / n, by in-place Gauss-Jordan
@@ -156,8 +216,16 @@ __global__ __launch_bounds__(1024) void k_inverse(const double* __restrict__ G,
   if (bad && threadIdx.x == 0) atomicOr(flags, TRD_FLAG_NOTSPD_BIT);
 }
 
+__global__ __launch_bounds__(256) void k_inverse64(const double* __restrict__ G, int n,
+                                                   double lambda_rel, double* __restrict__ Cinv,
+                                                   uint32_t* flags);
+
 hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
                           uint32_t* flags, hipStream_t st) {
+  if (n > 32 && n <= 64) {  // register form; smaller systems keep one element per thread
+    hipLaunchKernelGGL(k_inverse64, dim3(1), dim3(256), 0, st, G, n, lambda_rel, Cinv, flags);
+    return hipGetLastError();
+  }
   // small systems run in one or a few waves: fewer barrier participants per step
   int threads = ((n * n + 63) / 64) * 64;
   if (threads > 1024) threads = 1024;
@@ -171,6 +239,84 @@ hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_re
   return hipGetLastError();
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Cinv = (G + lambda I)^{-1} for n <= 64 in one work-group of 256 threads, with the same
+// elimination and the same SPD test as k_inverse.  Lane j of wave w keeps column j of rows
+// w, w + 4, ..., w + 60 in registers; the pivot column of those rows comes from lane k of
+// the same wave, the scaled pivot row from LDS (one barrier per step).
+__global__ __launch_bounds__(256) void k_inverse64(const double* __restrict__ G, int n,
+                                                   double lambda_rel, double* __restrict__ Cinv,
+                                                   uint32_t* flags) {
+  __shared__ double prow[2][64];
+  __shared__ double s_lam, s_thr;
+  __shared__ int s_bad;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = threadIdx.x & 63;
+  double A[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = w + 4 * q;
+    A[q] = (i < n && j < n) ? G[i * n + j] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    double tr = 0.0, mx = 0.0;
+    for (int i = 0; i < n; ++i) {
+      tr += G[i * n + i];
+      mx = fmax(mx, G[i * n + i]);
+    }
+    const double lam = lambda_rel * tr / n;
+    s_lam = lam;
+    s_thr = 64.0 * 2.220446049250313e-16 * (mx + lam);
+    s_bad = 0;
+  }
+  __syncthreads();
+  const double lam = s_lam, thr = s_thr;
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (w + 4 * q == j && j < n) A[q] += lam;
+  bool bad = false;
+#pragma unroll
+  for (int kq = 0; kq < 16; ++kq) {
+#pragma unroll
+    for (int kw = 0; kw < 4; ++kw) {
+      const int k = 4 * kq + kw;
+      if (k < n && !bad) {  // uniform over the group
+        const int buf = k & 1;
+        if (w == kw) {
+          const double piv = readlane_f64(A[kq], k);
+          if (!(piv > thr) || !isfinite(piv)) {
+            if (j == 0) s_bad = 1;
+          } else {
+            prow[buf][j] = (j == k ? 1.0 : A[kq]) * (1.0 / piv);
+          }
+        }
+        __syncthreads();
+        bad = s_bad != 0;
+        if (!bad) {
+          const double pr = prow[buf][j];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const double f = readlane_f64(A[q], k);
+            A[q] = (w + 4 * q == k) ? pr : (j == k ? 0.0 : A[q]) - f * pr;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = w + 4 * q;
+    if (i < n && j < n) Cinv[i * n + j] = bad ? 0.0 : A[q];
+  }
+  if (bad && threadIdx.x == 0) atomicOr(flags, TRD_FLAG_NOTSPD_BIT);
+}
+
 // h = d Cinv (I_k x n), written in FP64 and in the problem dtype; per-block partial
 // sums of <d, h> (fixed order).  A NOTSPD flag zeroes h.
 template <typename real>
@@ -181,8 +327,15 @@ __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict_
                                                        double* __restrict__ part,
                                                        const uint32_t* flags) {
   __shared__ double red[4];
+  __shared__ double Cs[64 * 64];  // Cinv staged when n <= 64
   const int64_t total = Ik * n;
   const bool bad = (*flags & TRD_FLAG_NOTSPD_BIT) != 0;
+  const bool staged = n <= 64;
+  if (staged) {
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) Cs[t] = Cinv[t];
+    __syncthreads();
+  }
+  const double* Cp = staged ? Cs : Cinv;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double contrib = 0.0;
   if (t < total) {
@@ -190,7 +343,7 @@ __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict_
     const int c = (int)(t % n);
     double s = 0.0;
     if (!bad)
-      for (int l = 0; l < n; ++l) s = fma(d64[i * n + l], Cinv[(int64_t)l * n + c], s);
+      for (int l = 0; l < n; ++l) s = fma(d64[i * n + l], Cp[(int64_t)l * n + c], s);
     h64[t] = s;
     if (h_real) h_real[t] = (real)s;
     contrib = d64[t] * s;
@@ -567,11 +720,23 @@ __global__ __launch_bounds__(256) void k_qhist(const float* __restrict__ keys,
   const int64_t n = *nslots;
   const uint32_t prefix = state[0];
   const int hi_shift = shift + bits;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t key = __float_as_uint(keys[i]);
-    const bool match = hi_shift >= 32 ? true : ((key >> hi_shift) == prefix);
-    if (match) atomicAdd(&lh[(key >> shift) & (nb - 1u)], 1u);
+  // four keys per lane per round (one 16-byte load); the round loop is uniform per wave
+  const int64_t n4 = (n + 3) / 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n4; base += stride) {
+    const int64_t i4 = base + threadIdx.x;
+    float4 k4 = {0.f, 0.f, 0.f, 0.f};
+    const bool full = 4 * i4 + 3 < n;
+    if (full) k4 = reinterpret_cast<const float4*>(keys)[i4];
+    const float kv[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = 4 * i4 + u;
+      const bool in = i < n;
+      const uint32_t key = in ? __float_as_uint(full ? kv[u] : keys[i]) : 0u;
+      const bool match = in && (hi_shift >= 32 || (key >> hi_shift) == prefix);
+      if (match) atomicAdd(&lh[(key >> shift) & (nb - 1u)], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)

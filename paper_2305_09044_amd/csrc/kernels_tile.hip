@@ -22,18 +22,6 @@ namespace trd {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-static int grid_for(int64_t n, int threads, int64_t cap = 1 << 20) {
-  int64_t g = (n + threads - 1) / threads;
-  if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return (int)g;
-}
-
-__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even (finite)
-  uint32_t u = __float_as_uint(f);
-  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
-
 // order LDS accesses among the lanes of one wave (the tiles below are per wave)
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -145,26 +133,6 @@ hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* 
     hipLaunchKernelGGL((k_tblock<double, true>), dim3(nb), dim3(256), 0, st, targs(L), mask,
                        (const double*)X);
   }
-  return hipGetLastError();
-}
-
-// f32 table [n][in_stride] -> bf16 table [n][K], zero padded
-__global__ void k_table_bf16(const float* __restrict__ in, int64_t n, int in_stride, int K,
-                             uint16_t* __restrict__ out) {
-  const int64_t total = n * K;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = t / K;
-    const int j = (int)(t % K);
-    out[t] = j < in_stride ? f2bf(in[i * in_stride + j]) : (uint16_t)0;
-  }
-}
-
-hipError_t launch_table_bf16(const float* in, int64_t n, int in_stride, int K, uint16_t* out,
-                             hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_table_bf16, dim3(grid_for(n * K, 256)), dim3(256), 0, st, in, n, in_stride,
-                     K, out);
   return hipGetLastError();
 }
 

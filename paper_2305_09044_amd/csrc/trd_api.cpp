@@ -310,10 +310,13 @@ int ensure_part(trd_ctx* ctx, int64_t need_pass, int64_t need_misc) {
   return TRD_OK;
 }
 
-int contract_chunks(int64_t Ik, int64_t nB) {
-  int64_t by_work = (nB + 15) / 16;
-  int64_t by_grid = std::max<int64_t>(1, 2048 / std::max<int64_t>(Ik, 1));
-  return (int)std::max<int64_t>(1, std::min(by_work, by_grid));
+// chunks of the B-mode range for the gradient contraction (split K): about two
+// work-groups per CU over the (i_k, a) pair tiles, at least two B items per chunk
+int contract_chunks(int64_t Ik, int64_t nB, int r_k) {
+  const int64_t ntile = (Ik * r_k + 255) / 256;
+  const int64_t by_grid = std::max<int64_t>(1, (2 * (int64_t)g_num_cu) / std::max<int64_t>(ntile, 1));
+  const int64_t by_work = std::max<int64_t>(1, (nB + 1) / 2);
+  return (int)std::min(by_grid, by_work);
 }
 
 // ---------------------------------------------------------------- per-update state
@@ -491,7 +494,11 @@ int build_U(trd_ctx* ctx, const Update& up, const void* const* cores, ItemRef& U
   return TRD_OK;
 }
 
-// T-like table: left(i_k) @ U(m_B), padded to RRP.  left in core layout (I_k items).
+int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStream_t st);
+
+// T-like table: left(i_k) @ U(m_B), padded to RRP.  left in core layout (I_k items).  For
+// the matrix-core passes the table is written directly as bf16, padded to K (out == T
+// goes to Tb, out == TH to THb).
 int build_rowtable(trd_ctx* ctx, const Update& up, const void* left, const ItemRef& Uref,
                    int64_t nB, void* out, hipStream_t st) {
   const Split& sp = up.sp;
@@ -499,10 +506,17 @@ int build_rowtable(trd_ctx* ctx, const Update& up, const void* left, const ItemR
   L.ptr = left;
   L.stride = (int64_t)sp.r_k * sp.r_k1;
   const int64_t Ik = up.counts[sp.k];
+  int64_t stride = sp.RRP;
+  const bool bf = up.TL != nullptr;
+  if (bf) {
+    TRY(ensure_bf16_tables(ctx, up.TL->nrows, up.TL->ncols, up.TL->K, st));
+    out = out == ctx->TH ? (void*)ctx->THb : (void*)ctx->Tb;
+    stride = up.TL->K;
+  }
   if (sp.p == 0) {
-    CK(launch_pack(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, out, sp.RRP, 0, st));
+    CK(launch_pack(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, out, stride, 0, st, bf));
   } else {
-    CK(launch_merge(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, Uref, nB, sp.r_s, out, sp.RRP, 0, st));
+    CK(launch_merge(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, Uref, nB, sp.r_s, out, stride, 0, st, bf));
   }
   return TRD_OK;
 }
@@ -516,8 +530,17 @@ int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hip
   int64_t nL = up.counts[m0];
   const int r0 = ctx->ranks[m0];  // == r_s
   int rB = ctx->ranks[(m0 + 1) % N];
+  // matrix-core passes: the final table goes straight to bf16, padded to K
+  const bool bf = up.TL != nullptr;
+  void* Vout = ctx->V;
+  int64_t Vstride = sp.RRP;
+  if (bf) {
+    TRY(ensure_bf16_tables(ctx, up.TL->nrows, up.TL->ncols, up.TL->K, st));
+    Vout = ctx->Vb;
+    Vstride = up.TL->K;
+  }
   if (sp.q == 1) {
-    CK(launch_pack(ctx->dtype, L, nL, r0, rB, ctx->V, sp.RRP, 1, st));
+    CK(launch_pack(ctx->dtype, L, nL, r0, rB, Vout, Vstride, 1, st, bf));
     return TRD_OK;
   }
   void* bufs[2] = {ctx->chainA, ctx->chainB};
@@ -525,9 +548,9 @@ int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hip
     const int m = sp.C[t];
     const int rC = ctx->ranks[(m + 1) % N];
     const bool last = t == sp.q - 1;
-    void* out = last ? ctx->V : bufs[t & 1];
+    void* out = last ? Vout : bufs[t & 1];
     CK(launch_merge(ctx->dtype, L, nL, r0, rB, core_ref(ctx, cores[m], m, up.lists), up.counts[m],
-                    rC, out, last ? sp.RRP : (int64_t)r0 * rC, last ? 1 : 0, st));
+                    rC, out, last ? Vstride : (int64_t)r0 * rC, last ? 1 : 0, st, last && bf));
     L.ptr = out;
     L.stride = (int64_t)r0 * rC;
     L.list = nullptr;
@@ -587,21 +610,7 @@ int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStr
   return TRD_OK;
 }
 
-// matrix-core pass: bf16 copies of the FP32 tables (before the timed kernel), then the
-// MFMA kernel
-int prepare_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
-  const TLayout& TL = *up.TL;
-  const Split& sp = up.sp;
-  TRY(ensure_bf16_tables(ctx, TL.nrows, TL.ncols, TL.K, st));
-  if (mode == kModeLS) {
-    CK(launch_table_bf16((const float*)ctx->TH, TL.nrows, sp.RRP, TL.K, ctx->THb, st));
-  } else {
-    CK(launch_table_bf16((const float*)ctx->T, TL.nrows, sp.RRP, TL.K, ctx->Tb, st));
-    CK(launch_table_bf16((const float*)ctx->V, TL.ncols, sp.RRP, TL.K, ctx->Vb, st));
-  }
-  return TRD_OK;
-}
-
+// matrix-core pass (its bf16 tables are written by the table builders)
 int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   const TLayout& TL = *up.TL;
   const Split& sp = up.sp;
@@ -634,7 +643,6 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
 
 int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
-  if (up.TL) TRY(prepare_tile_pass(ctx, up, mode, st));  // outside the timed interval
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     CK(hipEventCreate(&e0));
@@ -676,7 +684,7 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   const int64_t Ik = up.counts[sp.k];
   int64_t nB = 1;
   for (int t = 0; t < sp.p; ++t) nB *= up.counts[sp.B[t]];
-  const int nchunk = contract_chunks(Ik, nB);
+  const int nchunk = contract_chunks(Ik, nB, sp.r_k);
   TRY(ensure_part(ctx, up_nwg(up) * 3, std::max<int64_t>((int64_t)nchunk * Ik * sp.r_k * sp.r_k1, 8)));
   const int64_t nd = Ik * sp.r_k * sp.r_k1;
   if (nd > ctx->cap_d) {
@@ -692,9 +700,11 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   TRY(ensure_S(ctx, (int64_t)up_nct(up) * L.nrows * sp.RRP));
   TRY(run_pass(ctx, up, stats_dev ? kModeGrad : kModeGradFast, st));
   if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, stats_dev, st));
-  CK(launch_sum_tiles(ctx->dtype, ctx->S, up_nct(up), L.nrows * sp.RRP, st));
-  CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, 1, L.nrows, Ik, nB, sp.r_k, sp.r_s, sp.r_k1,
-                     Uref, ctx->part_misc, nchunk, st));
+  // the column-group partials are first summed by a streaming kernel
+  const int ncg = up_nct(up);
+  if (ncg > 1) CK(launch_sum_partials(ctx->dtype, ctx->S, ncg, L.nrows * sp.RRP, st));
+  CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, Ik, nB, sp.r_k, sp.r_s, sp.r_k1, Uref,
+                     ctx->part_misc, nchunk, st));
   CK(launch_contract_finish(ctx->dtype, ctx->part_misc, nchunk, Ik, sp.r_k * sp.r_k1, ctx->d64,
                             d_out, scale, st));
   if (Uout) *Uout = Uref;
@@ -737,6 +747,27 @@ int ring_gram(trd_ctx* ctx, int k, double* G_out, hipStream_t st) {
   if (N == 2) {
     CK(launch_realign(cur, G_out, ctx->ranks[k], ctx->ranks[s1], st));
     return TRD_OK;
+  }
+  // small ranks: the whole ring in one work-group
+  {
+    RingArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    bool fits = true;
+    ra.nf = N - 1;
+    for (int t = 1; t <= N - 1; ++t) {
+      const int m = (k + t) % N;
+      ra.K[t - 1] = ctx->K[m];
+      ra.rows[t - 1] = ctx->ranks[m] * ctx->ranks[m];
+      ra.cols[t - 1] = ctx->ranks[(m + 1) % N] * ctx->ranks[(m + 1) % N];
+      fits = fits && ra.rows[t - 1] <= 64 && ra.cols[t - 1] <= 64;
+    }
+    ra.r_k = ctx->ranks[k];
+    ra.r_k1 = ctx->ranks[s1];
+    ra.G = G_out;
+    if (fits && (int64_t)3 * 4096 * sizeof(double) <= g_lds_max) {
+      CK(launch_ring(ra, st));
+      return TRD_OK;
+    }
   }
   for (int t = 2; t <= N - 1; ++t) {
     const int m = (k + t) % N;
@@ -948,7 +979,7 @@ int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ran
     int64_t nB = 1;
     for (int t = 0; t < sp.p; ++t) nB *= ctx->dims[sp.B[t]];
     const int64_t R = (int64_t)sp.r_k * sp.r_k1;
-    needMisc = std::max(needMisc, (int64_t)contract_chunks(dims[k], nB) * dims[k] * R);
+    needMisc = std::max(needMisc, (int64_t)contract_chunks(dims[k], nB, sp.r_k) * dims[k] * R);
     needMisc = std::max(needMisc, (dims[k] * R + 255) / 256);
     needD = std::max(needD, dims[k] * R);
   }

@@ -110,15 +110,18 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_accum_i64(int64_t* dst, const int64_t* src, hipStream_t st);
 
 // tables (Def. 2 merges)
+// bf16_out: the table is written as bf16 bits (FP32 problems only), for the matrix-core passes
 hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRef R, int64_t nR,
-                        int rC, void* out, int64_t out_stride, int transpose_out, hipStream_t st);
+                        int rC, void* out, int64_t out_stride, int transpose_out, hipStream_t st,
+                        bool bf16_out = false);
 hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* out,
-                       int64_t out_stride, int transpose_out, hipStream_t st);
-hipError_t launch_to_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t st);
-hipError_t launch_contract(int dtype, const void* S, int RRP, int n_ct, int64_t nrows, int64_t Ik,
-                           int64_t nB, int r_k, int r_s, int r_k1, ItemRef U, double* part,
-                           int nchunk, hipStream_t st);
-hipError_t launch_sum_tiles(int dtype, void* S, int n_ct, int64_t n, hipStream_t st);
+                       int64_t out_stride, int transpose_out, hipStream_t st,
+                       bool bf16_out = false);
+// in-place fixed-order sum of n_ct partial arrays of n elements into the first
+hipError_t launch_sum_partials(int dtype, void* S, int n_ct, int64_t n, hipStream_t st);
+hipError_t launch_contract(int dtype, const void* S, int RRP, int64_t Ik, int64_t nB, int r_k,
+                           int r_s, int r_k1, ItemRef U, double* part, int nchunk,
+                           hipStream_t st);
 hipError_t launch_contract_finish(int dtype, const double* part, int nchunk, int64_t Ik, int RRk,
                                   double* d64, void* d_out, double scale, hipStream_t st);
 
@@ -156,6 +159,15 @@ hipError_t launch_finish_step(int dtype, const double* pnum, int64_t n_num, cons
                               uint32_t* flags_user, double* eta, double* eta_user, void* Z,
                               const double* h, int64_t nz, hipStream_t st);
 hipError_t launch_realign(const double* P, double* G, int r_k, int r_k1, hipStream_t st);
+// ring product of eq. 13 in one work-group (factor sides <= 64), realigned into G
+struct RingArgs {
+  const double* K[kMaxN];
+  int rows[kMaxN], cols[kMaxN];  // factor f is rows[f] x cols[f]; cols[f] == rows[f + 1]
+  int nf;
+  int r_k, r_k1;
+  double* G;
+};
+hipError_t launch_ring(const RingArgs& a, hipStream_t st);
 hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
                           uint32_t* flags, hipStream_t st);
 hipError_t launch_apply_inverse(const double* d64, const double* Cinv, int64_t Ik, int n,
@@ -224,8 +236,6 @@ int64_t tile_cw(int K);
 size_t tpass_lds(int mode, int K, int CW);
 hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* X, int dtype,
                              bool fill, hipStream_t st);
-hipError_t launch_table_bf16(const float* in, int64_t n, int in_stride, int K, uint16_t* out,
-                             hipStream_t st);
 hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st);
 
 // sigma quantile by radix select over float bit patterns
