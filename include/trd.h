@@ -51,6 +51,8 @@ extern "C" {
 /* precision of the entry-wise passes (problem dtype TRD_F32 only for BF16) */
 #define TRD_PREC_NATIVE 0     /* subchain tables and passes in the problem dtype */
 #define TRD_PREC_BF16   1     /* subchain tables in bf16, residual/weights/accumulators fp32 */
+#define TRD_PREC_BF16X3 2     /* as BF16, with the reconstruction from split bf16 tables
+                                 (hi + lo, three matrix-core products): ~16-bit residuals */
 
 /* device flag bits written by trd_step / trd_fit */
 #define TRD_FLAG_EMPTY     1u /* the update touched no observed entry: eta = 0 */
@@ -227,7 +229,10 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
  * (trd_fit uses its own opts.precision).  TRD_PREC_BF16 (FP32 problems only): the
  * subchain tables are rounded to bf16 and the reconstruction and gradient contractions
  * run on the matrix cores (BF16 operands, FP32 accumulation); residuals, weights and the
- * FGMC Gram / scaled step stay in FP32 / FP64.  RStS sketches always use the native passes.
+ * FGMC Gram / scaled step stay in FP32 / FP64.  TRD_PREC_BF16X3 also keeps the bf16
+ * remainder of every reconstruction-table element and adds the two cross products, so the
+ * residual is accurate to about 2^-16 relative instead of 2^-8 (the gradient contraction
+ * stays a single bf16 product).  RStS sketches always use the native passes.
  * The first BF16 use of a core builds its bitmask-tile layout (synchronizes the stream).
  */
 int trd_set_precision(trd_ctx* ctx, int precision);

@@ -24,7 +24,8 @@ TRD_ENOTSPD = -4
 TRD_ESTATE = -5
 TRD_EUNSUPPORTED = -6
 TRD_F32, TRD_F64 = 0, 1
-TRD_PREC_NATIVE, TRD_PREC_BF16 = 0, 1
+TRD_PREC_NATIVE, TRD_PREC_BF16, TRD_PREC_BF16X3 = 0, 1, 2
+PRECISIONS = {"native": TRD_PREC_NATIVE, "bf16": TRD_PREC_BF16, "bf16x3": TRD_PREC_BF16X3}
 TRD_FLAG_EMPTY, TRD_FLAG_ZERO_DEN, TRD_FLAG_NOTSPD = 1, 2, 4
 TRD_SIGMA_FIXED, TRD_SIGMA_GIVEN, TRD_SIGMA_QUANTILE = 0, 1, 2
 
@@ -279,7 +280,7 @@ class Problem:
             for j, v in enumerate(sketch_sizes):
                 o.sketch_sizes[j] = int(v)
         o.seed = int(seed)
-        o.precision = {"native": TRD_PREC_NATIVE, "bf16": TRD_PREC_BF16}[precision]
+        o.precision = PRECISIONS[precision]
         rep = trd_fit_report()
         eh = (C.c_double * max_sweeps)()
         sh = (C.c_double * max_sweeps)()
@@ -310,7 +311,7 @@ class Problem:
         return grads
 
     def set_precision(self, precision: str):
-        code = {"native": TRD_PREC_NATIVE, "bf16": TRD_PREC_BF16}[precision]
+        code = PRECISIONS[precision]
         _check(load().trd_set_precision(self._ctx, code), self._ctx)
 
     def profile(self, enable: bool):

@@ -18,11 +18,21 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {  // round to nearest ev
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// store one element of a table: the problem type, or bf16 bits for the matrix-core passes
+// store one element of a table: the problem type, or bf16 bits for the matrix-core passes;
+// with out_lo also the bf16 of the remainder v - hi (split tables: hi + lo carries about
+// 16 significant bits)
 template <typename real, bool BF>
-__device__ __forceinline__ void put(void* out, int64_t i, real v) {
-  if constexpr (BF) static_cast<uint16_t*>(out)[i] = bf16_bits((float)v);
-  else static_cast<real*>(out)[i] = v;
+__device__ __forceinline__ void put(void* out, void* out_lo, int64_t i, real v) {
+  if constexpr (BF) {
+    const uint16_t hi = bf16_bits((float)v);
+    static_cast<uint16_t*>(out)[i] = hi;
+    if (out_lo) {
+      const float hv = __uint_as_float((uint32_t)hi << 16);
+      static_cast<uint16_t*>(out_lo)[i] = bf16_bits((float)v - hv);
+    }
+  } else {
+    static_cast<real*>(out)[i] = v;
+  }
 }
 
 // out item (l + nL*j) = L(l) @ R(j): L(l) rA x rB, R(j) rB x rC, all column-major.
@@ -34,7 +44,8 @@ template <typename real, typename idx_t, bool BF>
 __global__ void k_merge(const real* __restrict__ L, int64_t Ls, const int32_t* __restrict__ Llist,
                         int64_t nL, int rA, int rB, const real* __restrict__ R, int64_t Rs,
                         const int32_t* __restrict__ Rlist, int64_t nR, int rC,
-                        void* __restrict__ out, int64_t out_stride, int transpose_out) {
+                        void* __restrict__ out, void* __restrict__ out_lo, int64_t out_stride,
+                        int transpose_out) {
   const idx_t os = (idx_t)out_stride;
   const idx_t total = (idx_t)(nL * nR) * os;
   const int used = rA * rC;
@@ -53,27 +64,27 @@ __global__ void k_merge(const real* __restrict__ L, int64_t Ls, const int32_t* _
       const real* Rp = R + (Rlist ? (int64_t)Rlist[j] : (int64_t)j) * Rs;
       for (int b = 0; b < rB; ++b) acc = fma(Lp[a + rA * b], Rp[b + rB * c], acc);
     }
-    put<real, BF>(out, (int64_t)t, acc);
+    put<real, BF>(out, out_lo, (int64_t)t, acc);
   }
 }
 
 template <typename real, bool BF>
 static void merge_idx(dim3 g, dim3 b, hipStream_t st, bool small, const ItemRef& L, int64_t nL,
                       int rA, int rB, const ItemRef& R, int64_t nR, int rC, void* out,
-                      int64_t out_stride, int transpose_out) {
+                      void* out_lo, int64_t out_stride, int transpose_out) {
   if (small)
     hipLaunchKernelGGL((k_merge<real, uint32_t, BF>), g, b, 0, st, (const real*)L.ptr, L.stride,
                        L.list, nL, rA, rB, (const real*)R.ptr, R.stride, R.list, nR, rC, out,
-                       out_stride, transpose_out);
+                       out_lo, out_stride, transpose_out);
   else
     hipLaunchKernelGGL((k_merge<real, int64_t, BF>), g, b, 0, st, (const real*)L.ptr, L.stride,
                        L.list, nL, rA, rB, (const real*)R.ptr, R.stride, R.list, nR, rC, out,
-                       out_stride, transpose_out);
+                       out_lo, out_stride, transpose_out);
 }
 
 hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRef R, int64_t nR,
                         int rC, void* out, int64_t out_stride, int transpose_out, hipStream_t st,
-                        bool bf16_out) {
+                        bool bf16_out, void* out_lo) {
   const int64_t total = nL * nR * out_stride;
   if (total <= 0) return hipSuccess;
   const int grid = grid_for(total, 256);
@@ -81,13 +92,13 @@ hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRe
   dim3 g(grid), b(256);
   if (bf16_out) {
     if (dtype != 0) return hipErrorInvalidValue;
-    merge_idx<float, true>(g, b, st, small, L, nL, rA, rB, R, nR, rC, out, out_stride,
+    merge_idx<float, true>(g, b, st, small, L, nL, rA, rB, R, nR, rC, out, out_lo, out_stride,
                            transpose_out);
   } else if (dtype == 0) {
-    merge_idx<float, false>(g, b, st, small, L, nL, rA, rB, R, nR, rC, out, out_stride,
+    merge_idx<float, false>(g, b, st, small, L, nL, rA, rB, R, nR, rC, out, nullptr, out_stride,
                             transpose_out);
   } else {
-    merge_idx<double, false>(g, b, st, small, L, nL, rA, rB, R, nR, rC, out, out_stride,
+    merge_idx<double, false>(g, b, st, small, L, nL, rA, rB, R, nR, rC, out, nullptr, out_stride,
                              transpose_out);
   }
   return hipGetLastError();
@@ -96,8 +107,8 @@ hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRe
 // Copy items (optionally through an index list), optionally transposed, zero padded.
 template <typename real, bool BF>
 __global__ void k_pack(const real* __restrict__ in, int64_t is, const int32_t* __restrict__ list,
-                       int64_t n, int rA, int rB, void* __restrict__ out, int64_t out_stride,
-                       int transpose_out) {
+                       int64_t n, int rA, int rB, void* __restrict__ out,
+                       void* __restrict__ out_lo, int64_t out_stride, int transpose_out) {
   const int64_t total = n * out_stride;
   const int64_t used = (int64_t)rA * rB;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -112,25 +123,26 @@ __global__ void k_pack(const real* __restrict__ in, int64_t is, const int32_t* _
       const real* p = in + (list ? (int64_t)list[item] : item) * is;
       v = p[a + rA * b];
     }
-    put<real, BF>(out, t, v);
+    put<real, BF>(out, out_lo, t, v);
   }
 }
 
 hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* out,
-                       int64_t out_stride, int transpose_out, hipStream_t st, bool bf16_out) {
+                       int64_t out_stride, int transpose_out, hipStream_t st, bool bf16_out,
+                       void* out_lo) {
   const int64_t total = n * out_stride;
   if (total <= 0) return hipSuccess;
   dim3 g(grid_for(total, 256)), b(256);
   if (bf16_out) {
     if (dtype != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_pack<float, true>), g, b, 0, st, (const float*)in.ptr, in.stride, in.list,
-                       n, rA, rB, out, out_stride, transpose_out);
+                       n, rA, rB, out, out_lo, out_stride, transpose_out);
   } else if (dtype == 0) {
     hipLaunchKernelGGL((k_pack<float, false>), g, b, 0, st, (const float*)in.ptr, in.stride,
-                       in.list, n, rA, rB, out, out_stride, transpose_out);
+                       in.list, n, rA, rB, out, nullptr, out_stride, transpose_out);
   } else {
     hipLaunchKernelGGL((k_pack<double, false>), g, b, 0, st, (const double*)in.ptr, in.stride,
-                       in.list, n, rA, rB, out, out_stride, transpose_out);
+                       in.list, n, rA, rB, out, nullptr, out_stride, transpose_out);
   }
   return hipGetLastError();
 }

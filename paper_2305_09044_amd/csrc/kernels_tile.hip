@@ -12,6 +12,10 @@
 //   3. S^T (K x 64 rows) += V^T-items^T (K x 32 cols) . Y^T (32 cols x 64 rows) on the
 //      matrix cores: the row factor of the gradient of eq. 9.
 // Matrix-core work covers every position of a block; vector work is per observed entry.
+// Split form (SPLIT): the T and V tables also come as bf16 remainders (t = t_hi + t_lo),
+// and Xhat adds the products t_hi v_lo and t_lo v_hi, so the reconstruction (and the
+// residual) carries about 16 significant bits instead of 8; the gradient contraction
+// stays a single bf16 product.
 // A work-group (4 waves = 4 block rows) walks a group of column tiles and keeps its S
 // accumulators in registers; the V^T items of the current tile are staged transposed in
 // LDS as the A operand of step 3.
@@ -147,7 +151,9 @@ constexpr int kYTile = 64 * kYS;        // bf16
 constexpr int kXBytes = 4 * kXTile * 4; // four waves
 constexpr int kYBytes = 4 * kYTile * 2;
 
-template <int K> struct TileRounds { static constexpr int v = K <= 32 ? 12 : (K <= 64 ? 8 : 4); };
+template <int K, bool SPLIT> struct TileRounds {
+  static constexpr int v = K <= 32 ? 12 : (K <= 64 && !SPLIT ? 8 : 4);
+};
 
 size_t tpass_lds(int mode, int K, int CW) {
   if (mode == kModeGrad || mode == kModeGradFast)
@@ -156,11 +162,11 @@ size_t tpass_lds(int mode, int K, int CW) {
   return (size_t)kXBytes;
 }
 
-template <int K, int MODE>
+template <int K, int MODE, bool SPLIT>
 __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   constexpr int KS = K / 16;       // k-steps of the reconstruction MFMA
   constexpr int MT = K / 32;       // m-tiles of the gradient MFMA
-  constexpr int kR = TileRounds<K>::v;  // entry rounds of 64 held in registers per chunk
+  constexpr int kR = TileRounds<K, SPLIT>::v;  // entry rounds of 64 in registers per chunk
   constexpr bool kGrad = MODE == kModeGrad || MODE == kModeGradFast;
   constexpr bool kLS = MODE == kModeLS;
   constexpr bool kStats = MODE == kModeGrad || MODE == kModeLoss;
@@ -184,6 +190,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
 
   // B operand of the reconstruction: this wave's 64 T items (and TH for the line search)
   bf16x8 tb[2][KS];
+  bf16x8 tlo[SPLIT ? 2 : 1][SPLIT ? KS : 1];
   bf16x8 thb[kLS ? 2 : 1][kLS ? KS : 1];
 #pragma unroll
   for (int n = 0; n < 2; ++n) {
@@ -194,6 +201,11 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
       tb[n][s] = z;
       if (row < a.nrows)
         tb[n][s] = *reinterpret_cast<const bf16x8*>(a.T + row * K + s * 16 + h * 8);
+      if constexpr (SPLIT) {
+        tlo[n][s] = z;
+        if (row < a.nrows)
+          tlo[n][s] = *reinterpret_cast<const bf16x8*>(a.T_lo + row * K + s * 16 + h * 8);
+      }
       if constexpr (kLS) {
         thb[n][s] = z;
         if (row < a.nrows)
@@ -260,18 +272,26 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   struct Set {
     float x[kR];
     uint32_t p[kR];
-    bf16x8 av[KS];
   };
   const int64_t bb = rb * a.n_chunks;
-  auto load_set = [&](Set& S, int64_t gc, int64_t bo) {
+  auto load_set = [&](Set& S, int64_t bo) {
 #pragma unroll
     for (int t = 0; t < kR; ++t) {
       S.x[t] = a.vals[bo + 64 * t + l];
       S.p[t] = a.pos[bo + 64 * t + l];
     }
+  };
+  // A operand of the reconstruction (V^T items of one chunk): loaded for the next chunk
+  // as soon as the current chunk's products have been issued
+  bf16x8 av[KS];
+  bf16x8 avlo[SPLIT ? KS : 1];
+  auto load_av = [&](int64_t gc) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
-      S.av[s] = *reinterpret_cast<const bf16x8*>(a.V + (gc * 32 + li) * K + s * 16 + h * 8);
+    for (int s = 0; s < KS; ++s) {
+      av[s] = *reinterpret_cast<const bf16x8*>(a.V + (gc * 32 + li) * K + s * 16 + h * 8);
+      if constexpr (SPLIT)
+        avlo[s] = *reinterpret_cast<const bf16x8*>(a.V_lo + (gc * 32 + li) * K + s * 16 + h * 8);
+    }
   };
 
   constexpr int KV = K / 8;  // 16-byte vectors per table item
@@ -312,8 +332,8 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     }
     if (!rb_ok) return;  // uniform over the wave; it still joins every tile barrier
 
-    // prefetch the next chunk (index gc + 1 <= n_chunks, offset bo_end <= nobs)
-    load_set(N, gc + 1, bo_end);
+    // prefetch the next chunk's entries (offset bo_end <= nobs)
+    load_set(N, bo_end);
     const int64_t bo_nn = a.boff[bb + min(gc + 3, gc_end)];
 
     // 1. Xhat^T (and Q^T) of this chunk
@@ -324,11 +344,17 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
-        xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(C.av[s], tb[n][s], xacc[n], 0, 0, 0);
+        if constexpr (SPLIT) {  // remainder products first, then the leading one
+          xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(avlo[s], tb[n][s], xacc[n], 0, 0, 0);
+          xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], tlo[n][s], xacc[n], 0, 0, 0);
+        }
+        xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], tb[n][s], xacc[n], 0, 0, 0);
         if constexpr (kLS)
-          qacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(C.av[s], thb[n][s], qacc[n], 0, 0, 0);
+          qacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], thb[n][s], qacc[n], 0, 0, 0);
       }
     }
+    // the next chunk's operands (chunk index gc + 1 <= n_chunks: within the table slack)
+    load_av(gc + 1);
 
     // 2. spill Xhat (and Q) to LDS as [row][col]; clear the y tile
     // accumulator v of n-tile n: col 8 (v/4) + 4 h + v%4, row 32 n + li
@@ -404,7 +430,8 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     bo_cur = a.boff[bb + gc_beg];
     bo_end = a.boff[bb + gc_beg + 1];
     bo_nend = a.boff[bb + min(gc_beg + 2, gc_end)];
-    load_set(A, gc_beg, bo_cur);
+    load_set(A, bo_cur);
+    load_av(gc_beg);
   }
   for (int64_t gc = gc_beg; gc < gc_end; gc += 2) {
     step(gc, A, B);
@@ -459,35 +486,43 @@ int64_t tile_cw(int K) {
   return cw;
 }
 
-template <int K>
+template <int K, bool SPLIT>
 static hipError_t launch_k(int mode, const TPassArgs& a, hipStream_t st) {
   const int64_t nwg = a.n_rg * a.n_cg;
   const size_t lds = tpass_lds(mode, K, a.CW);
   if ((int64_t)lds > g_lds_max) return hipErrorInvalidConfiguration;
   dim3 g((unsigned)nwg), b(256);
   switch (mode) {
-    case kModeGrad: hipLaunchKernelGGL((k_tpass<K, kModeGrad>), g, b, lds, st, a); break;
-    case kModeGradFast: hipLaunchKernelGGL((k_tpass<K, kModeGradFast>), g, b, lds, st, a); break;
-    case kModeLS: hipLaunchKernelGGL((k_tpass<K, kModeLS>), g, b, lds, st, a); break;
-    case kModeResid: hipLaunchKernelGGL((k_tpass<K, kModeResid>), g, b, lds, st, a); break;
-    default: hipLaunchKernelGGL((k_tpass<K, kModeLoss>), g, b, lds, st, a); break;
+    case kModeGrad: hipLaunchKernelGGL((k_tpass<K, kModeGrad, SPLIT>), g, b, lds, st, a); break;
+    case kModeGradFast:
+      hipLaunchKernelGGL((k_tpass<K, kModeGradFast, SPLIT>), g, b, lds, st, a);
+      break;
+    case kModeLS: hipLaunchKernelGGL((k_tpass<K, kModeLS, SPLIT>), g, b, lds, st, a); break;
+    case kModeResid: hipLaunchKernelGGL((k_tpass<K, kModeResid, SPLIT>), g, b, lds, st, a); break;
+    default: hipLaunchKernelGGL((k_tpass<K, kModeLoss, SPLIT>), g, b, lds, st, a); break;
   }
   return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_ks(int mode, const TPassArgs& a, hipStream_t st) {
+  return (a.T_lo && a.V_lo) ? launch_k<K, true>(mode, a, st) : launch_k<K, false>(mode, a, st);
 }
 
 hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {
   if (a.n_rg * a.n_cg <= 0 || a.n_chunks <= 0) return hipSuccess;
   // the grid and chunk walk must cover exactly the layout the pass indexes
+  if ((a.T_lo == nullptr) != (a.V_lo == nullptr)) return hipErrorInvalidValue;
   if (a.CW % 32 != 0 || a.n_chpt != a.CW / 32 || a.cpg < 1 || a.n_rb > 4 * a.n_rg ||
       (int64_t)a.n_cg * a.cpg * a.n_chpt < a.n_chunks ||
       (int64_t)(a.n_cg - 1) * a.cpg * a.n_chpt >= a.n_chunks || a.n_chunks * 32 < a.ncols ||
       a.n_rb * 64 < a.nrows || a.RRP > K)
     return hipErrorInvalidValue;
   switch (K) {
-    case 32: return launch_k<32>(mode, a, st);
-    case 64: return launch_k<64>(mode, a, st);
-    case 96: return launch_k<96>(mode, a, st);
-    case 128: return launch_k<128>(mode, a, st);
+    case 32: return launch_ks<32>(mode, a, st);
+    case 64: return launch_ks<64>(mode, a, st);
+    case 96: return launch_ks<96>(mode, a, st);
+    case 128: return launch_ks<128>(mode, a, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -56,7 +56,8 @@ struct trd_ctx {
   std::vector<TLayout> tlayouts;  // bitmask-tile layout per core (BF16 form, built on demand)
   int prec = TRD_PREC_NATIVE;     // precision of the entry passes
   uint16_t* Tb = nullptr; uint16_t* THb = nullptr; uint16_t* Vb = nullptr;
-  int64_t cap_Tb = 0, cap_Vb = 0;
+  uint16_t* Tb_lo = nullptr; uint16_t* Vb_lo = nullptr;  // split (BF16X3) remainders
+  int64_t cap_Tb = 0, cap_Vb = 0, cap_Tlo = 0, cap_Vlo = 0;
 
   // tables and work buffers (sized for the largest core and sketch)
   void* T = nullptr; void* TH = nullptr; void* V = nullptr; void* S = nullptr;
@@ -431,9 +432,11 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   return TRD_OK;
 }
 
+bool bf16_form(int prec) { return prec == TRD_PREC_BF16 || prec == TRD_PREC_BF16X3; }
+
 int prepare_update(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
   if (sk) return prepare_sketch(ctx, k, sk, up, st);  // sketches use the ELL passes
-  if (ctx->prec == TRD_PREC_BF16) {
+  if (bf16_form(ctx->prec)) {
     TRY(ensure_tile_layout(ctx, k, st));
     up.TL = &ctx->tlayouts[k];
   }
@@ -508,15 +511,18 @@ int build_rowtable(trd_ctx* ctx, const Update& up, const void* left, const ItemR
   const int64_t Ik = up.counts[sp.k];
   int64_t stride = sp.RRP;
   const bool bf = up.TL != nullptr;
+  void* lo = nullptr;  // remainder table of the split form (reconstruction table only)
   if (bf) {
     TRY(ensure_bf16_tables(ctx, up.TL->nrows, up.TL->ncols, up.TL->K, st));
+    if (out != ctx->TH && ctx->prec == TRD_PREC_BF16X3) lo = ctx->Tb_lo;
     out = out == ctx->TH ? (void*)ctx->THb : (void*)ctx->Tb;
     stride = up.TL->K;
   }
   if (sp.p == 0) {
-    CK(launch_pack(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, out, stride, 0, st, bf));
+    CK(launch_pack(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, out, stride, 0, st, bf, lo));
   } else {
-    CK(launch_merge(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, Uref, nB, sp.r_s, out, stride, 0, st, bf));
+    CK(launch_merge(ctx->dtype, L, Ik, sp.r_k, sp.r_k1, Uref, nB, sp.r_s, out, stride, 0, st, bf,
+                    lo));
   }
   return TRD_OK;
 }
@@ -533,14 +539,16 @@ int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hip
   // matrix-core passes: the final table goes straight to bf16, padded to K
   const bool bf = up.TL != nullptr;
   void* Vout = ctx->V;
+  void* Vlo = nullptr;
   int64_t Vstride = sp.RRP;
   if (bf) {
     TRY(ensure_bf16_tables(ctx, up.TL->nrows, up.TL->ncols, up.TL->K, st));
     Vout = ctx->Vb;
+    if (ctx->prec == TRD_PREC_BF16X3) Vlo = ctx->Vb_lo;
     Vstride = up.TL->K;
   }
   if (sp.q == 1) {
-    CK(launch_pack(ctx->dtype, L, nL, r0, rB, Vout, Vstride, 1, st, bf));
+    CK(launch_pack(ctx->dtype, L, nL, r0, rB, Vout, Vstride, 1, st, bf, Vlo));
     return TRD_OK;
   }
   void* bufs[2] = {ctx->chainA, ctx->chainB};
@@ -550,7 +558,8 @@ int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hip
     const bool last = t == sp.q - 1;
     void* out = last ? Vout : bufs[t & 1];
     CK(launch_merge(ctx->dtype, L, nL, r0, rB, core_ref(ctx, cores[m], m, up.lists), up.counts[m],
-                    rC, out, last ? Vstride : (int64_t)r0 * rC, last ? 1 : 0, st, last && bf));
+                    rC, out, last ? Vstride : (int64_t)r0 * rC, last ? 1 : 0, st, last && bf,
+                    last ? Vlo : nullptr));
     L.ptr = out;
     L.stride = (int64_t)r0 * rC;
     L.list = nullptr;
@@ -594,18 +603,28 @@ int up_nct(const Update& up) { return up.TL ? up.TL->n_cg : up.L->n_cg; }
 const int64_t* up_nobs_dev(const Update& up) { return up.TL ? up.TL->total_dev : up.L->nobs_dev; }
 
 int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStream_t st) {
+  const bool split = ctx->prec == TRD_PREC_BF16X3;
   if (nrows * K > ctx->cap_Tb) {
     TRY(alloc_n(ctx, &ctx->Tb, nrows * K));
     TRY(alloc_n(ctx, &ctx->THb, nrows * K));
     ctx->cap_Tb = nrows * K;
   }
+  if (split && nrows * K > ctx->cap_Tlo) {
+    TRY(alloc_n(ctx, &ctx->Tb_lo, nrows * K));
+    ctx->cap_Tlo = nrows * K;
+  }
+  // column tables: slack of one column tile past the last column (the MFMA pass reads
+  // whole chunks ahead); zero filled once (later tables leave only finite values behind)
+  const int64_t n = ncols * K + tile_cw(K) * (int64_t)K + 64 * K;
   if (ncols * K > ctx->cap_Vb) {
-    // slack of one column tile past the last column: the MFMA pass reads whole tiles;
-    // zero filled once (later tables leave only finite values behind)
-    const int64_t n = ncols * K + tile_cw(K) * (int64_t)K + 64 * K;
     TRY(alloc_n(ctx, &ctx->Vb, n));
     CK(launch_zero(ctx->Vb, (size_t)n * sizeof(uint16_t), st));
     ctx->cap_Vb = ncols * K;
+  }
+  if (split && ncols * K > ctx->cap_Vlo) {
+    TRY(alloc_n(ctx, &ctx->Vb_lo, n));
+    CK(launch_zero(ctx->Vb_lo, (size_t)n * sizeof(uint16_t), st));
+    ctx->cap_Vlo = ncols * K;
   }
   return TRD_OK;
 }
@@ -619,6 +638,10 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   a.T = ctx->Tb;
   a.TH = ctx->THb;
   a.V = ctx->Vb;
+  if (ctx->prec == TRD_PREC_BF16X3) {
+    a.T_lo = ctx->Tb_lo;
+    a.V_lo = ctx->Vb_lo;
+  }
   a.S = (float*)ctx->S;
   a.boff = TL.boff;
   a.vals = TL.vals;
@@ -1097,9 +1120,9 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
   if (!o) return fail(ctx, TRD_EINVAL, "opts is NULL");
   if (o->max_sweeps < 1) return fail(ctx, TRD_EINVAL, "max_sweeps must be >= 1");
   if (!(o->lambda_rel >= 0.0)) return fail(ctx, TRD_EINVAL, "lambda_rel must be >= 0");
-  if (o->precision != TRD_PREC_NATIVE && o->precision != TRD_PREC_BF16)
+  if (o->precision != TRD_PREC_NATIVE && !bf16_form(o->precision))
     return fail(ctx, TRD_EINVAL, "unknown precision");
-  if (o->precision == TRD_PREC_BF16 && ctx->dtype != TRD_F32)
+  if (bf16_form(o->precision) && ctx->dtype != TRD_F32)
     return fail(ctx, TRD_EUNSUPPORTED, "the BF16 form needs an FP32 problem");
   if (o->sigma_mode == TRD_SIGMA_FIXED) TRY(check_sigma(ctx, o->sigma));
   else if (o->sigma_mode == TRD_SIGMA_GIVEN) {
@@ -1276,9 +1299,9 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
 
 int trd_set_precision(trd_ctx* ctx, int precision) {
   if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
-  if (precision != TRD_PREC_NATIVE && precision != TRD_PREC_BF16)
+  if (precision != TRD_PREC_NATIVE && !bf16_form(precision))
     return fail(ctx, TRD_EINVAL, "unknown precision");
-  if (precision == TRD_PREC_BF16) {
+  if (bf16_form(precision)) {
     if (!ctx->has_problem) return fail(ctx, TRD_ESTATE, "call trd_set_problem first");
     if (ctx->dtype != TRD_F32) return fail(ctx, TRD_EUNSUPPORTED, "the BF16 form needs an FP32 problem");
   }

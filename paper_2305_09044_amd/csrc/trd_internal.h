@@ -110,13 +110,14 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_accum_i64(int64_t* dst, const int64_t* src, hipStream_t st);
 
 // tables (Def. 2 merges)
-// bf16_out: the table is written as bf16 bits (FP32 problems only), for the matrix-core passes
+// bf16_out: the table is written as bf16 bits (FP32 problems only), for the matrix-core
+// passes; out_lo (with bf16_out) also receives the bf16 of each element's remainder
 hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRef R, int64_t nR,
                         int rC, void* out, int64_t out_stride, int transpose_out, hipStream_t st,
-                        bool bf16_out = false);
+                        bool bf16_out = false, void* out_lo = nullptr);
 hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* out,
                        int64_t out_stride, int transpose_out, hipStream_t st,
-                       bool bf16_out = false);
+                       bool bf16_out = false, void* out_lo = nullptr);
 // in-place fixed-order sum of n_ct partial arrays of n elements into the first
 hipError_t launch_sum_partials(int dtype, void* S, int n_ct, int64_t n, hipStream_t st);
 hipError_t launch_contract(int dtype, const void* S, int RRP, int64_t Ik, int64_t nB, int r_k,
@@ -218,6 +219,8 @@ struct TPassArgs {
   const uint16_t* T;     // [nrows][K] bf16
   const uint16_t* TH;    // [nrows][K] bf16 (line search)
   const uint16_t* V;     // [ncols][K] bf16
+  const uint16_t* T_lo;  // split tables (remainders), or nullptr
+  const uint16_t* V_lo;
   float* S;              // [n_cg][nrows][RRP] per-column-group partials
   const int64_t* boff;
   const float* vals;
