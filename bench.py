@@ -124,6 +124,15 @@ def equal_accuracy(prob, Z0_flat, xstar_d, sweeps, checkpoints, band=0.03, n_sam
     def first_hit(rows, target):
         return next((r for r in rows if r[2] <= target * (1 + band)), None)
 
+    # common error levels: sweeps and time each precision needs to get there
+    levels = {}
+    for lv in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        row = {}
+        for p, rows in res.items():
+            h = next((r for r in rows if r[2] <= lv), None)
+            row[names[p]] = None if h is None else {"sweeps": h[0], "ms": round(h[1] * 1e3, 3)}
+        levels[f"{lv:.0e}"] = row
+    out["levels"] = levels
     for form in ("bf16", "bf16x3"):
         e_star = res[form][-1][2]
         hf, h32 = first_hit(res[form], e_star), first_hit(res["native"], e_star)
@@ -178,7 +187,7 @@ def main():
     ap.add_argument("--no-equal-accuracy", action="store_true",
                     help="skip the FP32-vs-BF16 time-to-equal-recovery-error comparison")
     ap.add_argument("--accuracy-sweeps", type=int, default=30)
-    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"],
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "bf16x3"],
                     help="bf16: matrix-core passes with bf16 subchain tables (FP32 residuals); "
                          "bf16x3: the same with the reconstruction from split bf16 tables")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -276,7 +285,7 @@ def main():
         Z0_flat = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(Z0, np.float32)]
         out["equal_accuracy"] = equal_accuracy(prob, Z0_flat, xstar_d, C, cps)
         log("equal accuracy:", json.dumps({k: v for k, v in out["equal_accuracy"].items()
-                                           if k != "trace"}))
+                                           if k not in ("trace", "levels")}))
     if not args.no_cpu_baseline:
         if args.cpu_sample:
             sample = tuple(int(v) for v in args.cpu_sample.split(","))

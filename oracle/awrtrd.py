@@ -162,6 +162,35 @@ def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, s
     return new, info
 
 
+def gradient_row(cores: List[np.ndarray], k: int, idx: np.ndarray, vals: np.ndarray,
+                 sigma: float, chunk: int = 1 << 16) -> np.ndarray:
+    """Row i of eq. (9) from the observed entries of slice i_k = i, for tensors too large
+    for the explicit unfolding: d(i)[a + b r_k] = sum over the entries of
+    w(e) e A(m)[b, a], with A(m) = Z_{k+1}(i_{k+1}) ... Z_{k-1}(i_{k-1}) (Thm. 1),
+    e = x - Tr(Z_k(i) A(m)) and w of eq. (7).
+
+    idx: (n, N) integer indices of the entries (all with idx[:, k] == i); vals: (n,) values.
+    Returns the r_k * r_{k+1} row in the column order of unfold_core."""
+    N = len(cores)
+    idx = np.asarray(idx, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    i = int(idx[0, k]) if len(idx) else 0
+    Zi = cores[k][:, i, :]                               # r_k x r_{k+1}
+    rk, rk1 = Zi.shape
+    D = np.zeros((rk1, rk))                              # accumulates sum y A(m)
+    for s in range(0, len(vals), chunk):
+        sl = slice(s, s + chunk)
+        order = cyclic_order(N, k)
+        A = cores[order[0]][:, idx[sl, order[0]], :].transpose(1, 0, 2)   # (n, r, r')
+        for j in order[1:]:
+            A = np.matmul(A, cores[j][:, idx[sl, j], :].transpose(1, 0, 2))
+        xhat = np.einsum("ab,nba->n", Zi, A)             # Tr(Z_k(i) A(m))
+        e = vals[sl] - xhat
+        y = weights(e, sigma) * e
+        D += np.einsum("n,nba->ba", y, A)
+    return D.reshape(-1)                                 # index b * r_k + a
+
+
 # ----------------------------------------------------------------------------------
 # sweep, convergence, sigma, fit
 # ----------------------------------------------------------------------------------

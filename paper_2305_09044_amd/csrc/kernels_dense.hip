@@ -96,52 +96,76 @@ hipError_t launch_realign(const double* P, double* G, int r_k, int r_k1, hipStre
   return hipGetLastError();
 }
 
-// The whole ring product of eq. 13 for factor sides <= 64 in one work-group: running
-// product and next factor in LDS, the last product realigned into G as above.
-__global__ __launch_bounds__(1024) void k_ring(RingArgs a) {
-  extern __shared__ double sm[];
-  double* X = sm;
+// The whole ring product of eq. 13 for factor sides <= 64 in one work-group.  The running
+// product is kept transposed (Xt[l][i]) and the next factor as Y[l][j], both zero padded to
+// 64 x 64 in LDS; thread (ti, tj) of a 16 x 16 grid accumulates the 4 x 4 block of rows
+// 4 ti.. and columns 4 tj.. from two 32-byte reads per k-step, then stores it transposed
+// as the next Xt.  The last product is realigned into G as above.
+__global__ __launch_bounds__(256) void k_ring(RingArgs a) {
+  extern __shared__ __align__(16) double sm[];
+  double* Xt = sm;
   double* Y = sm + 4096;
-  double* Z = sm + 8192;
+  double* Zt = sm + 8192;
+  const int tid = threadIdx.x;
   const int rows = a.rows[0];
   int inner = a.cols[0];
-  for (int t = threadIdx.x; t < rows * inner; t += blockDim.x) X[t] = a.K[0][t];
-  __syncthreads();
+  {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = tid + 256 * q, l = t >> 6, i = t & 63;
+      v[q] = (i < rows && l < inner) ? a.K[0][i * inner + l] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Xt[tid + 256 * q] = v[q];
+  }
+  const int ti = tid >> 4, tj = tid & 15;
   for (int f = 1; f < a.nf; ++f) {
     const int cols = a.cols[f];
-    for (int t = threadIdx.x; t < inner * cols; t += blockDim.x) Y[t] = a.K[f][t];
-    __syncthreads();
-    // up to four outputs per thread (rows * cols <= 4096), accumulated side by side
-    int oi[4], oj[4];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    {
+      double v[16];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = threadIdx.x + 1024 * q;
-      oi[q] = t < rows * cols ? t / cols : 0;
-      oj[q] = t < rows * cols ? t % cols : 0;
+      for (int q = 0; q < 16; ++q) {
+        const int t = tid + 256 * q, l = t >> 6, j = t & 63;
+        v[q] = (l < inner && j < cols) ? a.K[f][l * cols + j] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) Y[tid + 256 * q] = v[q];
     }
-    const int nq = (rows * cols + 1023) / 1024;
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     for (int l = 0; l < inner; ++l) {
+      const double2 x0 = *reinterpret_cast<const double2*>(Xt + l * 64 + 4 * ti);
+      const double2 x1 = *reinterpret_cast<const double2*>(Xt + l * 64 + 4 * ti + 2);
+      const double2 y0 = *reinterpret_cast<const double2*>(Y + l * 64 + 4 * tj);
+      const double2 y1 = *reinterpret_cast<const double2*>(Y + l * 64 + 4 * tj + 2);
+      const double xv[4] = {x0.x, x0.y, x1.x, x1.y};
+      const double yv[4] = {y0.x, y0.y, y1.x, y1.y};
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (q < nq) acc[q] = fma(X[oi[q] * inner + l], Y[l * cols + oj[q]], acc[q]);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(xv[u], yv[v], acc[u][v]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = threadIdx.x + 1024 * q;
-      if (t < rows * cols) Z[t] = acc[q];
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Zt[(4 * tj + v) * 64 + 4 * ti + u] = acc[u][v];
     __syncthreads();
-    double* tmp = X;
-    X = Z;
-    Z = tmp;
+    double* tmp = Xt;
+    Xt = Zt;
+    Zt = tmp;
     inner = cols;
   }
+  __syncthreads();
   const int r_k = a.r_k, r_k1 = a.r_k1, R = r_k * r_k1;
-  for (int t = threadIdx.x; t < rows * inner; t += blockDim.x) {
+  for (int t = tid; t < rows * inner; t += 256) {
     const int i = t / inner, j = t % inner;
     const int b = i / r_k1, b2 = i % r_k1, al = j / r_k, a2 = j % r_k;
-    a.G[(int64_t)(al + b * r_k) * R + (a2 + b2 * r_k)] = X[t];
+    a.G[(int64_t)(al + b * r_k) * R + (a2 + b2 * r_k)] = Xt[j * 64 + i];
   }
 }
 
@@ -152,7 +176,7 @@ hipError_t launch_ring(const RingArgs& a, hipStream_t st) {
     if (f > 0 && a.rows[f] != a.cols[f - 1]) return hipErrorInvalidValue;
   }
   if (a.rows[0] != a.r_k1 * a.r_k1 || a.cols[a.nf - 1] != a.r_k * a.r_k) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_ring, dim3(1), dim3(1024), 3 * 4096 * sizeof(double), st, a);
+  hipLaunchKernelGGL(k_ring, dim3(1), dim3(256), 3 * 4096 * sizeof(double), st, a);
   return hipGetLastError();
 }
 
@@ -331,8 +355,18 @@ __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict_
   const int64_t total = Ik * n;
   const bool bad = (*flags & TRD_FLAG_NOTSPD_BIT) != 0;
   const bool staged = n <= 64;
-  if (staged) {
-    for (int t = threadIdx.x; t < n * n; t += blockDim.x) Cs[t] = Cinv[t];
+  if (staged) {  // 256 threads, at most 16 elements each, all loads in flight first
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      v[q] = t < n * n ? Cinv[t] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      if (t < n * n) Cs[t] = v[q];
+    }
     __syncthreads();
   }
   const double* Cp = staged ? Cs : Cinv;

@@ -39,27 +39,27 @@ __device__ __forceinline__ void put(void* out, void* out_lo, int64_t i, real v) 
 // Output element (a, c) of an item sits at a + rA*c, or at c + rC*a when transposed;
 // positions rA*rC .. out_stride-1 are zero padding.  One thread per output element
 // (consecutive threads: consecutive elements, so the L reads coalesce and the R reads
-// broadcast); 32-bit index arithmetic when the element count allows.
-template <typename real, typename idx_t, bool BF>
-__global__ void k_merge(const real* __restrict__ L, int64_t Ls, const int32_t* __restrict__ Llist,
-                        int64_t nL, int rA, int rB, const real* __restrict__ R, int64_t Rs,
-                        const int32_t* __restrict__ Rlist, int64_t nR, int rC,
-                        void* __restrict__ out, void* __restrict__ out_lo, int64_t out_stride,
-                        int transpose_out) {
-  const idx_t os = (idx_t)out_stride;
-  const idx_t total = (idx_t)(nL * nR) * os;
+// broadcast).  Small element counts: 32-bit indices with multiply-high divisions.
+struct MergeDivs {
+  FastDiv os, nL, rA, rC;
+};
+
+template <typename real, bool BF>
+__global__ void k_merge32(const real* __restrict__ L, int64_t Ls, const int32_t* __restrict__ Llist,
+                          uint32_t nL, int rA, int rB, const real* __restrict__ R, int64_t Rs,
+                          const int32_t* __restrict__ Rlist, uint32_t total, int rC,
+                          void* __restrict__ out, void* __restrict__ out_lo, uint32_t out_stride,
+                          int transpose_out, MergeDivs dv) {
   const int used = rA * rC;
-  const idx_t nLi = (idx_t)nL;
-  for (idx_t t = (idx_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (idx_t)gridDim.x * blockDim.x) {
-    const idx_t item = t / os;
-    const int e = (int)(t - item * os);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const uint32_t item = dv.os.div(t);
+    const int e = (int)(t - item * out_stride);
     real acc = real(0);
     if (e < used) {
       int a, c;
-      if (transpose_out) { c = e % rC; a = e / rC; }
-      else { a = e % rA; c = e / rA; }
-      const idx_t l = item % nLi, j = item / nLi;
+      if (transpose_out) { a = (int)dv.rC.div((uint32_t)e); c = e - a * rC; }
+      else { c = (int)dv.rA.div((uint32_t)e); a = e - c * rA; }
+      const uint32_t j = dv.nL.div(item), l = item - j * nL;
       const real* Lp = L + (Llist ? (int64_t)Llist[l] : (int64_t)l) * Ls;
       const real* Rp = R + (Rlist ? (int64_t)Rlist[j] : (int64_t)j) * Rs;
       for (int b = 0; b < rB; ++b) acc = fma(Lp[a + rA * b], Rp[b + rB * c], acc);
@@ -68,18 +68,114 @@ __global__ void k_merge(const real* __restrict__ L, int64_t Ls, const int32_t* _
   }
 }
 
+// Natural layout with rA, out_stride and the L item stride multiples of 4 (FP32): one
+// thread per 4 consecutive rows a of an output column, one 16-byte L read per b.
+template <bool BF>
+__global__ void k_merge4(const float* __restrict__ L, int64_t Ls, const int32_t* __restrict__ Llist,
+                         uint32_t nL, int rA, int rB, const float* __restrict__ R, int64_t Rs,
+                         const int32_t* __restrict__ Rlist, uint32_t total4, int rC,
+                         void* __restrict__ out, void* __restrict__ out_lo, uint32_t os4,
+                         MergeDivs dv) {
+  const int used = rA * rC;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total4; t += gridDim.x * blockDim.x) {
+    const uint32_t item = dv.os.div(t);
+    const int e = 4 * (int)(t - item * os4);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (e < used) {
+      const int c = (int)dv.rA.div((uint32_t)e);
+      const int a = e - c * rA;
+      const uint32_t j = dv.nL.div(item), l = item - j * nL;
+      const float* Lp = L + (Llist ? (int64_t)Llist[l] : (int64_t)l) * Ls;
+      const float* Rp = R + (Rlist ? (int64_t)Rlist[j] : (int64_t)j) * Rs;
+      for (int b = 0; b < rB; ++b) {
+        const float4 lv = *reinterpret_cast<const float4*>(Lp + a + rA * b);
+        const float rv = Rp[b + rB * c];
+        acc[0] = fmaf(lv.x, rv, acc[0]);
+        acc[1] = fmaf(lv.y, rv, acc[1]);
+        acc[2] = fmaf(lv.z, rv, acc[2]);
+        acc[3] = fmaf(lv.w, rv, acc[3]);
+      }
+    }
+    if constexpr (BF) {  // four bf16 in one 8-byte store (and four remainders)
+      uint16_t hi[4], lo[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        hi[u] = bf16_bits(acc[u]);
+        lo[u] = bf16_bits(acc[u] - __uint_as_float((uint32_t)hi[u] << 16));
+      }
+      reinterpret_cast<uint2*>(out)[t] =
+          uint2{(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
+      if (out_lo)
+        reinterpret_cast<uint2*>(out_lo)[t] = uint2{(uint32_t)lo[0] | ((uint32_t)lo[1] << 16),
+                                                    (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
+    } else {
+      reinterpret_cast<float4*>(out)[t] = float4{acc[0], acc[1], acc[2], acc[3]};
+    }
+  }
+}
+
+template <typename real, bool BF>
+__global__ void k_merge(const real* __restrict__ L, int64_t Ls, const int32_t* __restrict__ Llist,
+                        int64_t nL, int rA, int rB, const real* __restrict__ R, int64_t Rs,
+                        const int32_t* __restrict__ Rlist, int64_t nR, int rC,
+                        void* __restrict__ out, void* __restrict__ out_lo, int64_t out_stride,
+                        int transpose_out) {
+  const int64_t total = nL * nR * out_stride;
+  const int used = rA * rC;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t item = t / out_stride;
+    const int e = (int)(t - item * out_stride);
+    real acc = real(0);
+    if (e < used) {
+      int a, c;
+      if (transpose_out) { c = e % rC; a = e / rC; }
+      else { a = e % rA; c = e / rA; }
+      const int64_t l = item % nL, j = item / nL;
+      const real* Lp = L + (Llist ? (int64_t)Llist[l] : l) * Ls;
+      const real* Rp = R + (Rlist ? (int64_t)Rlist[j] : j) * Rs;
+      for (int b = 0; b < rB; ++b) acc = fma(Lp[a + rA * b], Rp[b + rB * c], acc);
+    }
+    put<real, BF>(out, out_lo, t, acc);
+  }
+}
+
 template <typename real, bool BF>
 static void merge_idx(dim3 g, dim3 b, hipStream_t st, bool small, const ItemRef& L, int64_t nL,
                       int rA, int rB, const ItemRef& R, int64_t nR, int rC, void* out,
                       void* out_lo, int64_t out_stride, int transpose_out) {
-  if (small)
-    hipLaunchKernelGGL((k_merge<real, uint32_t, BF>), g, b, 0, st, (const real*)L.ptr, L.stride,
-                       L.list, nL, rA, rB, (const real*)R.ptr, R.stride, R.list, nR, rC, out,
-                       out_lo, out_stride, transpose_out);
-  else
-    hipLaunchKernelGGL((k_merge<real, int64_t, BF>), g, b, 0, st, (const real*)L.ptr, L.stride,
-                       L.list, nL, rA, rB, (const real*)R.ptr, R.stride, R.list, nR, rC, out,
-                       out_lo, out_stride, transpose_out);
+  if constexpr (sizeof(real) == 4) {
+    if (small && !transpose_out && rA % 4 == 0 && out_stride % 4 == 0 && L.stride % 4 == 0 &&
+        reinterpret_cast<uintptr_t>(L.ptr) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(out) % (BF ? 8 : 16) == 0 &&
+        reinterpret_cast<uintptr_t>(out_lo) % 8 == 0) {
+      MergeDivs dv;
+      dv.os = FastDiv((uint32_t)(out_stride / 4));
+      dv.nL = FastDiv((uint32_t)nL);
+      dv.rA = FastDiv((uint32_t)rA);
+      const uint32_t total4 = (uint32_t)(nL * nR * out_stride / 4);
+      dim3 g4((unsigned)((total4 + 255) / 256 < (1u << 20) ? (total4 + 255) / 256 : (1u << 20)));
+      hipLaunchKernelGGL((k_merge4<BF>), g4, b, 0, st, (const float*)L.ptr, L.stride, L.list,
+                         (uint32_t)nL, rA, rB, (const float*)R.ptr, R.stride, R.list, total4, rC,
+                         out, out_lo, (uint32_t)(out_stride / 4), dv);
+      return;
+    }
+  }
+  if (small) {
+    MergeDivs dv;
+    dv.os = FastDiv((uint32_t)out_stride);
+    dv.nL = FastDiv((uint32_t)nL);
+    dv.rA = FastDiv((uint32_t)rA);
+    dv.rC = FastDiv((uint32_t)rC);
+    hipLaunchKernelGGL((k_merge32<real, BF>), g, b, 0, st, (const real*)L.ptr, L.stride, L.list,
+                       (uint32_t)nL, rA, rB, (const real*)R.ptr, R.stride, R.list,
+                       (uint32_t)(nL * nR * out_stride), rC, out, out_lo, (uint32_t)out_stride,
+                       transpose_out, dv);
+  } else {
+    hipLaunchKernelGGL((k_merge<real, BF>), g, b, 0, st, (const real*)L.ptr, L.stride, L.list, nL,
+                       rA, rB, (const real*)R.ptr, R.stride, R.list, nR, rC, out, out_lo,
+                       out_stride, transpose_out);
+  }
 }
 
 hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRef R, int64_t nR,
@@ -180,15 +276,18 @@ hipError_t launch_sum_partials(int dtype, void* S, int n_ct, int64_t n, hipStrea
 // (St^T U^T of the two-factor split of the gradient); St is the summed row factor of the
 // gradient pass.  U.ptr == nullptr: no B modes, U = identity (r_s = r_k1), D(i_k) = St(i_k).
 // A split-K product: grid (pair tiles, nchunk); thread = one (i_k, a) pair, holding the
-// r_k1 outputs D(i_k)[a, :] in registers while it walks the m_B of its chunk.  The U item
-// of an m_B is the same for the whole group (scalar loads); the S loads of consecutive
-// threads are consecutive.  Partials per chunk go to part[chunk][i_k][a + r_k b].
-template <typename real>
-__global__ __launch_bounds__(256) void k_contract(const real* __restrict__ S, int RRP,
-                                                  int64_t Ik, int64_t nB, int r_k, int r_s,
-                                                  int r_k1, const real* __restrict__ U,
-                                                  int64_t Us, const int32_t* __restrict__ Ulist,
+// r_k1 outputs D(i_k)[a, :] in registers while it walks the m_B of its chunk, with the
+// next m_B's S values (summed over the n_ct column-group partials, pstride apart) loaded
+// one step ahead.  The U item of an m_B is shared through LDS (double buffered, one
+// barrier per m_B).  Partials per chunk go to part[chunk][i_k][a + r_k b].
+template <typename real, int MAXR>
+__global__ __launch_bounds__(256) void k_contract(const real* __restrict__ S, int RRP, int n_ct,
+                                                  int64_t pstride, int64_t Ik, int64_t nB,
+                                                  int r_k, int r_s, int r_k1,
+                                                  const real* __restrict__ U, int64_t Us,
+                                                  const int32_t* __restrict__ Ulist,
                                                   double* __restrict__ part, int nchunk) {
+  __shared__ real Ua[2][MAXR * MAXR];
   const int64_t pa = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = pa < Ik * r_k;
   const int64_t ik = ok ? pa / r_k : 0;
@@ -196,46 +295,95 @@ __global__ __launch_bounds__(256) void k_contract(const real* __restrict__ S, in
   const int chunk = blockIdx.y;
   const int64_t per = (nB + nchunk - 1) / nchunk;
   const int64_t m0 = chunk * per, m1 = min(nB, m0 + per);
-  double acc[kMaxRank];
+  const int US = r_k1 * r_s;
+  double acc[MAXR];
 #pragma unroll
-  for (int b = 0; b < kMaxRank; ++b) acc[b] = 0.0;
-#pragma unroll 2
-  for (int64_t m = m0; m < m1; ++m) {
+  for (int b = 0; b < MAXR; ++b) acc[b] = 0.0;
+  // S values of the first m_B (all r_s of them, summed over the partials), loaded ahead
+  auto load_s = [&](int64_t m, real* sv) {
     const real* sp = S + (ik + Ik * m) * RRP + a;
-    if (U) {
-      const real* up = U + (Ulist ? (int64_t)Ulist[m] : m) * Us;
-      for (int c = 0; c < r_s; ++c) {
-        const double sv = ok ? (double)sp[r_k * c] : 0.0;
+    // all loads of the step are issued before any is used (n_ct <= 4 here)
+    real part_v[4][MAXR];
 #pragma unroll
-        for (int b = 0; b < kMaxRank; ++b)
-          if (b < r_k1) acc[b] = fma(sv, (double)up[b + r_k1 * c], acc[b]);
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < MAXR; ++c)
+        part_v[q][c] = (ok && c < r_s && m < m1 && q < n_ct) ? sp[(int64_t)q * pstride + r_k * c]
+                                                             : real(0);
+#pragma unroll
+    for (int c = 0; c < MAXR; ++c)
+      sv[c] = (part_v[0][c] + part_v[1][c]) + (part_v[2][c] + part_v[3][c]);
+  };
+  // thread t < US carries element t of the U item, one m_B ahead
+  auto load_u = [&](int64_t m) -> real {
+    if (!U || m >= m1 || (int)threadIdx.x >= US) return real(0);
+    return U[(Ulist ? (int64_t)Ulist[m] : m) * Us + threadIdx.x];
+  };
+  real cur[MAXR], nxt[MAXR];
+  load_s(m0, cur);
+  real uval = load_u(m0);
+  for (int64_t m = m0; m < m1; ++m) {
+    const int buf = (int)((m - m0) & 1);
+    if (U && (int)threadIdx.x < US) Ua[buf][threadIdx.x] = uval;  // shared by the group
+    uval = load_u(m + 1);
+    load_s(m + 1, nxt);  // next m_B's values in flight while this one is used
+    __syncthreads();
+    if (U) {
+#pragma unroll
+      for (int c = 0; c < MAXR; ++c) {
+        if (c < r_s) {
+          const double sv = (double)cur[c];
+#pragma unroll
+          for (int b = 0; b < MAXR; ++b)
+            if (b < r_k1) acc[b] = fma(sv, (double)Ua[buf][b + r_k1 * c], acc[b]);
+        }
       }
     } else {
 #pragma unroll
-      for (int b = 0; b < kMaxRank; ++b)
-        if (b < r_k1) acc[b] += ok ? (double)sp[r_k * b] : 0.0;
+      for (int b = 0; b < MAXR; ++b)
+        if (b < r_k1) acc[b] += (double)cur[b];
     }
+#pragma unroll
+    for (int c = 0; c < MAXR; ++c) cur[c] = nxt[c];
   }
   if (ok) {
     double* pp = part + ((int64_t)chunk * Ik + ik) * (r_k * r_k1) + a;
 #pragma unroll
-    for (int b = 0; b < kMaxRank; ++b)
+    for (int b = 0; b < MAXR; ++b)
       if (b < r_k1) pp[r_k * b] = acc[b];
   }
 }
 
-hipError_t launch_contract(int dtype, const void* S, int RRP, int64_t Ik, int64_t nB, int r_k,
-                           int r_s, int r_k1, ItemRef U, double* part, int nchunk,
-                           hipStream_t st) {
-  if (r_k1 > kMaxRank || r_k * r_s > RRP || (!U.ptr && r_s != r_k1)) return hipErrorInvalidValue;
+template <typename real, int MAXR>
+static void contract_r(dim3 g, dim3 b, hipStream_t st, const void* S, int RRP, int n_ct,
+                       int64_t pstride, int64_t Ik, int64_t nB, int r_k, int r_s, int r_k1,
+                       const ItemRef& U, double* part, int nchunk) {
+  hipLaunchKernelGGL((k_contract<real, MAXR>), g, b, 0, st, (const real*)S, RRP, n_ct, pstride,
+                     Ik, nB, r_k, r_s, r_k1, (const real*)U.ptr, U.stride, U.list, part, nchunk);
+}
+
+template <typename real>
+static void contract_real(dim3 g, dim3 b, hipStream_t st, const void* S, int RRP, int n_ct,
+                          int64_t pstride, int64_t Ik, int64_t nB, int r_k, int r_s, int r_k1,
+                          const ItemRef& U, double* part, int nchunk) {
+  const int mr = r_s > r_k1 ? r_s : r_k1;  // unroll bound: the smallest of 4, 8, 16 that fits
+  if (mr <= 4) contract_r<real, 4>(g, b, st, S, RRP, n_ct, pstride, Ik, nB, r_k, r_s, r_k1, U, part, nchunk);
+  else if (mr <= 8) contract_r<real, 8>(g, b, st, S, RRP, n_ct, pstride, Ik, nB, r_k, r_s, r_k1, U, part, nchunk);
+  else contract_r<real, 16>(g, b, st, S, RRP, n_ct, pstride, Ik, nB, r_k, r_s, r_k1, U, part, nchunk);
+}
+
+hipError_t launch_contract(int dtype, const void* S, int RRP, int n_ct, int64_t pstride,
+                           int64_t Ik, int64_t nB, int r_k, int r_s, int r_k1, ItemRef U,
+                           double* part, int nchunk, hipStream_t st) {
+  if (r_k1 > kMaxRank || r_s > kMaxRank || r_k * r_s > RRP || (!U.ptr && r_s != r_k1) ||
+      r_k1 * r_s > 256 || n_ct < 1 || n_ct > 4)
+    return hipErrorInvalidValue;
   const int64_t ntile = (Ik * r_k + 255) / 256;
   dim3 g((unsigned)ntile, (unsigned)nchunk), b(256);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_contract<float>, g, b, 0, st, (const float*)S, RRP, Ik, nB, r_k, r_s,
-                       r_k1, (const float*)U.ptr, U.stride, U.list, part, nchunk);
+    contract_real<float>(g, b, st, S, RRP, n_ct, pstride, Ik, nB, r_k, r_s, r_k1, U, part, nchunk);
   else
-    hipLaunchKernelGGL(k_contract<double>, g, b, 0, st, (const double*)S, RRP, Ik, nB, r_k, r_s,
-                       r_k1, (const double*)U.ptr, U.stride, U.list, part, nchunk);
+    contract_real<double>(g, b, st, S, RRP, n_ct, pstride, Ik, nB, r_k, r_s, r_k1, U, part, nchunk);
   return hipGetLastError();
 }
 

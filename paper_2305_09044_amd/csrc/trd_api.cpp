@@ -723,11 +723,15 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   TRY(ensure_S(ctx, (int64_t)up_nct(up) * L.nrows * sp.RRP));
   TRY(run_pass(ctx, up, stats_dev ? kModeGrad : kModeGradFast, st));
   if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, stats_dev, st));
-  // the column-group partials are first summed by a streaming kernel
-  const int ncg = up_nct(up);
-  if (ncg > 1) CK(launch_sum_partials(ctx->dtype, ctx->S, ncg, L.nrows * sp.RRP, st));
-  CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, Ik, nB, sp.r_k, sp.r_s, sp.r_k1, Uref,
-                     ctx->part_misc, nchunk, st));
+  // a few column-group partials are added by the contraction as it loads S; many are
+  // first summed by a streaming kernel
+  int ncg = up_nct(up);
+  if (ncg > 4) {
+    CK(launch_sum_partials(ctx->dtype, ctx->S, ncg, L.nrows * sp.RRP, st));
+    ncg = 1;
+  }
+  CK(launch_contract(ctx->dtype, ctx->S, sp.RRP, ncg, L.nrows * sp.RRP, Ik, nB, sp.r_k, sp.r_s,
+                     sp.r_k1, Uref, ctx->part_misc, nchunk, st));
   CK(launch_contract_finish(ctx->dtype, ctx->part_misc, nchunk, Ik, sp.r_k * sp.r_k1, ctx->d64,
                             d_out, scale, st));
   if (Uout) *Uout = Uref;

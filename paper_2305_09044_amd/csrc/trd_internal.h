@@ -44,6 +44,23 @@ inline void column_groups(int64_t n_rg, int n_ct, int& n_cg, int& cpg) {
   n_cg = (n_ct + cpg - 1) / cpg;
 }
 
+// Division of 32-bit unsigned numerators by a fixed divisor d >= 1 through a multiply-high
+// (Granlund and Montgomery, 1994): s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1,
+// n / d = (mulhi(n, m) + n) >> s, exact for every 32-bit n.
+struct FastDiv {
+  uint32_t d = 1, m = 1;
+  int s = 0;
+  FastDiv() = default;
+  explicit FastDiv(uint32_t div) : d(div) {
+    s = 0;
+    while ((1ull << s) < d) ++s;
+    m = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    return (uint32_t)(((uint64_t)__umulhi(n, m) + n) >> s);
+  }
+};
+
 // A table of small column-major matrices ("items"), item t at ptr + idx(t) * stride.
 struct ItemRef {
   const void* ptr = nullptr;
@@ -120,9 +137,9 @@ hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* o
                        bool bf16_out = false, void* out_lo = nullptr);
 // in-place fixed-order sum of n_ct partial arrays of n elements into the first
 hipError_t launch_sum_partials(int dtype, void* S, int n_ct, int64_t n, hipStream_t st);
-hipError_t launch_contract(int dtype, const void* S, int RRP, int64_t Ik, int64_t nB, int r_k,
-                           int r_s, int r_k1, ItemRef U, double* part, int nchunk,
-                           hipStream_t st);
+hipError_t launch_contract(int dtype, const void* S, int RRP, int n_ct, int64_t pstride,
+                           int64_t Ik, int64_t nB, int r_k, int r_s, int r_k1, ItemRef U,
+                           double* part, int nchunk, hipStream_t st);
 hipError_t launch_contract_finish(int dtype, const double* part, int nchunk, int64_t Ik, int RRk,
                                   double* d64, void* d_out, double scale, hipStream_t st);
 

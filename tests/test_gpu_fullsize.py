@@ -1,0 +1,160 @@
+"""Parity at the workloads' full sizes, in the configurations bench.py times.
+
+The oracle cannot unfold these tensors, so it computes sampled outputs one at a time from
+the same seeded inputs (built exactly as bench.py builds them):
+  * reconstructed entries (Def. 1) at a uniform sample of positions;
+  * whole gradient rows of eq. (9) from the observed entries of a slice (gradient_row);
+  * the FGMC Gram matrix (eq. 13, cheap at any size) against the explicit sum of
+    Kronecker factors;
+  * RStS index sets (bit-exact) and the complete sketched gradient (eq. 15), whose
+    subtensor the oracle can hold.
+Bars: reconstruction 1e-5 relative; FP32 gradient rows 1e-4 relative Frobenius (a row sums
+about 1e6 FP32 products, so its rounding grows like sqrt(n) 2^-24 ~ 6e-5); the BF16 forms
+as in test_gpu_bf16 (2e-2); Gram 1e-12; index sets exact."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import bench  # noqa: E402
+import synth  # noqa: E402
+from oracle import awrtrd as aw  # noqa: E402
+from oracle import rng as orng  # noqa: E402
+from oracle import tr  # noqa: E402
+from _helpers import rel  # noqa: E402
+
+import paper_2305_09044_amd as trd  # noqa: E402
+
+
+class Full:
+    """One workload at full size: device problem plus host copies for the oracle."""
+
+    def __init__(self, name, seed=0):
+        w, dims, Xd, Pd, mask, xs = bench.build_inputs(name, seed)
+        self.w, self.dims = w, tuple(dims)
+        self.prob = trd.Problem(Xd, Pd, dims, w.ranks)
+        self.Xd, self.Pd, self.xs = Xd, Pd, xs
+        self.X = Xd.cpu().numpy()               # column-major flat, FP32
+        self.mask = mask                        # host, shaped
+        Z = synth.init_cores(dims, w.ranks, seed)
+        self.Z = [z.astype(np.float32).astype(np.float64) for z in Z]
+        self.cores = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(self.Z, np.float32)]
+        self.strides = np.cumprod((1,) + self.dims[:-1])
+        self._rows = {}
+
+    def oracle_row(self, k, i, sigma):
+        key = (k, i, sigma)
+        if key not in self._rows:
+            idx, vals = self.slice_entries(k, i)
+            self._rows[key] = aw.gradient_row(self.Z, k, idx, vals, sigma)
+        return self._rows[key]
+
+    def slice_entries(self, k, i):
+        """Indices (n, N) and values of the observed entries with i_k = i."""
+        sub = np.take(self.mask, i, axis=k)
+        rest = np.argwhere(sub != 0)
+        idx = np.insert(rest, k, i, axis=1).astype(np.int64)
+        lin = idx @ self.strides
+        return idx, self.X[lin].astype(np.float64)
+
+    def close(self):
+        self.prob.close()
+        del self.prob, self.Xd, self.Pd, self.xs, self.cores
+        torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def cfg_prec():
+    f = Full("tr5_60_r8")
+    yield f
+    f.close()
+
+
+def _grad_rows(f, k, rows, sigma, prec):
+    f.prob.set_precision(prec)
+    d, stats = f.prob.grad(f.cores, k, sigma)
+    f.prob.set_precision("native")
+    r, r2 = f.w.ranks[k], f.w.ranks[(k + 1) % len(f.dims)]
+    D = d.cpu().numpy().astype(np.float64).reshape(f.dims[k], r2 * r)
+    return [(D[i], f.oracle_row(k, i, sigma)) for i in rows], stats
+
+
+@pytest.mark.parametrize("prec,bar", [("native", 1e-4), ("bf16x3", 2e-2), ("bf16", 2e-2)])
+def test_precision_workload_gradient_rows(cfg_prec, prec, bar):
+    # 60^5, rank 8, 10% observed: rows of d for a first and a middle core
+    f = cfg_prec
+    sigma = 1.0
+    worst = 0.0
+    for k, rows in ((0, (0, 37)), (2, (59,))):
+        pairs, stats = _grad_rows(f, k, rows, sigma, prec)
+        for got, ref in pairs:
+            e = rel(got, ref)
+            worst = max(worst, e)
+            assert e <= bar, (prec, k, e)
+    print(f"{prec}: worst gradient-row error {worst:.2e}")
+
+
+def test_precision_workload_reconstruction_and_gram(cfg_prec):
+    f = cfg_prec
+    g = np.random.default_rng(7)
+    n = int(np.prod(f.dims))
+    lin = np.sort(g.choice(n, 4096, replace=False)).astype(np.int64)
+    got = f.prob.reconstruct(f.cores, torch.from_numpy(lin).cuda()).cpu().numpy()
+    ref = tr.reconstruct_at(f.Z, lin)
+    assert rel(got, ref) <= 1e-5
+    for k in (0, 3):
+        G = f.prob.fgmc_gram(f.cores, k).cpu().numpy()
+        assert rel(G, aw.gram_fgmc(f.Z, k)) <= 1e-12
+
+
+def test_precision_workload_step_decreases_loss(cfg_prec):
+    # at full size the line search is checked by what it guarantees: a positive step that
+    # lowers the frozen-weight objective, in each timed precision
+    f = cfg_prec
+    sigma = 1.0
+    for prec in ("native", "bf16x3", "bf16"):
+        cores = [c.clone() for c in f.cores]
+        f.prob.set_precision("native")
+        before = float(f.prob.loss_fwd(cores, sigma))
+        f.prob.set_precision(prec)
+        eta, flags = f.prob.step(cores, 1, sigma)
+        f.prob.set_precision("native")
+        after = float(f.prob.loss_fwd(cores, sigma))
+        assert int(flags) == 0 and float(eta) > 0.0, prec
+        assert after < before, (prec, before, after)
+
+
+@pytest.mark.parametrize("name", ["tr4_100_r5", "video_240x320x3x200_r8"])
+def test_sketch_workloads_full_size(name):
+    # RStS at the workloads' sketch sizes: index sets bit-exact, sketched gradient complete
+    f = Full(name)
+    try:
+        sizes = list(f.w.sketch)
+        sigma = 0.5
+        for t, k in ((0, 0), (3, len(f.dims) - 1)):
+            got = trd.trd_sample_sketch(11, t, k, f.dims, sizes)
+            ref = orng.sketch_indices(11, t, k, f.dims, sizes)
+            for j in range(len(f.dims)):
+                assert got[j].cpu().numpy().tolist() == ref[j]
+            sk, _ = trd.make_sketch(sizes, 11, t)
+            d, stats = f.prob.grad(f.cores, k, sigma, sketch=sk)
+            ix = np.ix_(*[np.asarray(s, dtype=np.int64) for s in ref])
+            lin = np.zeros([len(s) for s in ref], dtype=np.int64)
+            for j, s in enumerate(ref):
+                shape = [1] * len(f.dims)
+                shape[j] = len(s)
+                lin = lin + (np.asarray(s, dtype=np.int64) * f.strides[j]).reshape(shape)
+            Xs = f.X[lin].astype(np.float64)
+            Ps = f.mask[ix]
+            cs = [z[:, np.asarray(s), :] for z, s in zip(f.Z, ref)]
+            _, info = aw.core_update(Xs, Ps, cs, k, sigma)
+            r, r2 = f.w.ranks[k], f.w.ranks[(k + 1) % len(f.dims)]
+            D = d.cpu().numpy().astype(np.float64).reshape(f.dims[k], r2 * r)
+            assert rel(D, info.d) <= 1e-4, (name, t, k)
+            assert int(stats[2].item()) == int(Ps.sum())
+    finally:
+        f.close()

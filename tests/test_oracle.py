@@ -392,3 +392,18 @@ def test_sizes_from_J():
     assert orng.sizes_from_J(30000, (240, 320, 3, 200)) == [32, 32, 3, 32]
     assert orng.sizes_from_J(8000, (100, 100, 100, 100)) == [20, 20, 20, 20]
     assert orng.sizes_from_J(27, (9, 9, 9, 9)) == [3, 3, 3, 3]
+
+
+@pytest.mark.parametrize("dims,ranks,k", [((6, 5, 7, 4), (2, 3, 2, 3), 1),
+                                         ((5, 6, 4), (3, 2, 4), 2)])
+def test_gradient_row_matches_unfolded_gradient(dims, ranks, k):
+    # eq. (9) one row at a time (the form used on tensors too large to unfold) equals the
+    # explicit (W o P o E) A of the full update, row by row and with non-square ranks
+    Z, P, X = _masked_problem(dims, ranks, 5, rho=0.5)
+    sigma = 0.7
+    _, info = aw.core_update(X, P, Z, k, sigma)
+    obs = np.argwhere(P.astype(bool))
+    for i in range(dims[k]):
+        sel = obs[obs[:, k] == i]
+        row = aw.gradient_row(Z, k, sel, X[tuple(sel.T)], sigma, chunk=7)
+        np.testing.assert_allclose(row, info.d[i], rtol=1e-12, atol=1e-12)
