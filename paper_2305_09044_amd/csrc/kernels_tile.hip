@@ -16,9 +16,11 @@
 // and Xhat adds the products t_hi v_lo and t_lo v_hi, so the reconstruction (and the
 // residual) carries about 16 significant bits instead of 8; the gradient contraction
 // stays a single bf16 product.
-// A work-group (4 waves = 4 block rows) walks a group of column tiles and keeps its S
-// accumulators in registers; the V^T items of the current tile are staged transposed in
-// LDS as the A operand of step 3.
+// A work-group (4 waves = 4 block rows) walks a group of column tiles; each wave keeps its
+// S accumulators in registers and works on its own LDS tiles (no work-group barrier in
+// the walk).  The column table is read in operand-fragment order (k_fragments): every
+// operand load of a wave is one contiguous kilobyte, for the reconstruction (V^T items)
+// and for the gradient products (V items, the transposed order).
 #include "trd_internal.h"
 
 namespace trd {
@@ -156,8 +158,9 @@ template <int K, bool SPLIT> struct TileRounds {
 };
 
 size_t tpass_lds(int mode, int K, int CW) {
-  if (mode == kModeGrad || mode == kModeGradFast)
-    return (size_t)kXBytes + kYBytes + (size_t)K * (CW + 8) * 2;
+  (void)K;
+  (void)CW;
+  if (mode == kModeGrad || mode == kModeGradFast) return (size_t)kXBytes + kYBytes;
   if (mode == kModeLS) return 2 * (size_t)kXBytes;
   return (size_t)kXBytes;
 }
@@ -171,7 +174,6 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   constexpr bool kLS = MODE == kModeLS;
   constexpr bool kStats = MODE == kModeGrad || MODE == kModeLoss;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int CWP = a.CW + 8;
   // the wave index is uniform over the wave: keep it (and everything derived from it:
   // block row, block offsets, loop bounds) in scalar registers
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -179,7 +181,6 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   float* Xs = reinterpret_cast<float*>(smem_raw) + w * kXTile;
   float* Qs = reinterpret_cast<float*>(smem_raw + kXBytes) + w * kXTile;             // LS
   uint16_t* Ys = reinterpret_cast<uint16_t*>(smem_raw + kXBytes) + w * kYTile;       // grad
-  uint16_t* Vc = reinterpret_cast<uint16_t*>(smem_raw + kXBytes + kYBytes);          // grad
 
   const int64_t wg = blockIdx.x;
   const int64_t cg = wg / a.n_rg, g = wg % a.n_rg;
@@ -214,6 +215,10 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     }
   }
 
+  // Wait for the table operands here, on every path: left pending into the chunk loop,
+  // they make its first products wait for every load in flight, prefetches included.
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+
   const double sig = *a.sigma;
   const bool ls_limit = isinf(sig);
   const float inv2s2 = ls_limit ? 0.f : (float)(0.5 / (sig * sig));
@@ -230,12 +235,13 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 
   // one observed entry: x, in-block position p; `valid` false for lanes past the block's
-  // entries (their p is masked into the tile, their y goes to the tile's padding column
-  // and their sums are dropped).  No branches, so a group of rounds issues its LDS reads
+  // entries (their p belongs to a later block or the zero slack, their y goes to the
+  // tile's padding column and their sums are dropped).  No branches, so a group of rounds issues its LDS reads
   // together.  In the least-squares limit k2 = 0 and the weight is exactly 1.
   auto entry = [&](float x, uint32_t p, bool valid, int64_t idx) {
-    p &= 2047u;
-    const int r = (int)(p >> 5), c = (int)(p & 31u);
+    // bits 0..10 of p: the position (< 2048 for every slot read: positions of this or a
+    // later block, or zero slack); the bits above are ignored
+    const int r = (int)((p >> 5) & 63u), c = (int)(p & 31u);
     const float xh = Xs[r * kXS + c];
     const float e = x - xh;
     const float wgt = __builtin_amdgcn_exp2f(-(e * e * k2));
@@ -263,22 +269,39 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     }
   };
 
-  // Software pipeline over the chunks, unrolled by two so that the two register sets
-  // swap roles without copies: at the top of a chunk the next chunk's entries and
-  // V^T-item operands are loaded into the idle set, so they have a whole chunk to
-  // arrive.  The value / position arrays and the bf16 column table carry slack
+  // Software pipeline over the chunks, unrolled by three so that three register sets of
+  // entries rotate without copies: at the top of a chunk the entries two chunks ahead
+  // are loaded into the idle set, so they have two whole chunks to arrive.  The value / position arrays and the bf16 column table carry slack
   // (>= 64 kR + 64 entries, >= 64 items) and the offset index is clamped to the walk, so
   // these loads need no bounds branch; what they read past a block's end is never used.
+  // Positions are read as the aligned 32-bit word that holds them and shifted at their
+  // use: a 16-bit load would be widened right after it arrives, which makes the chunk
+  // wait for its own prefetch.
   struct Set {
     float x[kR];
-    uint32_t p[kR];
+    uint32_t pw[kR];
+    uint32_t sh;  // 16 when the position is the word's upper half
   };
   const int64_t bb = rb * a.n_chunks;
+  // Block offsets of this wave's walk (at most 64 values, gc_beg .. gc_end): lane i holds
+  // boff[bb + gc_beg + i] in a vector register and a chunk reads its offset back with
+  // readlane.  A scalar load here would sit in the LDS-wait of every chunk (both are
+  // counted by lgkmcnt); the vector load is waited for once.
+  const int64_t bwin = (rb_ok && gc_beg < gc_end) ? a.boff[bb + min(gc_beg + l, gc_end)] : 0;
+  auto boff_at = [&](int64_t gc) -> int64_t {  // gc in [gc_beg, gc_end]
+    const int i = (int)(gc - gc_beg);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bwin, i);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)bwin >> 32), i);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+  };
+  const uint32_t* posw = reinterpret_cast<const uint32_t*>(a.pos);
   auto load_set = [&](Set& S, int64_t bo) {
+    S.sh = (uint32_t)((bo + l) & 1) * 16u;  // parity of bo + 64 t + l
+    const int64_t w0 = (bo + l) >> 1;         // word of bo + 64 t + l: w0 + 32 t
 #pragma unroll
     for (int t = 0; t < kR; ++t) {
       S.x[t] = a.vals[bo + 64 * t + l];
-      S.p[t] = a.pos[bo + 64 * t + l];
+      S.pw[t] = posw[w0 + 32 * t];
     }
   };
   // A operand of the reconstruction (V^T items of one chunk): loaded for the next chunk
@@ -288,53 +311,38 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   auto load_av = [&](int64_t gc) {
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      av[s] = *reinterpret_cast<const bf16x8*>(a.V + (gc * 32 + li) * K + s * 16 + h * 8);
+      av[s] = *reinterpret_cast<const bf16x8*>(a.Vf + gc * 32 * K + s * 512 + l * 8);
       if constexpr (SPLIT)
-        avlo[s] = *reinterpret_cast<const bf16x8*>(a.V_lo + (gc * 32 + li) * K + s * 16 + h * 8);
+        avlo[s] = *reinterpret_cast<const bf16x8*>(a.Vf_lo + gc * 32 * K + s * 512 + l * 8);
     }
   };
 
-  constexpr int KV = K / 8;  // 16-byte vectors per table item
+  auto clear_y = [&]() {
+    uint4* yz = reinterpret_cast<uint4*>(Ys);
+#pragma unroll
+    for (int i = 0; i < kYTile * 2 / 16 / 64; ++i) yz[l + 64 * i] = uint4{0u, 0u, 0u, 0u};
+  };
+
+  // A operand of the gradient product (V^T rows of one chunk), read from the transposed
+  // table: loaded for the next chunk right after the current chunk's products
+  bf16x8 aw[kGrad ? 2 : 1][kGrad ? MT : 1];
+  auto load_aw = [&](int64_t gc) {
+    if constexpr (kGrad) {
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          aw[s2][mt] = *reinterpret_cast<const bf16x8*>(a.VTf + gc * 32 * K +
+                                                        (s2 * MT + mt) * 512 + l * 8);
+    }
+  };
+
   // [bo_cur, bo_end): entries of the current chunk; bo_nend: end of the next one
   int64_t bo_cur = 0, bo_end = 0, bo_nend = 0;
-  auto step = [&](int64_t gc, const Set& C, Set& N) {
-    const int cc = (int)((gc - gc_beg) % a.n_chpt);  // chunk inside the current tile
-    if constexpr (kGrad) {
-      if (cc == 0) {  // new column tile: every wave is past the old one, restage V^T items
-        __syncthreads();
-        const int64_t col0 = gc * 32;
-        const int nct = (int)min((int64_t)a.CW, a.ncols - col0);
-        const int nvec = a.CW * KV;
-        for (int i0 = 0; i0 < nvec; i0 += 4 * 256) {
-          uint4 buf[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + 256 * u + threadIdx.x;
-            const int c = i % a.CW, jv = i / a.CW;
-            buf[u] = uint4{0u, 0u, 0u, 0u};
-            if (i < nvec && c < nct)
-              buf[u] = *reinterpret_cast<const uint4*>(a.V + (col0 + c) * K + 8 * jv);
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + 256 * u + threadIdx.x;
-            if (i < nvec) {
-              const int c = i % a.CW, jv = i / a.CW;
-              const uint32_t wv[4] = {buf[u].x, buf[u].y, buf[u].z, buf[u].w};
-#pragma unroll
-              for (int e = 0; e < 8; ++e)
-                Vc[(8 * jv + e) * CWP + c] = (uint16_t)(wv[e >> 1] >> ((e & 1) * 16));
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
+  auto step = [&](int64_t gc, const Set& C, Set& N) {  // N: the set for chunk gc + 2
     if (!rb_ok) return;  // uniform over the wave; it still joins every tile barrier
 
-    // prefetch the next chunk's entries (offset bo_end <= nobs)
-    load_set(N, bo_end);
-    const int64_t bo_nn = a.boff[bb + min(gc + 3, gc_end)];
+    const int64_t bo_nn = boff_at(min(gc + 3, gc_end));
 
     // 1. Xhat^T (and Q^T) of this chunk
     floatx16 xacc[2] = {floatx16{}, floatx16{}};
@@ -353,8 +361,11 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
           qacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], thb[n][s], qacc[n], 0, 0, 0);
       }
     }
-    // the next chunk's operands (chunk index gc + 1 <= n_chunks: within the table slack)
+    // the next chunk's operands (chunk index gc + 1 <= n_chunks: within the table slack),
+    // then the entries two chunks ahead (offset bo_nend <= nobs).  In this order the wait
+    // for the operands at the next chunk's products leaves the entry loads in flight.
     load_av(gc + 1);
+    load_set(N, bo_nend);
 
     // 2. spill Xhat (and Q) to LDS as [row][col]; clear the y tile
     // accumulator v of n-tile n: col 8 (v/4) + 4 h + v%4, row 32 n + li
@@ -372,14 +383,10 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
         }
       }
     }
-    if constexpr (kGrad) {
-      uint4* yz = reinterpret_cast<uint4*>(Ys);
-#pragma unroll
-      for (int i = 0; i < kYTile * 2 / 16 / 64; ++i) yz[l + 64 * i] = uint4{0u, 0u, 0u, 0u};
-    }
     wave_sync();
 
-    // 3. the observed entries of the block, four rounds of 64 at a time
+    // 3. the observed entries of the block, four rounds of 64 at a time (the y tile is
+    // all zero here: cleared before the loop and after every chunk)
     const int nent = (int)(bo_end - bo_cur);
 #pragma unroll
     for (int t0 = 0; t0 < kR; t0 += 4) {
@@ -387,7 +394,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
 #pragma unroll
         for (int t = t0; t < t0 + 4; ++t) {
           const int i = 64 * t + l;
-          entry(C.x[t], C.p[t], i < nent, bo_cur + i);
+          entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i);
         }
       }
     }
@@ -409,37 +416,61 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
         for (int n = 0; n < 2; ++n)
           yb[n] = *reinterpret_cast<const bf16x8*>(Ys + (32 * n + li) * kYS + 16 * s2 + 8 * h);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const bf16x8 aw = *reinterpret_cast<const bf16x8*>(Vc + (32 * mt + li) * CWP + cc * 32 +
-                                                             16 * s2 + 8 * h);
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int n = 0; n < 2; ++n)
-            sacc[mt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, yb[n], sacc[mt][n], 0, 0, 0);
+            sacc[mt][n] =
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[s2][mt], yb[n], sacc[mt][n], 0, 0, 0);
+      }
+      // the next chunk's operands (chunk gc + 1 <= n_chunks: inside the table's padding)
+      load_aw(gc + 1);
+      // clear the y tile for the next chunk (LDS accesses of a wave complete in order, so
+      // these stores follow the reads above): only the positions this chunk wrote, unless
+      // the block had more entries than the register rounds hold
+      if (nent <= 64 * kR) {
+#pragma unroll
+        for (int t0 = 0; t0 < kR; t0 += 4) {
+          if (64 * t0 < nent) {
+#pragma unroll
+            for (int t = t0; t < t0 + 4; ++t) {
+              const uint32_t p = C.pw[t] >> C.sh;
+              if (64 * t + l < nent) Ys[((p >> 5) & 63u) * kYS + (p & 31u)] = 0;
+            }
+          }
         }
+      } else {
+        clear_y();
       }
     }
-    wave_sync();  // tile reads done before the next chunk overwrites them
+    wave_sync();  // tile reads (and clears) done before the next chunk writes the tiles
 
     bo_cur = bo_end;
     bo_end = bo_nend;
     bo_nend = bo_nn;
   };
 
-  Set A, B;
+  Set A, B, C;
+  if constexpr (kGrad) clear_y();
   if (rb_ok && gc_beg < gc_end) {
-    bo_cur = a.boff[bb + gc_beg];
-    bo_end = a.boff[bb + gc_beg + 1];
-    bo_nend = a.boff[bb + min(gc_beg + 2, gc_end)];
+    bo_cur = boff_at(gc_beg);
+    bo_end = boff_at(gc_beg + 1);
+    bo_nend = boff_at(min(gc_beg + 2, gc_end));
+    load_aw(gc_beg);
+    load_av(gc_beg);  // before the entries, as inside the loop, so that the counted waits
+                      // agree on both paths
     load_set(A, bo_cur);
-    load_av(gc_beg);
+    load_set(B, bo_end);
   }
-  for (int64_t gc = gc_beg; gc < gc_end; gc += 2) {
-    step(gc, A, B);
+  for (int64_t gc = gc_beg; gc < gc_end; gc += 3) {
+    step(gc, A, C);
     if (gc + 1 < gc_end) step(gc + 1, B, A);
+    if (gc + 2 < gc_end) step(gc + 2, C, B);
   }
 
   if constexpr (kGrad) {
-    // S^T accumulator: lane l holds row 32 n + li of the block, j = 32 mt + 8 (v/4) + 4h + v%4
+    // S^T accumulator: lane l holds row 32 n + li of the block and, in register v,
+    // j = 32 mt + 8 (v/4) + 4h + v%4: four consecutive j per group of four registers,
+    // stored as one 16-byte vector (RRP is a multiple of 4, so j0 < RRP covers j0 + 3)
 #pragma unroll
     for (int n = 0; n < 2; ++n) {
       const int64_t row = rb * 64 + 32 * n + li;
@@ -448,9 +479,12 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int j = mt * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-          if (j < a.RRP) sp[j] = sacc[mt][n][v];
+        for (int q = 0; q < 4; ++q) {
+          const int j0 = mt * 32 + 8 * q + 4 * h;
+          if (j0 < a.RRP)
+            *reinterpret_cast<float4*>(sp + j0) =
+                float4{sacc[mt][n][4 * q], sacc[mt][n][4 * q + 1], sacc[mt][n][4 * q + 2],
+                       sacc[mt][n][4 * q + 3]};
         }
     }
   }
@@ -478,6 +512,58 @@ int tile_k(int RR) { return (RR + 31) / 32 * 32; }
 
 // column-tile width of the gradient pass: the bf16 V^T tile fills what the per-wave
 // tiles leave of half the CU's LDS (two work-groups per CU)
+// Fragment order of the column table, per 32-column chunk g (columns past ncols are 0):
+//   Vf  [g][s < K/16][lane][8]:        V[32 g + lane % 32][16 s + 8 (lane / 32) + i]
+//   VTf [g][s2 < 2][mt < K/32][lane][8]: V[32 g + 16 s2 + 8 (lane / 32) + i][32 mt + lane % 32]
+// i.e. the A operands of the reconstruction and gradient products exactly as the lanes
+// hold them, so that a wave reads each operand as one contiguous kilobyte.
+__global__ __launch_bounds__(256) void k_fragments(const uint16_t* __restrict__ V, int64_t ncols,
+                                                   int K, uint16_t* __restrict__ Vf,
+                                                   uint16_t* __restrict__ VTf) {
+  __shared__ __align__(16) uint16_t tile[32 * (128 + 8)];  // [column][k], row stride K + 8
+  const int ks = K + 8;
+  const int64_t g = blockIdx.x;
+  const int64_t c0 = g * 32;
+  const int kv = K / 8;
+  for (int e = threadIdx.x; e < 32 * kv; e += 256) {
+    const int c = e / kv, j = e - c * kv;
+    uint4 u = uint4{0u, 0u, 0u, 0u};
+    if (c0 + c < ncols) u = *reinterpret_cast<const uint4*>(V + (c0 + c) * K + 8 * j);
+    *reinterpret_cast<uint4*>(tile + c * ks + 8 * j) = u;
+  }
+  __syncthreads();
+  const int64_t base = g * 32 * K;
+  const int nvec = 4 * K;  // 16-byte vectors per chunk, in either order
+  for (int e = threadIdx.x; e < nvec; e += 256) {
+    const int l = e & 63, li = l & 31, h = l >> 5;
+    {  // Vf: e = s * 64 + lane
+      const int s = e >> 6;
+      *reinterpret_cast<uint4*>(Vf + base + 8 * e) =
+          *reinterpret_cast<const uint4*>(tile + li * ks + 16 * s + 8 * h);
+    }
+    if (VTf) {  // VTf: e = (s2 * MT + mt) * 64 + lane
+      const int MT = K / 32;
+      const int q = e >> 6, s2 = q / MT, mt = q - s2 * MT;
+      uint32_t w[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 16 * s2 + 8 * h + 2 * i;
+        w[i] = (uint32_t)tile[c * ks + 32 * mt + li] | ((uint32_t)tile[(c + 1) * ks + 32 * mt + li] << 16);
+      }
+      *reinterpret_cast<uint4*>(VTf + base + 8 * e) = uint4{w[0], w[1], w[2], w[3]};
+    }
+  }
+}
+
+hipError_t launch_fragments(const uint16_t* V, int64_t ncols, int K, uint16_t* Vf, uint16_t* VTf,
+                            hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  if (K <= 0 || K > 128 || K % 32 != 0) return hipErrorInvalidValue;
+  const int64_t nch = (ncols + 31) / 32 + 1;  // the padding chunk included
+  hipLaunchKernelGGL(k_fragments, dim3((unsigned)nch), dim3(256), 0, st, V, ncols, K, Vf, VTf);
+  return hipGetLastError();
+}
+
 int64_t tile_cw(int K) {
   int64_t budget = g_lds_max >= 2 * 81920 ? 81920 - 1024 : g_lds_max - 1024;
   int64_t cw = (budget - kXBytes - kYBytes) / (2 * K) - 8;
@@ -506,17 +592,22 @@ static hipError_t launch_k(int mode, const TPassArgs& a, hipStream_t st) {
 
 template <int K>
 static hipError_t launch_ks(int mode, const TPassArgs& a, hipStream_t st) {
-  return (a.T_lo && a.V_lo) ? launch_k<K, true>(mode, a, st) : launch_k<K, false>(mode, a, st);
+  return (a.T_lo && a.Vf_lo) ? launch_k<K, true>(mode, a, st) : launch_k<K, false>(mode, a, st);
 }
 
 hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {
   if (a.n_rg * a.n_cg <= 0 || a.n_chunks <= 0) return hipSuccess;
   // the grid and chunk walk must cover exactly the layout the pass indexes
-  if ((a.T_lo == nullptr) != (a.V_lo == nullptr)) return hipErrorInvalidValue;
+  if ((a.T_lo == nullptr) != (a.Vf_lo == nullptr)) return hipErrorInvalidValue;
   if (a.CW % 32 != 0 || a.n_chpt != a.CW / 32 || a.cpg < 1 || a.n_rb > 4 * a.n_rg ||
+      (int64_t)a.cpg * a.n_chpt > 63 ||
       (int64_t)a.n_cg * a.cpg * a.n_chpt < a.n_chunks ||
       (int64_t)(a.n_cg - 1) * a.cpg * a.n_chpt >= a.n_chunks || a.n_chunks * 32 < a.ncols ||
       a.n_rb * 64 < a.nrows || a.RRP > K)
+    return hipErrorInvalidValue;
+  // the fragment tables hold n_chunks + 1 chunks (tile_frag_elems), the passes read one
+  // chunk ahead; the gradient products need the transposed one
+  if (a.Vf == nullptr || ((mode == kModeGrad || mode == kModeGradFast) && a.VTf == nullptr))
     return hipErrorInvalidValue;
   switch (K) {
     case 32: return launch_ks<32>(mode, a, st);

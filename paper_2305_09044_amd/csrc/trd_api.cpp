@@ -57,7 +57,9 @@ struct trd_ctx {
   int prec = TRD_PREC_NATIVE;     // precision of the entry passes
   uint16_t* Tb = nullptr; uint16_t* THb = nullptr; uint16_t* Vb = nullptr;
   uint16_t* Tb_lo = nullptr; uint16_t* Vb_lo = nullptr;  // split (BF16X3) remainders
-  int64_t cap_Tb = 0, cap_Vb = 0, cap_Tlo = 0, cap_Vlo = 0;
+  // Vb (and Vb_lo) in operand-fragment order, and Vb transposed in fragment order
+  uint16_t* Vf = nullptr; uint16_t* Vf_lo = nullptr; uint16_t* VTf = nullptr;
+  int64_t cap_Tb = 0, cap_Vb = 0, cap_Tlo = 0, cap_Vlo = 0, cap_Vf = 0, cap_Vflo = 0;
 
   // tables and work buffers (sized for the largest core and sketch)
   void* T = nullptr; void* TH = nullptr; void* V = nullptr; void* S = nullptr;
@@ -411,6 +413,10 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   T.n_rb = (T.nrows + 63) / 64;
   T.n_rg = (T.n_rb + 3) / 4;
   column_groups(T.n_rg, T.n_ct, T.n_cg, T.cpg);
+  if (T.cpg * T.n_chpt > 63) {  // a wave's walk keeps its block offsets in one register
+    T.cpg = std::max(1, 63 / T.n_chpt);
+    T.n_cg = (T.n_ct + T.cpg - 1) / T.cpg;
+  }
   T.n_blocks = T.n_rb * T.n_chunks;
   if ((int64_t)tpass_lds(kModeGradFast, T.K, T.CW) > g_lds_max)
     return fail(ctx, TRD_EUNSUPPORTED, "matrix-core pass does not fit the device LDS");
@@ -527,6 +533,18 @@ int build_rowtable(trd_ctx* ctx, const Update& up, const void* left, const ItemR
   return TRD_OK;
 }
 
+// the bf16 column table of the matrix-core passes in operand-fragment order (and its
+// transpose; the split remainder without)
+int fragment_coltable(trd_ctx* ctx, const Update& up, hipStream_t st) {
+  const TLayout& TL = *up.TL;
+  const bool split = ctx->prec == TRD_PREC_BF16X3;
+  const int64_t nf = tile_frag_elems(TL.ncols, TL.K);
+  if (nf > ctx->cap_Vf || (split && nf > ctx->cap_Vflo)) return TRD_ESTATE;
+  CK(launch_fragments(ctx->Vb, TL.ncols, TL.K, ctx->Vf, ctx->VTf, st));
+  if (split) CK(launch_fragments(ctx->Vb_lo, TL.ncols, TL.K, ctx->Vf_lo, nullptr, st));
+  return TRD_OK;
+}
+
 // V^T(m_C): product of the C cores, stored transposed (a + r_k*c) and padded to RRP
 int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hipStream_t st) {
   const Split& sp = up.sp;
@@ -549,6 +567,7 @@ int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hip
   }
   if (sp.q == 1) {
     CK(launch_pack(ctx->dtype, L, nL, r0, rB, Vout, Vstride, 1, st, bf, Vlo));
+    if (bf) TRY(fragment_coltable(ctx, up, st));
     return TRD_OK;
   }
   void* bufs[2] = {ctx->chainA, ctx->chainB};
@@ -566,6 +585,7 @@ int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hip
     nL *= up.counts[m];
     rB = rC;
   }
+  if (bf) TRY(fragment_coltable(ctx, up, st));
   return TRD_OK;
 }
 
@@ -613,18 +633,27 @@ int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStr
     TRY(alloc_n(ctx, &ctx->Tb_lo, nrows * K));
     ctx->cap_Tlo = nrows * K;
   }
-  // column tables: slack of one column tile past the last column (the MFMA pass reads
-  // whole chunks ahead); zero filled once (later tables leave only finite values behind)
-  const int64_t n = ncols * K + tile_cw(K) * (int64_t)K + 64 * K;
+  // column tables as the builders write them ([ncols][K]); the passes read the
+  // fragment-order copies below
   if (ncols * K > ctx->cap_Vb) {
-    TRY(alloc_n(ctx, &ctx->Vb, n));
-    CK(launch_zero(ctx->Vb, (size_t)n * sizeof(uint16_t), st));
+    TRY(alloc_n(ctx, &ctx->Vb, ncols * K));
     ctx->cap_Vb = ncols * K;
   }
   if (split && ncols * K > ctx->cap_Vlo) {
-    TRY(alloc_n(ctx, &ctx->Vb_lo, n));
-    CK(launch_zero(ctx->Vb_lo, (size_t)n * sizeof(uint16_t), st));
+    TRY(alloc_n(ctx, &ctx->Vb_lo, ncols * K));
     ctx->cap_Vlo = ncols * K;
+  }
+  // fragment-order copies read by the matrix-core passes (written whole, padding
+  // included, after every column table)
+  const int64_t nf = tile_frag_elems(ncols, K);
+  if (nf > ctx->cap_Vf) {
+    TRY(alloc_n(ctx, &ctx->Vf, nf));
+    TRY(alloc_n(ctx, &ctx->VTf, nf));
+    ctx->cap_Vf = nf;
+  }
+  if (split && nf > ctx->cap_Vflo) {
+    TRY(alloc_n(ctx, &ctx->Vf_lo, nf));
+    ctx->cap_Vflo = nf;
   }
   return TRD_OK;
 }
@@ -637,10 +666,11 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   memset(&a, 0, sizeof(a));
   a.T = ctx->Tb;
   a.TH = ctx->THb;
-  a.V = ctx->Vb;
+  a.Vf = ctx->Vf;
+  a.VTf = ctx->VTf;
   if (ctx->prec == TRD_PREC_BF16X3) {
     a.T_lo = ctx->Tb_lo;
-    a.V_lo = ctx->Vb_lo;
+    a.Vf_lo = ctx->Vf_lo;
   }
   a.S = (float*)ctx->S;
   a.boff = TL.boff;

@@ -235,9 +235,13 @@ struct TLayout {
 struct TPassArgs {
   const uint16_t* T;     // [nrows][K] bf16
   const uint16_t* TH;    // [nrows][K] bf16 (line search)
-  const uint16_t* V;     // [ncols][K] bf16
+  // column table in operand-fragment order, one 32-column chunk after another (zero past
+  // the last column, one chunk of padding at the end): Vf for the reconstruction
+  // products, VTf (the transpose) for the gradient products, Vf_lo the split remainder
+  const uint16_t* Vf;
+  const uint16_t* VTf;
   const uint16_t* T_lo;  // split tables (remainders), or nullptr
-  const uint16_t* V_lo;
+  const uint16_t* Vf_lo;
   float* S;              // [n_cg][nrows][RRP] per-column-group partials
   const int64_t* boff;
   const float* vals;
@@ -254,6 +258,12 @@ constexpr int64_t kTileSlack = 64 * 16 + 64;
 int tile_k(int RR);
 int64_t tile_cw(int K);
 size_t tpass_lds(int mode, int K, int CW);
+// elements of a fragment-order column table: whole chunks of 32 columns plus one chunk
+// that the passes read ahead
+inline int64_t tile_frag_elems(int64_t ncols, int K) { return ((ncols + 31) / 32 + 1) * 32 * K; }
+// V [ncols][K] bf16 -> Vf (and VTf unless nullptr) in fragment order, padding included
+hipError_t launch_fragments(const uint16_t* V, int64_t ncols, int K, uint16_t* Vf, uint16_t* VTf,
+                            hipStream_t st);
 hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* X, int dtype,
                              bool fill, hipStream_t st);
 hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st);
