@@ -2,7 +2,8 @@
 //
 // The observed entries of a core-k matrix (rows = (i_k, first subchain modes), cols =
 // the rest) are grouped in blocks of 64 rows x 32 columns.  A block stores its observed
-// values and their in-block positions p = 32 r + c (r < 64, c < 32), in increasing p.
+// values and their in-block positions in increasing (r, c) order (r < 64, c < 32), each
+// as the index 36 r + c of the entry in the per-wave LDS tiles (row stride 36).
 // One wave owns a 64-row block row and walks its blocks (32-column chunks):
 //   1. Xhat^T (32 cols x 64 rows) = V^T-items (32 x K) . T-items^T (K x 64) on the
 //      matrix cores (Thm. 1): bf16 operands, FP32 accumulation, spilled to LDS;
@@ -26,6 +27,9 @@
 namespace trd {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// row stride (elements) of the per-wave LDS tiles, and so of the stored positions
+constexpr int kTS = 36;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // order LDS accesses among the lanes of one wave (the tiles below are per wave)
@@ -55,9 +59,9 @@ static TileArgs targs(const TLayout& L) {
   return a;
 }
 
-// Block b = rb * n_chunks + ch, one wave per block.  Round t covers positions
-// p = 64 t + lane (row 2 t + lane / 32, column lane % 32), so the ballot of a round lists
-// its observed entries in increasing p.  Count pass (FILL = false): per-block counts;
+// Block b = rb * n_chunks + ch, one wave per block.  Round t covers p = 64 t + lane
+// (row 2 t + lane / 32, column lane % 32), so the ballot of a round lists its observed
+// entries in increasing (r, c).  Count pass (FILL = false): per-block counts;
 // fill pass: values and positions at boff[b] onwards.
 template <typename real, bool FILL>
 __global__ __launch_bounds__(256) void k_tblock(TileArgs a, const uint8_t* __restrict__ mask,
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(256) void k_tblock(TileArgs a, const uint8_t* __res
       if (obs) {
         const int pre = __popcll(bal & ((1ull << l) - 1ull));
         a.vals[out + pre] = (float)X[off];
-        a.pos[out + pre] = (uint16_t)p;
+        a.pos[out + pre] = (uint16_t)((p >> 5) * kTS + (p & 31));
       }
       out += __popcll(bal);
     } else {
@@ -144,10 +148,12 @@ hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* 
 
 // ---------------------------------------------------------------- the MFMA pass
 
-// Per-wave LDS tiles.  Row strides are odd multiples of 16 bytes, so the 16-byte accesses
-// of eight consecutive rows by eight lanes fall in distinct banks.
-constexpr int kXS = 36;                 // f32 stride of the xhat (and q) tile
-constexpr int kYS = 40;                 // bf16 stride of the y tile
+// Per-wave LDS tiles, both with row stride kTS, so that one stored position indexes
+// either.  The f32 rows (144 bytes, an odd multiple of 16) put the 16-byte spill stores of
+// eight consecutive rows in distinct banks; the bf16 rows (72 bytes) are read as 8-byte
+// halves, 32 rows to 32 distinct bank pairs.
+constexpr int kXS = kTS;                // f32 stride of the xhat (and q) tile
+constexpr int kYS = kTS;                // bf16 stride of the y tile
 constexpr int kXTile = 64 * kXS;        // floats
 constexpr int kYTile = 64 * kYS;        // bf16
 constexpr int kXBytes = 4 * kXTile * 4; // four waves
@@ -234,21 +240,21 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   }
   float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 
-  // one observed entry: x, in-block position p; `valid` false for lanes past the block's
-  // entries (their p belongs to a later block or the zero slack, their y goes to the
-  // tile's padding column and their sums are dropped).  No branches, so a group of rounds issues its LDS reads
+  // one observed entry: x, tile index p (36 r + c); `valid` false for lanes past the
+  // block's entries (their p belongs to a later block or the zero slack, their y goes to
+  // a padding column and their sums are dropped).  No branches, so a group of rounds issues its LDS reads
   // together.  In the least-squares limit k2 = 0 and the weight is exactly 1.
   auto entry = [&](float x, uint32_t p, bool valid, int64_t idx) {
-    // bits 0..10 of p: the position (< 2048 for every slot read: positions of this or a
-    // later block, or zero slack); the bits above are ignored
-    const int r = (int)((p >> 5) & 63u), c = (int)(p & 31u);
-    const float xh = Xs[r * kXS + c];
+    // bits 0..11 of p: the tile index (< 64 kTS for every slot read: positions of this
+    // or a later block, or zero slack); the bits above are ignored
+    const int pi = (int)(p & 4095u);
+    const float xh = Xs[pi];
     const float e = x - xh;
     const float wgt = __builtin_amdgcn_exp2f(-(e * e * k2));
     if constexpr (kGrad)
-      Ys[r * kYS + (valid ? c : 32)] = __builtin_bit_cast(uint16_t, (__bf16)(wgt * e));
+      Ys[valid ? pi : 32] = __builtin_bit_cast(uint16_t, (__bf16)(wgt * e));
     if constexpr (kLS) {
-      const float q = Qs[r * kXS + c];
+      const float q = Qs[pi];
       f0 = fmaf(valid ? wgt * q : 0.f, q, f0);
     }
     if constexpr (MODE == kModeResid) {
@@ -269,11 +275,15 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     }
   };
 
-  // Software pipeline over the chunks, unrolled by three so that three register sets of
-  // entries rotate without copies: at the top of a chunk the entries two chunks ahead
-  // are loaded into the idle set, so they have two whole chunks to arrive.  The value / position arrays and the bf16 column table carry slack
-  // (>= 64 kR + 64 entries, >= 64 items) and the offset index is clamped to the walk, so
-  // these loads need no bounds branch; what they read past a block's end is never used.
+  // Software pipeline over the chunks.  In step gc the LDS tiles hold Xhat (and Q) of
+  // chunk gc and Y of chunk gc - 1; one straight-line block issues the products of
+  // Xhat(gc + 1) and of S += V^T Y(gc - 1) on the matrix cores and, while they run, the
+  // vector work of the entries of chunk gc; then Xhat(gc + 1) is spilled.  Three register
+  // sets of entries rotate without copies (unroll by three): the set of chunk gc - 1
+  // gives the positions to clear in the y tile and is then reloaded with chunk gc + 2.
+  // The value / position arrays and the fragment tables carry slack (>= 64 kR + 64
+  // entries, one chunk) and the indices are clamped to the walk, so these loads need no
+  // bounds branch; what they read past a block's end is never used.
   // Positions are read as the aligned 32-bit word that holds them and shifted at their
   // use: a 16-bit load would be widened right after it arrives, which makes the chunk
   // wait for its own prefetch.
@@ -318,9 +328,11 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   };
 
   auto clear_y = [&]() {
-    uint4* yz = reinterpret_cast<uint4*>(Ys);
+    uint4* yz = reinterpret_cast<uint4*>(Ys);  // kYTile * 2 bytes, a multiple of 16
+    constexpr int nv = kYTile * 2 / 16;
 #pragma unroll
-    for (int i = 0; i < kYTile * 2 / 16 / 64; ++i) yz[l + 64 * i] = uint4{0u, 0u, 0u, 0u};
+    for (int i = 0; i < (nv + 63) / 64; ++i)
+      if (l + 64 * i < nv) yz[l + 64 * i] = uint4{0u, 0u, 0u, 0u};
   };
 
   // A operand of the gradient product (V^T rows of one chunk), read from the transposed
@@ -337,16 +349,12 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     }
   };
 
-  // [bo_cur, bo_end): entries of the current chunk; bo_nend: end of the next one
-  int64_t bo_cur = 0, bo_end = 0, bo_nend = 0;
-  auto step = [&](int64_t gc, const Set& C, Set& N) {  // N: the set for chunk gc + 2
-    if (!rb_ok) return;  // uniform over the wave; it still joins every tile barrier
-
-    const int64_t bo_nn = boff_at(min(gc + 3, gc_end));
-
-    // 1. Xhat^T (and Q^T) of this chunk
-    floatx16 xacc[2] = {floatx16{}, floatx16{}};
-    floatx16 qacc[kLS ? 2 : 1];
+  floatx16 xacc[2];
+  floatx16 qacc[kLS ? 2 : 1];
+  // Xhat^T (and Q^T) of one chunk from the operands in av (and avlo)
+  auto recon = [&]() {
+    xacc[0] = floatx16{};
+    xacc[1] = floatx16{};
     if constexpr (kLS) { qacc[0] = floatx16{}; qacc[1] = floatx16{}; }
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -361,14 +369,10 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
           qacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], thb[n][s], qacc[n], 0, 0, 0);
       }
     }
-    // the next chunk's operands (chunk index gc + 1 <= n_chunks: within the table slack),
-    // then the entries two chunks ahead (offset bo_nend <= nobs).  In this order the wait
-    // for the operands at the next chunk's products leaves the entry loads in flight.
-    load_av(gc + 1);
-    load_set(N, bo_nend);
-
-    // 2. spill Xhat (and Q) to LDS as [row][col]; clear the y tile
-    // accumulator v of n-tile n: col 8 (v/4) + 4 h + v%4, row 32 n + li
+  };
+  // spill Xhat (and Q) to LDS as [row][col]: accumulator v of n-tile n holds col
+  // 8 (v/4) + 4 h + v%4 of row 32 n + li
+  auto spill = [&]() {
 #pragma unroll
     for (int n = 0; n < 2; ++n) {
 #pragma unroll
@@ -383,13 +387,83 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
         }
       }
     }
-    wave_sync();
-
-    // 3. the observed entries of the block, four rounds of 64 at a time (the y tile is
-    // all zero here: cleared before the loop and after every chunk)
-    const int nent = (int)(bo_end - bo_cur);
+  };
+  // B operand of the gradient product: Y^T fragments of the chunk in the y tile
+  bf16x8 yb[kGrad ? 2 : 1][kGrad ? 2 : 1];
+  auto read_y = [&]() {
+    if constexpr (kGrad) {
 #pragma unroll
-    for (int t0 = 0; t0 < kR; t0 += 4) {
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {  // rows are 8-byte aligned: two 8-byte reads
+          const uint2* yp =
+              reinterpret_cast<const uint2*>(Ys + (32 * n + li) * kYS + 16 * s2 + 8 * h);
+          const uint2 y0 = yp[0], y1 = yp[1];
+          yb[s2][n] = __builtin_bit_cast(bf16x8, uint4{y0.x, y0.y, y1.x, y1.y});
+        }
+    }
+  };
+  // S^T += V^T-items^T . Y^T over a chunk's 32 columns (two k-steps of 16)
+  auto grad_products = [&]() {
+    if constexpr (kGrad) {
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int n = 0; n < 2; ++n)
+            sacc[mt][n] =
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[s2][mt], yb[s2][n], sacc[mt][n], 0, 0, 0);
+    }
+  };
+
+  // [bo_cur, bo_end): entries of chunk gc; bo_nend: start of chunk gc + 2
+  int64_t bo_cur = 0, bo_end = 0, bo_nend = 0;
+  int nent_prev = 0;  // entries of chunk gc - 1 (0 before the first chunk)
+  // P: set of chunk gc - 1 on entry, of chunk gc + 2 on exit; C: set of chunk gc
+  auto step = [&](int64_t gc, const Set& C, Set& P) {
+    if (!rb_ok) return;  // uniform over the wave
+    const int64_t bo_nn = boff_at(min(gc + 3, gc_end));
+    const int nent = (int)(bo_end - bo_cur);
+
+    // 1. y fragments of chunk gc - 1, then clear its positions (LDS accesses of a wave
+    //    complete in order, so the clears follow the reads)
+    if constexpr (kGrad) {
+      read_y();
+      if (nent_prev <= 64 * kR) {
+#pragma unroll
+        for (int t0 = 0; t0 < kR; t0 += 4) {
+          if (64 * t0 < nent_prev) {
+#pragma unroll
+            for (int t = t0; t < t0 + 4; ++t) {
+              const uint32_t p = P.pw[t] >> P.sh;
+              if (64 * t + l < nent_prev) Ys[p & 4095u] = 0;
+            }
+          }
+        }
+      } else {
+        clear_y();
+      }
+    }
+    // the set of chunk gc - 1 is free: load the entries of chunk gc + 2 (offset
+    // bo_nend <= nobs)
+    load_set(P, bo_nend);
+
+    // 2. matrix-core products of Xhat(gc + 1) and S(gc - 1), with the first four rounds
+    //    of entries of chunk gc in the same straight-line block
+    recon();
+    grad_products();
+    // the next operands: V^T items of chunk gc + 2 (clamped: the fragment tables end
+    // with one padding chunk) and V^T rows of chunk gc
+    load_av(min(gc + 2, a.n_chunks));
+    load_aw(gc);
+#pragma unroll
+    for (int t = 0; t < 4 && t < kR; ++t) {
+      const int i = 64 * t + l;
+      entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i);
+    }
+#pragma unroll
+    for (int t0 = 4; t0 < kR; t0 += 4) {
       if (64 * t0 < nent) {
 #pragma unroll
         for (int t = t0; t < t0 + 4; ++t) {
@@ -407,43 +481,11 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     }
     wave_sync();
 
-    // 4. S^T += V^T-items^T . Y^T over the chunk's 32 columns (two k-steps of 16)
-    if constexpr (kGrad) {
-#pragma unroll
-      for (int s2 = 0; s2 < 2; ++s2) {
-        bf16x8 yb[2];
-#pragma unroll
-        for (int n = 0; n < 2; ++n)
-          yb[n] = *reinterpret_cast<const bf16x8*>(Ys + (32 * n + li) * kYS + 16 * s2 + 8 * h);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-          for (int n = 0; n < 2; ++n)
-            sacc[mt][n] =
-                __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[s2][mt], yb[n], sacc[mt][n], 0, 0, 0);
-      }
-      // the next chunk's operands (chunk gc + 1 <= n_chunks: inside the table's padding)
-      load_aw(gc + 1);
-      // clear the y tile for the next chunk (LDS accesses of a wave complete in order, so
-      // these stores follow the reads above): only the positions this chunk wrote, unless
-      // the block had more entries than the register rounds hold
-      if (nent <= 64 * kR) {
-#pragma unroll
-        for (int t0 = 0; t0 < kR; t0 += 4) {
-          if (64 * t0 < nent) {
-#pragma unroll
-            for (int t = t0; t < t0 + 4; ++t) {
-              const uint32_t p = C.pw[t] >> C.sh;
-              if (64 * t + l < nent) Ys[((p >> 5) & 63u) * kYS + (p & 31u)] = 0;
-            }
-          }
-        }
-      } else {
-        clear_y();
-      }
-    }
-    wave_sync();  // tile reads (and clears) done before the next chunk writes the tiles
+    // 3. Xhat(gc + 1) into the tiles (after this chunk's reads of them)
+    spill();
+    wave_sync();
 
+    nent_prev = nent;
     bo_cur = bo_end;
     bo_end = bo_nend;
     bo_nend = bo_nn;
@@ -451,20 +493,34 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
 
   Set A, B, C;
   if constexpr (kGrad) clear_y();
-  if (rb_ok && gc_beg < gc_end) {
+  const bool walk = rb_ok && gc_beg < gc_end;
+  if (walk) {
     bo_cur = boff_at(gc_beg);
     bo_end = boff_at(gc_beg + 1);
     bo_nend = boff_at(min(gc_beg + 2, gc_end));
-    load_aw(gc_beg);
-    load_av(gc_beg);  // before the entries, as inside the loop, so that the counted waits
-                      // agree on both paths
+    load_av(gc_beg);
     load_set(A, bo_cur);
     load_set(B, bo_end);
+#pragma unroll
+    for (int s2 = 0; s2 < (kGrad ? 2 : 1); ++s2)
+#pragma unroll
+      for (int mt = 0; mt < (kGrad ? MT : 1); ++mt) aw[s2][mt] = bf16x8{};  // no chunk gc_beg - 1
+    recon();
+    load_av(gc_beg + 1);  // <= n_chunks
+    spill();
+    wave_sync();
   }
+  // the first loads land before the walk: otherwise the counted waits at the top of the
+  // chunk loop must also cover these (register assignment differs between the two paths)
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   for (int64_t gc = gc_beg; gc < gc_end; gc += 3) {
     step(gc, A, C);
     if (gc + 1 < gc_end) step(gc + 1, B, A);
     if (gc + 2 < gc_end) step(gc + 2, C, B);
+  }
+  if (walk) {  // S of the last chunk
+    read_y();
+    grad_products();
   }
 
   if constexpr (kGrad) {
