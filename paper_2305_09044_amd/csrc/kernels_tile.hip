@@ -462,6 +462,14 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
       const int i = 64 * t + l;
       entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i);
     }
+    // interleave: a wave waits at every product it issues while the matrix core is busy
+    // with the previous one, so the vector work of the entries goes in between
+    constexpr int kMfma = KS * 2 * (SPLIT ? 3 : 1) + (kLS ? KS * 2 : 0) + (kGrad ? 4 * MT : 0);
+#pragma unroll
+    for (int i = 0; i < kMfma; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core product
+      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // three vector ALU instructions
+    }
 #pragma unroll
     for (int t0 = 4; t0 < kR; t0 += 4) {
       if (64 * t0 < nent) {
