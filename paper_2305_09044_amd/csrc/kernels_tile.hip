@@ -451,12 +451,13 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
 
     // 2. matrix-core products of Xhat(gc + 1) and S(gc - 1), with the first four rounds
     //    of entries of chunk gc in the same straight-line block
-    recon();
+    // (the gradient products first: their operands are then free before the
+    // reconstruction accumulators are live)
     grad_products();
-    // the next operands: V^T items of chunk gc + 2 (clamped: the fragment tables end
-    // with one padding chunk) and V^T rows of chunk gc
-    load_av(min(gc + 2, a.n_chunks));
-    load_aw(gc);
+    recon();
+    // without gradient products the registers allow loading the next reconstruction
+    // operands here, a whole chunk ahead of their use
+    if constexpr (!kGrad) load_av(min(gc + 2, a.n_chunks));
 #pragma unroll
     for (int t = 0; t < 4 && t < kR; ++t) {
       const int i = 64 * t + l;
@@ -464,7 +465,8 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     }
     // interleave: a wave waits at every product it issues while the matrix core is busy
     // with the previous one, so the vector work of the entries goes in between
-    constexpr int kMfma = KS * 2 * (SPLIT ? 3 : 1) + (kLS ? KS * 2 : 0) + (kGrad ? 4 * MT : 0);
+    // (not in the split form, whose registers are too tight for the longer live ranges)
+    constexpr int kMfma = SPLIT ? 0 : KS * 2 + (kLS ? KS * 2 : 0) + (kGrad ? 4 * MT : 0);
 #pragma unroll
     for (int i = 0; i < kMfma; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core product
@@ -492,6 +494,13 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     // 3. Xhat(gc + 1) into the tiles (after this chunk's reads of them)
     spill();
     wave_sync();
+    // 4. gradient passes: operands of the next step, loaded once the registers are free:
+    //    V^T rows of chunk gc and V^T items of chunk gc + 2 (clamped: the fragment tables
+    //    end with one padding chunk)
+    if constexpr (kGrad) {
+      load_aw(gc);
+      load_av(min(gc + 2, a.n_chunks));
+    }
 
     nent_prev = nent;
     bo_cur = bo_end;

@@ -317,7 +317,8 @@ int ensure_part(trd_ctx* ctx, int64_t need_pass, int64_t need_misc) {
 // work-groups per CU over the (i_k, a) pair tiles, at least two B items per chunk
 int contract_chunks(int64_t Ik, int64_t nB, int r_k) {
   const int64_t ntile = (Ik * r_k + 255) / 256;
-  const int64_t by_grid = std::max<int64_t>(1, (2 * (int64_t)g_num_cu) / std::max<int64_t>(ntile, 1));
+  // about four work-groups per CU: enough loads in flight to stream the partials
+  const int64_t by_grid = std::max<int64_t>(1, (4 * (int64_t)g_num_cu) / std::max<int64_t>(ntile, 1));
   const int64_t by_work = std::max<int64_t>(1, (nB + 1) / 2);
   return (int)std::min(by_grid, by_work);
 }
