@@ -159,8 +159,11 @@ constexpr int kYTile = 64 * kYS;        // bf16
 constexpr int kXBytes = 4 * kXTile * 4; // four waves
 constexpr int kYBytes = 4 * kYTile * 2;
 
-template <int K, bool SPLIT> struct TileRounds {
-  static constexpr int v = K <= 32 ? 12 : (K <= 64 && !SPLIT ? 8 : 4);
+// entry rounds of 64 held in registers per chunk: 12 for K = 32; for K = 64 (plain form) 4
+// or 8, chosen per layout by its mean entries per block (TPassArgs::rounds); 4 otherwise.
+// A block with more entries than the rounds hold takes the remaining rounds from memory.
+template <int K, bool SPLIT, bool WIDE> struct TileRounds {
+  static constexpr int v = K <= 32 ? 12 : (K <= 64 && !SPLIT && WIDE ? 8 : 4);
 };
 
 size_t tpass_lds(int mode, int K, int CW) {
@@ -171,11 +174,11 @@ size_t tpass_lds(int mode, int K, int CW) {
   return (size_t)kXBytes;
 }
 
-template <int K, int MODE, bool SPLIT>
+template <int K, int MODE, bool SPLIT, bool WIDE>
 __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   constexpr int KS = K / 16;       // k-steps of the reconstruction MFMA
   constexpr int MT = K / 32;       // m-tiles of the gradient MFMA
-  constexpr int kR = TileRounds<K, SPLIT>::v;  // entry rounds of 64 in registers per chunk
+  constexpr int kR = TileRounds<K, SPLIT, WIDE>::v;  // entry rounds of 64 in registers per chunk
   constexpr bool kGrad = MODE == kModeGrad || MODE == kModeGradFast;
   constexpr bool kLS = MODE == kModeLS;
   constexpr bool kStats = MODE == kModeGrad || MODE == kModeLoss;
@@ -645,27 +648,33 @@ int64_t tile_cw(int K) {
   return cw;
 }
 
-template <int K, bool SPLIT>
+template <int K, bool SPLIT, bool WIDE>
 static hipError_t launch_k(int mode, const TPassArgs& a, hipStream_t st) {
   const int64_t nwg = a.n_rg * a.n_cg;
   const size_t lds = tpass_lds(mode, K, a.CW);
   if ((int64_t)lds > g_lds_max) return hipErrorInvalidConfiguration;
   dim3 g((unsigned)nwg), b(256);
   switch (mode) {
-    case kModeGrad: hipLaunchKernelGGL((k_tpass<K, kModeGrad, SPLIT>), g, b, lds, st, a); break;
-    case kModeGradFast:
-      hipLaunchKernelGGL((k_tpass<K, kModeGradFast, SPLIT>), g, b, lds, st, a);
+    case kModeGrad:
+      hipLaunchKernelGGL((k_tpass<K, kModeGrad, SPLIT, WIDE>), g, b, lds, st, a);
       break;
-    case kModeLS: hipLaunchKernelGGL((k_tpass<K, kModeLS, SPLIT>), g, b, lds, st, a); break;
-    case kModeResid: hipLaunchKernelGGL((k_tpass<K, kModeResid, SPLIT>), g, b, lds, st, a); break;
-    default: hipLaunchKernelGGL((k_tpass<K, kModeLoss, SPLIT>), g, b, lds, st, a); break;
+    case kModeGradFast:
+      hipLaunchKernelGGL((k_tpass<K, kModeGradFast, SPLIT, WIDE>), g, b, lds, st, a);
+      break;
+    case kModeLS: hipLaunchKernelGGL((k_tpass<K, kModeLS, SPLIT, WIDE>), g, b, lds, st, a); break;
+    case kModeResid:
+      hipLaunchKernelGGL((k_tpass<K, kModeResid, SPLIT, WIDE>), g, b, lds, st, a);
+      break;
+    default: hipLaunchKernelGGL((k_tpass<K, kModeLoss, SPLIT, WIDE>), g, b, lds, st, a); break;
   }
   return hipGetLastError();
 }
 
 template <int K>
 static hipError_t launch_ks(int mode, const TPassArgs& a, hipStream_t st) {
-  return (a.T_lo && a.Vf_lo) ? launch_k<K, true>(mode, a, st) : launch_k<K, false>(mode, a, st);
+  if (a.T_lo && a.Vf_lo) return launch_k<K, true, false>(mode, a, st);
+  if (K == 64 && a.rounds > 4) return launch_k<K, false, true>(mode, a, st);
+  return launch_k<K, false, false>(mode, a, st);
 }
 
 hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {

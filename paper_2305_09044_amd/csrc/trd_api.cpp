@@ -691,6 +691,9 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   a.n_cg = TL.n_cg;
   a.RR = sp.RR;
   a.RRP = sp.RRP;
+  // eight register rounds only for blocks that average more than 224 entries (of 2048
+  // positions): below that, a block rarely needs a fifth round from memory
+  a.rounds = TL.n_blocks > 0 && TL.nobs > 224 * TL.n_blocks ? 8 : 4;
   CK(launch_tpass(mode, TL.K, a, st));
   return TRD_OK;
 }

@@ -251,6 +251,7 @@ struct TPassArgs {
   const double* sigma;
   int64_t nrows, ncols, n_chunks, n_rb, n_rg;
   int CW, n_chpt, cpg, n_cg, RR, RRP;
+  int rounds;            // entry rounds wanted in registers (K = 64: 8 for dense blocks)
 };
 
 // entries of slack after the value / position arrays of a tile layout
