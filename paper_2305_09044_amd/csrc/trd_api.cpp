@@ -67,6 +67,10 @@ struct trd_ctx {
   int64_t cap_T = 0, cap_V = 0, cap_U = 0, cap_chain = 0, cap_S = 0;
   double* K[kMaxN] = {nullptr};
   double* P0 = nullptr; double* P1 = nullptr; double* G = nullptr; double* Cinv = nullptr;
+  // second stream (default priority) for the FGMC Gram and its inverse, which depend only
+  // on the other cores and so run beside the gradient pass; fork / join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double* d64 = nullptr; double* h64 = nullptr; void* h_real = nullptr;
   int64_t cap_d = 0;
   double* part_pass = nullptr; int64_t cap_part_pass = 0;
@@ -850,6 +854,14 @@ int set_sigma(trd_ctx* ctx, double sigma, hipStream_t st) {
   return TRD_OK;
 }
 
+int ensure_side(trd_ctx* ctx) {
+  if (ctx->side) return TRD_OK;
+  CK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  CK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  CK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  return TRD_OK;
+}
+
 // one full core update (eqs. 9-12 / 15-18); K factors of the other cores must be current
 int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const trd_sketch* sk,
             double* eta_user, uint32_t* flags_user, hipStream_t st) {
@@ -859,11 +871,18 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
   const int64_t Ik = ctx->dims[k];
   const int R = sp.r_k * sp.r_k1;
   CK(launch_zero(ctx->flags, sizeof(uint32_t), st));
+  // G (eq. 13) and (G + lambda I)^{-1} need only the factors of the other cores: on the
+  // side stream, after everything queued so far, while the gradient runs here
+  TRY(ensure_side(ctx));
+  CK(hipEventRecord(ctx->ev_fork, st));
+  CK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+  TRY(ring_gram(ctx, k, ctx->G, ctx->side));
+  CK(launch_inverse(ctx->G, ctx->Cinv, R, lambda_rel, ctx->flags, ctx->side));
+  CK(hipEventRecord(ctx->ev_join, ctx->side));
   ItemRef Uref;
   int64_t nB;
   TRY(do_grad(ctx, up, (const void* const*)cores, nullptr, 1.0, nullptr, st, &Uref, &nB));
-  TRY(ring_gram(ctx, k, ctx->G, st));
-  CK(launch_inverse(ctx->G, ctx->Cinv, R, lambda_rel, ctx->flags, st));
+  CK(hipStreamWaitEvent(st, ctx->ev_join, 0));
   const int64_t nbl = (Ik * R + 255) / 256;
   TRY(ensure_part(ctx, 0, nbl));
   CK(launch_apply_inverse(ctx->d64, ctx->Cinv, Ik, R, ctx->h64, ctx->h_real, ctx->dtype,
@@ -938,6 +957,9 @@ void trd_destroy(trd_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
   for (hipEvent_t ev : ctx->ev_pairs) hipEventDestroy(ev);
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+  if (ctx->side) hipStreamDestroy(ctx->side);
   free_all(ctx);
   delete ctx;
 }
