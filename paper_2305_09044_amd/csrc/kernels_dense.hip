@@ -837,17 +837,24 @@ __global__ void k_qsigma(const uint32_t* state, double c, const double* sigma_mi
   *sigma = s;
 }
 
+hipError_t launch_quantile_init(const int64_t* nobs, double q, uint32_t* state, uint32_t* hist,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_qinit, dim3(1), dim3(1), 0, st, nobs, q, state, hist);
+  return hipGetLastError();
+}
+
 hipError_t launch_quantile_sigma(const float* keys, int64_t n_slots_hint, const int64_t* nslots,
                                  double q, double c, const double* sigma_min, double shrink,
                                  double* sigma, uint32_t* hist, uint32_t* state,
-                                 const int64_t* nobs, hipStream_t st) {
-  hipLaunchKernelGGL(k_qinit, dim3(1), dim3(1), 0, st, nobs, q, state, hist);
+                                 const int64_t* nobs, bool first_digit_done, hipStream_t st) {
+  if (!first_digit_done) hipLaunchKernelGGL(k_qinit, dim3(1), dim3(1), 0, st, nobs, q, state, hist);
   const int shifts[3] = {21, 10, 0};
   const int bitsv[3] = {11, 11, 10};
   const int g = grid_for(n_slots_hint, 256, 2048);
   for (int r = 0; r < 3; ++r) {
-    hipLaunchKernelGGL(k_qhist, dim3(g), dim3(256), 0, st, keys, nslots, shifts[r], bitsv[r],
-                       state, hist);
+    if (r > 0 || !first_digit_done)
+      hipLaunchKernelGGL(k_qhist, dim3(g), dim3(256), 0, st, keys, nslots, shifts[r], bitsv[r],
+                         state, hist);
     hipLaunchKernelGGL(k_qpick, dim3(1), dim3(1024), 0, st, bitsv[r], state, hist);
   }
   hipLaunchKernelGGL(k_qsigma, dim3(1), dim3(1), 0, st, state, c, sigma_min, shrink, sigma);

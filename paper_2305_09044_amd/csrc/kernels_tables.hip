@@ -140,72 +140,86 @@ __global__ void k_merge(const real* __restrict__ L, int64_t Ls, const int32_t* _
   }
 }
 
-// One output item per thread for the common square case (rA = rB = rC = R, R % 4 == 0,
-// FP32): the item (L_l . R_j, an R x R product) is formed in registers from L_l, read one
-// column of b at a time, and R_j, read whole; the sums run over b in order, as in the
-// kernels above, so the results are the same.  A thread writes its item contiguously.
-template <bool BF, int R>
+// The common square case (rA = rB = rC = R = 8, FP32 inputs): thread (item, c) forms the
+// R outputs a + R c (a < R) of its item, (L_l . R_j)[:, c], from L_l and column c of R_j;
+// the sums run over b in order, as in the kernels above, so the results are the same.
+// R consecutive threads write one item row, so every store instruction of a wave writes
+// one contiguous run.  With STAGE the nL left items are first copied to LDS (row stride
+// R*R + 4 floats, so that the eight items a wave reads fall in different banks).
+template <bool BF, int R, bool STAGE>
 __global__ __launch_bounds__(256) void k_merge_item(
     const float* __restrict__ L, int64_t Ls, const int32_t* __restrict__ Llist, uint32_t nL,
     const float* __restrict__ Rm, int64_t Rs, const int32_t* __restrict__ Rlist, uint32_t nItems,
     void* __restrict__ out, void* __restrict__ out_lo, int os, FastDiv nLdiv) {
-  const uint32_t item = blockIdx.x * 256u + threadIdx.x;
+  static_assert(R == 8, "one 16-byte bf16 group per thread");
+  extern __shared__ __align__(16) float Lsh[];
+  constexpr int LS = R * R + 4;
+  if constexpr (STAGE) {
+    for (uint32_t e = threadIdx.x; e < nL * (R * R / 4); e += 256) {
+      const uint32_t li = e / (R * R / 4), q = e - li * (R * R / 4);
+      const float4 v = *reinterpret_cast<const float4*>(
+          L + (Llist ? (int64_t)Llist[li] : (int64_t)li) * Ls + 4 * q);
+      *reinterpret_cast<float4*>(Lsh + li * LS + 4 * q) = v;
+    }
+    __syncthreads();
+  }
+  const uint64_t t = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  const uint32_t item = (uint32_t)(t / R), c = (uint32_t)(t % R);
   if (item >= nItems) return;
   const uint32_t j = nLdiv.div(item), l = item - j * nL;
-  const float* Lp = L + (Llist ? (int64_t)Llist[l] : (int64_t)l) * Ls;
-  const float* Rp = Rm + (Rlist ? (int64_t)Rlist[j] : (int64_t)j) * Rs;
-  float r[R * R];
+  const float* Lp = STAGE ? Lsh + l * LS : L + (Llist ? (int64_t)Llist[l] : (int64_t)l) * Ls;
+  const float* Rp = Rm + (Rlist ? (int64_t)Rlist[j] : (int64_t)j) * Rs + R * c;
+  float r[R];
 #pragma unroll
-  for (int i = 0; i < R * R / 4; ++i) {
+  for (int i = 0; i < R / 4; ++i) {
     const float4 v = reinterpret_cast<const float4*>(Rp)[i];
     r[4 * i] = v.x; r[4 * i + 1] = v.y; r[4 * i + 2] = v.z; r[4 * i + 3] = v.w;
   }
-  float acc[R * R];
+  float acc[R];
 #pragma unroll
-  for (int e = 0; e < R * R; ++e) acc[e] = 0.f;
+  for (int a = 0; a < R; ++a) acc[a] = 0.f;
 #pragma unroll
   for (int b = 0; b < R; ++b) {
-    float lv[R];
 #pragma unroll
     for (int a4 = 0; a4 < R / 4; ++a4) {
       const float4 v = *reinterpret_cast<const float4*>(Lp + R * b + 4 * a4);
-      lv[4 * a4] = v.x; lv[4 * a4 + 1] = v.y; lv[4 * a4 + 2] = v.z; lv[4 * a4 + 3] = v.w;
+      acc[4 * a4] = fmaf(v.x, r[b], acc[4 * a4]);
+      acc[4 * a4 + 1] = fmaf(v.y, r[b], acc[4 * a4 + 1]);
+      acc[4 * a4 + 2] = fmaf(v.z, r[b], acc[4 * a4 + 2]);
+      acc[4 * a4 + 3] = fmaf(v.w, r[b], acc[4 * a4 + 3]);
     }
-#pragma unroll
-    for (int c = 0; c < R; ++c)
-#pragma unroll
-      for (int a = 0; a < R; ++a) acc[a + R * c] = fmaf(lv[a], r[b + R * c], acc[a + R * c]);
   }
-  // item row: R * R values, then zeros up to os (os % 8 == 0 for bf16, % 4 for FP32)
-  static_assert(R * R % 8 == 0, "whole 16-byte groups of bf16");
+  // outputs 8c .. 8c + 7 of the item row; the R values past R * R up to os are zeros,
+  // written by the threads c < (os - R * R) / 8
   if constexpr (BF) {
-    uint4* o = reinterpret_cast<uint4*>(static_cast<uint16_t*>(out) + (int64_t)item * os);
-    uint4* olo = out_lo ? reinterpret_cast<uint4*>(static_cast<uint16_t*>(out_lo) + (int64_t)item * os)
-                        : nullptr;
+    uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int v8 = 0; v8 < R * R / 8; ++v8) {
-      uint32_t hw[4] = {0u, 0u, 0u, 0u}, lw[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const float x = acc[8 * v8 + u];
-        const uint16_t hi = bf16_bits(x);
-        const uint16_t lo = bf16_bits(x - __uint_as_float((uint32_t)hi << 16));
-        hw[u >> 1] |= (uint32_t)hi << ((u & 1) * 16);
-        lw[u >> 1] |= (uint32_t)lo << ((u & 1) * 16);
-      }
-      o[v8] = uint4{hw[0], hw[1], hw[2], hw[3]};
-      if (olo) olo[v8] = uint4{lw[0], lw[1], lw[2], lw[3]};
+    for (int u = 0; u < 8; ++u) {
+      const uint16_t hi = bf16_bits(acc[u]);
+      const uint16_t lo = bf16_bits(acc[u] - __uint_as_float((uint32_t)hi << 16));
+      hw[u >> 1] |= (uint32_t)hi << ((u & 1) * 16);
+      lw[u >> 1] |= (uint32_t)lo << ((u & 1) * 16);
     }
-    for (int v8 = R * R / 8; v8 < os / 8; ++v8) {
-      o[v8] = uint4{0u, 0u, 0u, 0u};
-      if (olo) olo[v8] = uint4{0u, 0u, 0u, 0u};
+    uint16_t* o = static_cast<uint16_t*>(out) + (int64_t)item * os;
+    *reinterpret_cast<uint4*>(o + 8 * c) = uint4{hw[0], hw[1], hw[2], hw[3]};
+    if (out_lo) {
+      uint16_t* ol = static_cast<uint16_t*>(out_lo) + (int64_t)item * os;
+      *reinterpret_cast<uint4*>(ol + 8 * c) = uint4{lw[0], lw[1], lw[2], lw[3]};
+    }
+    for (int z = R * R + 8 * (int)c; z < os; z += 8 * R) {
+      *reinterpret_cast<uint4*>(o + z) = uint4{0u, 0u, 0u, 0u};
+      if (out_lo)
+        *reinterpret_cast<uint4*>(static_cast<uint16_t*>(out_lo) + (int64_t)item * os + z) =
+            uint4{0u, 0u, 0u, 0u};
     }
   } else {
-    float4* o = reinterpret_cast<float4*>(static_cast<float*>(out) + (int64_t)item * os);
-#pragma unroll
-    for (int v4 = 0; v4 < R * R / 4; ++v4)
-      o[v4] = float4{acc[4 * v4], acc[4 * v4 + 1], acc[4 * v4 + 2], acc[4 * v4 + 3]};
-    for (int v4 = R * R / 4; v4 < os / 4; ++v4) o[v4] = float4{0.f, 0.f, 0.f, 0.f};
+    float* o = static_cast<float*>(out) + (int64_t)item * os;
+    *reinterpret_cast<float4*>(o + 8 * c) = float4{acc[0], acc[1], acc[2], acc[3]};
+    *reinterpret_cast<float4*>(o + 8 * c + 4) = float4{acc[4], acc[5], acc[6], acc[7]};
+    for (int z = R * R + 8 * (int)c; z < os; z += 8 * R) {
+      *reinterpret_cast<float4*>(o + z) = float4{0.f, 0.f, 0.f, 0.f};
+      *reinterpret_cast<float4*>(o + z + 4) = float4{0.f, 0.f, 0.f, 0.f};
+    }
   }
 }
 
@@ -217,15 +231,24 @@ static void merge_idx(dim3 g, dim3 b, hipStream_t st, bool small, const ItemRef&
     const uintptr_t ua = reinterpret_cast<uintptr_t>(out), ula = reinterpret_cast<uintptr_t>(out_lo);
     // (large tables only: with few items the element-parallel kernel below is faster)
     if (!transpose_out && rA == 8 && rB == 8 && rC == 8 && nL * nR >= 32768 &&
-        nL * nR < ((int64_t)1 << 31) &&
+        nL * nR < ((int64_t)1 << 28) &&
         out_stride >= 64 && out_stride % 8 == 0 && L.stride % 4 == 0 && R.stride % 4 == 0 &&
         reinterpret_cast<uintptr_t>(L.ptr) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(R.ptr) % 16 == 0 && ua % 16 == 0 && ula % 16 == 0) {
       const uint32_t items = (uint32_t)(nL * nR);
-      hipLaunchKernelGGL((k_merge_item<BF, 8>), dim3((items + 255) / 256), b, 0, st,
-                         (const float*)L.ptr, L.stride, L.list, (uint32_t)nL, (const float*)R.ptr,
-                         R.stride, R.list, items, out, out_lo, (int)out_stride,
-                         FastDiv((uint32_t)nL));
+      const size_t lds = (size_t)nL * (64 + 4) * sizeof(float);
+      const unsigned ng = (unsigned)(((uint64_t)items * 8 + 255) / 256);
+      if ((int64_t)lds <= 32768) {
+        hipLaunchKernelGGL((k_merge_item<BF, 8, true>), dim3(ng), b, lds, st,
+                           (const float*)L.ptr, L.stride, L.list, (uint32_t)nL,
+                           (const float*)R.ptr, R.stride, R.list, items, out, out_lo,
+                           (int)out_stride, FastDiv((uint32_t)nL));
+      } else {
+        hipLaunchKernelGGL((k_merge_item<BF, 8, false>), dim3(ng), b, 0, st,
+                           (const float*)L.ptr, L.stride, L.list, (uint32_t)nL,
+                           (const float*)R.ptr, R.stride, R.list, items, out, out_lo,
+                           (int)out_stride, FastDiv((uint32_t)nL));
+      }
       return;
     }
     if (small && !transpose_out && rA % 4 == 0 && out_stride % 4 == 0 && L.stride % 4 == 0 &&
@@ -483,8 +506,18 @@ __global__ __launch_bounds__(1024) void k_contract_finish(const double* __restri
   const int o = threadIdx.x & 63, gs = threadIdx.x >> 6;
   const int64_t t = (int64_t)blockIdx.x * 64 + o;
   double s = 0.0;
-  if (t < n)
-    for (int c = gs; c < nchunk; c += 16) s += part[(int64_t)c * n + t];
+  if (t < n) {
+    // loads eight chunks ahead of the (in-order) sums
+    int c = gs;
+    for (; c + 16 * 7 < nchunk; c += 16 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(c + 16 * u) * n + t];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nchunk; c += 16) s += part[(int64_t)c * n + t];
+  }
   red[gs][o] = s;
   __syncthreads();
   for (int w = 8; w > 0; w >>= 1) {

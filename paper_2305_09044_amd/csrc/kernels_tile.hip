@@ -158,6 +158,9 @@ constexpr int kXTile = 64 * kXS;        // floats
 constexpr int kYTile = 64 * kYS;        // bf16
 constexpr int kXBytes = 4 * kXTile * 4; // four waves
 constexpr int kYBytes = 4 * kYTile * 2;
+// residual pass: work-group histogram of the first quantile digit (key >> 21, 11 bits)
+constexpr int kQHistBins = 2048;
+constexpr int kQHistBytes = kQHistBins * 4;
 
 // entry rounds of 64 held in registers per chunk: 12 for K = 32; for K = 64 (plain form) 4
 // or 8, chosen per layout by its mean entries per block (TPassArgs::rounds); 4 otherwise.
@@ -171,6 +174,7 @@ size_t tpass_lds(int mode, int K, int CW) {
   (void)CW;
   if (mode == kModeGrad || mode == kModeGradFast) return (size_t)kXBytes + kYBytes;
   if (mode == kModeLS) return 2 * (size_t)kXBytes;
+  if (mode == kModeResid) return (size_t)kXBytes + kQHistBytes;
   return (size_t)kXBytes;
 }
 
@@ -190,6 +194,13 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   float* Xs = reinterpret_cast<float*>(smem_raw) + w * kXTile;
   float* Qs = reinterpret_cast<float*>(smem_raw + kXBytes) + w * kXTile;             // LS
   uint16_t* Ys = reinterpret_cast<uint16_t*>(smem_raw + kXBytes) + w * kYTile;       // grad
+  uint32_t* qh = reinterpret_cast<uint32_t*>(smem_raw + kXBytes);                     // resid
+  if constexpr (MODE == kModeResid) {
+    if (a.qhist) {
+      for (int i = threadIdx.x; i < kQHistBins; i += 256) qh[i] = 0u;
+      __syncthreads();
+    }
+  }
 
   const int64_t wg = blockIdx.x;
   const int64_t cg = wg / a.n_rg, g = wg % a.n_rg;
@@ -261,7 +272,10 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
       f0 = fmaf(valid ? wgt * q : 0.f, q, f0);
     }
     if constexpr (MODE == kModeResid) {
-      if (valid) a.resid[idx] = fabsf(e);
+      if (valid) {
+        a.resid[idx] = fabsf(e);
+        if (a.qhist) atomicAdd(&qh[__float_as_uint(fabsf(e)) >> 21], 1u);
+      }
     }
     if constexpr (kStats) {
       const float uu = e * e * inv2s2;
@@ -581,6 +595,11 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   if (threadIdx.x < 3) {
     const double* r = red[threadIdx.x];
     a.partials[wg * 3 + threadIdx.x] = (r[0] + r[1]) + (r[2] + r[3]);
+  }
+  if constexpr (MODE == kModeResid) {  // the work-group's digit counts into the global one
+    if (a.qhist)
+      for (int i = threadIdx.x; i < kQHistBins; i += 256)
+        if (qh[i]) atomicAdd(&a.qhist[i], qh[i]);
   }
 }
 

@@ -682,6 +682,10 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   a.vals = TL.vals;
   a.pos = TL.pos;
   a.resid = ctx->resid;
+  // the residual pass also counts the first quantile digit (launch_quantile_init first)
+  a.qhist = mode == kModeResid ? ctx->qhist : nullptr;
+  // the residual pass also counts the first quantile digit (launch_quantile_init first)
+  a.qhist = mode == kModeResid ? ctx->qhist : nullptr;
   a.partials = ctx->part_pass;
   a.sigma = ctx->scal + kSigma;
   a.nrows = TL.nrows;
@@ -1254,10 +1258,11 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
       TRY(build_U(ctx, up, (const void* const*)cores, Uref, nB, st));
       TRY(build_rowtable(ctx, up, cores[0], Uref, nB, ctx->T, st));
       TRY(build_coltable(ctx, up, (const void* const*)cores, st));
+      if (up.TL) CK(launch_quantile_init(up_nobs_dev(up), o->q, ctx->qstate, ctx->qhist, st));
       TRY(run_pass(ctx, up, kModeResid, st));
       CK(launch_quantile_sigma(ctx->resid, nkeys, nkeys_dev, o->q, o->c, ctx->scal + kSigmaMin,
                                o->shrink, ctx->scal + kSigma, ctx->qhist, ctx->qstate,
-                               up_nobs_dev(up), st));
+                               up_nobs_dev(up), up.TL != nullptr, st));
     }
     for (int k = 0; k < N; ++k) {
       TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st));

@@ -247,6 +247,7 @@ struct TPassArgs {
   const float* vals;
   const uint16_t* pos;
   float* resid;          // kModeResid: |e| per observed entry, in value order
+  uint32_t* qhist;       // kModeResid: first-digit histogram of the |e| keys (or nullptr)
   double* partials;      // [n_wg][3]
   const double* sigma;
   int64_t nrows, ncols, n_chunks, n_rb, n_rg;
@@ -270,9 +271,15 @@ hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* 
 hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st);
 
 // sigma quantile by radix select over float bit patterns
+// radix select of the kernel-width quantile over the |e| keys: three digits (11, 11, 10
+// bits).  With first_digit_done the first digit's histogram is already in hist (written
+// by the residual pass after launch_quantile_init); otherwise the selection initialises
+// the state and counts every digit itself.
+hipError_t launch_quantile_init(const int64_t* nobs, double q, uint32_t* state, uint32_t* hist,
+                                hipStream_t st);
 hipError_t launch_quantile_sigma(const float* keys, int64_t n_slots_hint, const int64_t* nslots,
                                  double q, double c, const double* sigma_min, double shrink,
                                  double* sigma, uint32_t* hist, uint32_t* state,
-                                 const int64_t* nobs, hipStream_t st);
+                                 const int64_t* nobs, bool first_digit_done, hipStream_t st);
 
 }  // namespace trd
