@@ -452,9 +452,9 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
         for (int t0 = 0; t0 < kR; t0 += 4) {
           if (64 * t0 < nent_prev) {
 #pragma unroll
-            for (int t = t0; t < t0 + 4; ++t) {
+            for (int t = t0; t < t0 + 4; ++t) {  // no branch: other lanes clear padding
               const uint32_t p = P.pw[t] >> P.sh;
-              if (64 * t + l < nent_prev) Ys[p & 4095u] = 0;
+              Ys[64 * t + l < nent_prev ? (p & 4095u) : 32u] = 0;
             }
           }
         }
