@@ -173,18 +173,26 @@ size_t tpass_lds(int mode, int K, int CW) {
   (void)K;
   (void)CW;
   if (mode == kModeGrad || mode == kModeGradFast) return (size_t)kXBytes + kYBytes;
-  if (mode == kModeLS) return 2 * (size_t)kXBytes;
+  if (mode == kModeLS) return (size_t)kXBytes;  // the q tile only
   if (mode == kModeResid) return (size_t)kXBytes + kQHistBytes;
   return (size_t)kXBytes;
 }
 
+// (the line search keeps only q and the TH operands: four waves per SIMD for K = 64)
+#ifndef LS_WAVES
+#define LS_WAVES 2
+#endif
 template <int K, int MODE, bool SPLIT, bool WIDE>
-__global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
+__global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && !WIDE ? LS_WAVES : 2))) void k_tpass(
+    TPassArgs a) {
   constexpr int KS = K / 16;       // k-steps of the reconstruction MFMA
   constexpr int MT = K / 32;       // m-tiles of the gradient MFMA
   constexpr int kR = TileRounds<K, SPLIT, WIDE>::v;  // entry rounds of 64 in registers per chunk
   constexpr bool kGrad = MODE == kModeGrad || MODE == kModeGradFast;
   constexpr bool kLS = MODE == kModeLS;
+  // the line search reads the weights the gradient pass stored (same cores, sigma and
+  // layout, so the same values) and needs only the products q, not xhat
+  constexpr bool kRecon = !kLS;
   constexpr bool kStats = MODE == kModeGrad || MODE == kModeLoss;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // the wave index is uniform over the wave: keep it (and everything derived from it:
@@ -192,7 +200,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l = threadIdx.x & 63, h = l >> 5, li = l & 31;
   float* Xs = reinterpret_cast<float*>(smem_raw) + w * kXTile;
-  float* Qs = reinterpret_cast<float*>(smem_raw + kXBytes) + w * kXTile;             // LS
+  float* Qs = Xs;  // LS: the q tile in place of the xhat tile
   uint16_t* Ys = reinterpret_cast<uint16_t*>(smem_raw + kXBytes) + w * kYTile;       // grad
   uint32_t* qh = reinterpret_cast<uint32_t*>(smem_raw + kXBytes);                     // resid
   if constexpr (MODE == kModeResid) {
@@ -210,8 +218,8 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   const int64_t gc_end = min(a.n_chunks, gc_beg + (int64_t)a.cpg * a.n_chpt);
 
   // B operand of the reconstruction: this wave's 64 T items (and TH for the line search)
-  bf16x8 tb[2][KS];
-  bf16x8 tlo[SPLIT ? 2 : 1][SPLIT ? KS : 1];
+  bf16x8 tb[kRecon ? 2 : 1][kRecon ? KS : 1];
+  bf16x8 tlo[SPLIT && kRecon ? 2 : 1][SPLIT && kRecon ? KS : 1];
   bf16x8 thb[kLS ? 2 : 1][kLS ? KS : 1];
 #pragma unroll
   for (int n = 0; n < 2; ++n) {
@@ -219,10 +227,12 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       bf16x8 z = {};
-      tb[n][s] = z;
-      if (row < a.nrows)
-        tb[n][s] = *reinterpret_cast<const bf16x8*>(a.T + row * K + s * 16 + h * 8);
-      if constexpr (SPLIT) {
+      if constexpr (kRecon) {
+        tb[n][s] = z;
+        if (row < a.nrows)
+          tb[n][s] = *reinterpret_cast<const bf16x8*>(a.T + row * K + s * 16 + h * 8);
+      }
+      if constexpr (SPLIT && kRecon) {
         tlo[n][s] = z;
         if (row < a.nrows)
           tlo[n][s] = *reinterpret_cast<const bf16x8*>(a.T_lo + row * K + s * 16 + h * 8);
@@ -258,18 +268,25 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   // block's entries (their p belongs to a later block or the zero slack, their y goes to
   // a padding column and their sums are dropped).  No branches, so a group of rounds issues its LDS reads
   // together.  In the least-squares limit k2 = 0 and the weight is exactly 1.
-  auto entry = [&](float x, uint32_t p, bool valid, int64_t idx) {
+  // wkeep: where a gradient pass leaves the weight for a later store (nullptr: store now)
+  auto entry = [&](float x, uint32_t p, bool valid, int64_t idx, float* wkeep) {
     // bits 0..11 of p: the tile index (< 64 kTS for every slot read: positions of this
     // or a later block, or zero slack); the bits above are ignored
     const int pi = (int)(p & 4095u);
+    if constexpr (kLS) {  // x is the entry's weight here
+      const float q = Qs[pi];
+      f0 = fmaf(valid ? x * q : 0.f, q, f0);
+      return;
+    }
     const float xh = Xs[pi];
     const float e = x - xh;
     const float wgt = __builtin_amdgcn_exp2f(-(e * e * k2));
-    if constexpr (kGrad)
+    if constexpr (kGrad) {
       Ys[valid ? pi : 32] = __builtin_bit_cast(uint16_t, (__bf16)(wgt * e));
-    if constexpr (kLS) {
-      const float q = Qs[pi];
-      f0 = fmaf(valid ? wgt * q : 0.f, q, f0);
+      // the weight, for the line search of this update (lanes past the block's entries
+      // write a slot of their own past the last entry)
+      if (wkeep) *wkeep = wgt;
+      else if (a.wout) a.wout[valid ? idx : a.nobs + l] = wgt;
     }
     if constexpr (MODE == kModeResid) {
       if (valid) {
@@ -370,18 +387,18 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
   floatx16 qacc[kLS ? 2 : 1];
   // Xhat^T (and Q^T) of one chunk from the operands in av (and avlo)
   auto recon = [&]() {
-    xacc[0] = floatx16{};
-    xacc[1] = floatx16{};
+    if constexpr (kRecon) { xacc[0] = floatx16{}; xacc[1] = floatx16{}; }
     if constexpr (kLS) { qacc[0] = floatx16{}; qacc[1] = floatx16{}; }
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
-        if constexpr (SPLIT) {  // remainder products first, then the leading one
+        if constexpr (SPLIT && kRecon) {  // remainder products first, then the leading one
           xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(avlo[s], tb[n][s], xacc[n], 0, 0, 0);
           xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], tlo[n][s], xacc[n], 0, 0, 0);
         }
-        xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], tb[n][s], xacc[n], 0, 0, 0);
+        if constexpr (kRecon)
+          xacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], tb[n][s], xacc[n], 0, 0, 0);
         if constexpr (kLS)
           qacc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[s], thb[n][s], qacc[n], 0, 0, 0);
       }
@@ -394,9 +411,11 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     for (int n = 0; n < 2; ++n) {
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4) {
-        const float4 xv = {xacc[n][4 * q4], xacc[n][4 * q4 + 1], xacc[n][4 * q4 + 2],
-                           xacc[n][4 * q4 + 3]};
-        *reinterpret_cast<float4*>(Xs + (32 * n + li) * kXS + 8 * q4 + 4 * h) = xv;
+        if constexpr (kRecon) {
+          const float4 xv = {xacc[n][4 * q4], xacc[n][4 * q4 + 1], xacc[n][4 * q4 + 2],
+                             xacc[n][4 * q4 + 3]};
+          *reinterpret_cast<float4*>(Xs + (32 * n + li) * kXS + 8 * q4 + 4 * h) = xv;
+        }
         if constexpr (kLS) {
           const float4 qv = {qacc[n][4 * q4], qacc[n][4 * q4 + 1], qacc[n][4 * q4 + 2],
                              qacc[n][4 * q4 + 3]};
@@ -475,15 +494,16 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     // without gradient products the registers allow loading the next reconstruction
     // operands here, a whole chunk ahead of their use
     if constexpr (!kGrad) load_av(min(gc + 2, a.n_chunks));
+    float wk[4];  // weights of the first four rounds, stored after the operand loads below
 #pragma unroll
     for (int t = 0; t < 4 && t < kR; ++t) {
       const int i = 64 * t + l;
-      entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i);
+      entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i, &wk[t]);
     }
     // interleave: a wave waits at every product it issues while the matrix core is busy
     // with the previous one, so the vector work of the entries goes in between
     // (not in the split form, whose registers are too tight for the longer live ranges)
-    constexpr int kMfma = SPLIT ? 0 : KS * 2 + (kLS ? KS * 2 : 0) + (kGrad ? 4 * MT : 0);
+    constexpr int kMfma = SPLIT ? 0 : KS * 2 + (kGrad ? 4 * MT : 0);
 #pragma unroll
     for (int i = 0; i < kMfma; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core product
@@ -495,7 +515,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
 #pragma unroll
         for (int t = t0; t < t0 + 4; ++t) {
           const int i = 64 * t + l;
-          entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i);
+          entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i, nullptr);
         }
       }
     }
@@ -504,7 +524,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
       const bool valid = i < nent;
       const float x = valid ? a.vals[bo_cur + i] : 0.f;
       const uint32_t p = valid ? (uint32_t)a.pos[bo_cur + i] : 0u;
-      entry(x, p, valid, bo_cur + i);
+      entry(x, p, valid, bo_cur + i, nullptr);
     }
     wave_sync();
 
@@ -517,6 +537,15 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(TPassArgs a) {
     if constexpr (kGrad) {
       load_aw(gc);
       load_av(min(gc + 2, a.n_chunks));
+      // the weights last: memory operations retire in order, so stores issued before the
+      // operand loads would hold up the next step's wait for those operands
+      if (a.wout) {
+#pragma unroll
+        for (int t = 0; t < 4 && t < kR; ++t) {
+          const int i = 64 * t + l;
+          a.wout[i < nent ? bo_cur + i : a.nobs + l] = wk[t];
+        }
+      }
     }
 
     nent_prev = nent;

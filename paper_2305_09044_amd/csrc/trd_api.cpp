@@ -59,6 +59,9 @@ struct trd_ctx {
   uint16_t* Tb_lo = nullptr; uint16_t* Vb_lo = nullptr;  // split (BF16X3) remainders
   // Vb (and Vb_lo) in operand-fragment order, and Vb transposed in fragment order
   uint16_t* Vf = nullptr; uint16_t* Vf_lo = nullptr; uint16_t* VTf = nullptr;
+  // per-entry weights of the last gradient pass (tile layouts), read by its line search
+  float* wts = nullptr;
+  int64_t cap_wts = 0;
   int64_t cap_Tb = 0, cap_Vb = 0, cap_Tlo = 0, cap_Vlo = 0, cap_Vf = 0, cap_Vflo = 0;
 
   // tables and work buffers (sized for the largest core and sketch)
@@ -439,6 +442,13 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   CK(launch_zero(T.vals, (size_t)(T.nobs + kTileSlack) * sizeof(float), st));
   CK(launch_zero(T.pos, (size_t)(T.nobs + kTileSlack) * sizeof(uint16_t), st));
   CK(launch_tile_build(T, ctx->mask, ctx->X, ctx->dtype, true, st));
+  // weights: one per entry, the same slack (the line search reads them like values; the
+  // gradient pass's lanes past a block's end write their own slots past nobs); zeroed once
+  if (T.nobs + kTileSlack > ctx->cap_wts) {
+    TRY(alloc_n(ctx, &ctx->wts, T.nobs + kTileSlack));
+    CK(launch_zero(ctx->wts, (size_t)(T.nobs + kTileSlack) * sizeof(float), st));
+    ctx->cap_wts = T.nobs + kTileSlack;
+  }
   T.ready = true;
   return TRD_OK;
 }
@@ -702,6 +712,13 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   // eight register rounds only for blocks that average more than 224 entries (of 2048
   // positions): below that, a block rarely needs a fifth round from memory
   a.rounds = TL.n_blocks > 0 && TL.nobs > 224 * TL.n_blocks ? 8 : 4;
+  a.nobs = TL.nobs;
+  if (mode == kModeGrad || mode == kModeGradFast) a.wout = ctx->wts;
+  if (mode == kModeLS) {  // weights of this update's gradient pass; q needs no split tables
+    a.vals = ctx->wts;
+    a.T_lo = nullptr;
+    a.Vf_lo = nullptr;
+  }
   CK(launch_tpass(mode, TL.K, a, st));
   return TRD_OK;
 }
