@@ -32,6 +32,11 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kTS = 36;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// IEEE half bits of x (round to nearest even)
+__device__ __forceinline__ uint16_t f16_bits(float x) {
+  return __builtin_bit_cast(uint16_t, (_Float16)x);
+}
+
 // order LDS accesses among the lanes of one wave (the tiles below are per wave)
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -273,9 +278,10 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
     // bits 0..11 of p: the tile index (< 64 kTS for every slot read: positions of this
     // or a later block, or zero slack); the bits above are ignored
     const int pi = (int)(p & 4095u);
-    if constexpr (kLS) {  // x is the entry's weight here
+    if constexpr (kLS) {  // the low 16 bits of x hold the entry's weight (fp16)
+      const float wv = (float)__builtin_bit_cast(_Float16, (uint16_t)(__float_as_uint(x) & 0xffffu));
       const float q = Qs[pi];
-      f0 = fmaf(valid ? x * q : 0.f, q, f0);
+      f0 = fmaf(valid ? wv * q : 0.f, q, f0);
       return;
     }
     const float xh = Xs[pi];
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
       // the weight, for the line search of this update (lanes past the block's entries
       // write a slot of their own past the last entry)
       if (wkeep) *wkeep = wgt;
-      else if (a.wout) a.wout[valid ? idx : a.nobs + l] = wgt;
+      else if (a.wout) a.wout[valid ? idx : a.nobs + l] = f16_bits(wgt);
     }
     if constexpr (MODE == kModeResid) {
       if (valid) {
@@ -339,12 +345,16 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
     return (int64_t)(((uint64_t)hi << 32) | lo);
   };
   const uint32_t* posw = reinterpret_cast<const uint32_t*>(a.pos);
+  const uint32_t* winw = reinterpret_cast<const uint32_t*>(a.win);  // line search
   auto load_set = [&](Set& S, int64_t bo) {
     S.sh = (uint32_t)((bo + l) & 1) * 16u;  // parity of bo + 64 t + l
     const int64_t w0 = (bo + l) >> 1;         // word of bo + 64 t + l: w0 + 32 t
 #pragma unroll
     for (int t = 0; t < kR; ++t) {
-      S.x[t] = a.vals[bo + 64 * t + l];
+      if constexpr (kLS)  // the word holding the entry's fp16 weight
+        S.x[t] = __uint_as_float(winw[w0 + 32 * t]);
+      else
+        S.x[t] = a.vals[bo + 64 * t + l];
       S.pw[t] = posw[w0 + 32 * t];
     }
   };
@@ -498,7 +508,8 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
 #pragma unroll
     for (int t = 0; t < 4 && t < kR; ++t) {
       const int i = 64 * t + l;
-      entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i, &wk[t]);
+      entry(kLS ? __uint_as_float(__float_as_uint(C.x[t]) >> C.sh) : C.x[t], C.pw[t] >> C.sh,
+            i < nent, bo_cur + i, &wk[t]);
     }
     // interleave: a wave waits at every product it issues while the matrix core is busy
     // with the previous one, so the vector work of the entries goes in between
@@ -515,14 +526,17 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
 #pragma unroll
         for (int t = t0; t < t0 + 4; ++t) {
           const int i = 64 * t + l;
-          entry(C.x[t], C.pw[t] >> C.sh, i < nent, bo_cur + i, nullptr);
+          entry(kLS ? __uint_as_float(__float_as_uint(C.x[t]) >> C.sh) : C.x[t], C.pw[t] >> C.sh,
+                i < nent, bo_cur + i, nullptr);
         }
       }
     }
     for (int i0 = 64 * kR; i0 < nent; i0 += 64) {  // dense blocks: remaining rounds
       const int i = i0 + l;
       const bool valid = i < nent;
-      const float x = valid ? a.vals[bo_cur + i] : 0.f;
+      float x = 0.f;
+      if constexpr (kLS) x = valid ? __uint_as_float((uint32_t)a.win[bo_cur + i]) : 0.f;
+      else x = valid ? a.vals[bo_cur + i] : 0.f;
       const uint32_t p = valid ? (uint32_t)a.pos[bo_cur + i] : 0u;
       entry(x, p, valid, bo_cur + i, nullptr);
     }
@@ -543,7 +557,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
 #pragma unroll
         for (int t = 0; t < 4 && t < kR; ++t) {
           const int i = 64 * t + l;
-          a.wout[i < nent ? bo_cur + i : a.nobs + l] = wk[t];
+          a.wout[i < nent ? bo_cur + i : a.nobs + l] = f16_bits(wk[t]);
         }
       }
     }

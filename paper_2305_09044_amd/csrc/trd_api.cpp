@@ -60,7 +60,7 @@ struct trd_ctx {
   // Vb (and Vb_lo) in operand-fragment order, and Vb transposed in fragment order
   uint16_t* Vf = nullptr; uint16_t* Vf_lo = nullptr; uint16_t* VTf = nullptr;
   // per-entry weights of the last gradient pass (tile layouts), read by its line search
-  float* wts = nullptr;
+  uint16_t* wts = nullptr;  // fp16
   int64_t cap_wts = 0;
   int64_t cap_Tb = 0, cap_Vb = 0, cap_Tlo = 0, cap_Vlo = 0, cap_Vf = 0, cap_Vflo = 0;
 
@@ -444,10 +444,11 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   CK(launch_tile_build(T, ctx->mask, ctx->X, ctx->dtype, true, st));
   // weights: one per entry, the same slack (the line search reads them like values; the
   // gradient pass's lanes past a block's end write their own slots past nobs); zeroed once
-  if (T.nobs + kTileSlack > ctx->cap_wts) {
-    TRY(alloc_n(ctx, &ctx->wts, T.nobs + kTileSlack));
-    CK(launch_zero(ctx->wts, (size_t)(T.nobs + kTileSlack) * sizeof(float), st));
-    ctx->cap_wts = T.nobs + kTileSlack;
+  // (fp16, read as aligned 32-bit words: one element more for an odd count)
+  if (T.nobs + kTileSlack + 1 > ctx->cap_wts) {
+    TRY(alloc_n(ctx, &ctx->wts, T.nobs + kTileSlack + 1));
+    CK(launch_zero(ctx->wts, (size_t)(T.nobs + kTileSlack + 1) * sizeof(uint16_t), st));
+    ctx->cap_wts = T.nobs + kTileSlack + 1;
   }
   T.ready = true;
   return TRD_OK;
@@ -715,7 +716,7 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   a.nobs = TL.nobs;
   if (mode == kModeGrad || mode == kModeGradFast) a.wout = ctx->wts;
   if (mode == kModeLS) {  // weights of this update's gradient pass; q needs no split tables
-    a.vals = ctx->wts;
+    a.win = ctx->wts;
     a.T_lo = nullptr;
     a.Vf_lo = nullptr;
   }

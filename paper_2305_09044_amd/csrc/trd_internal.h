@@ -246,9 +246,9 @@ struct TPassArgs {
   const int64_t* boff;
   const float* vals;
   const uint16_t* pos;
-  float* wout;           // gradient modes: weight per observed entry, in value order, with
-                         // one slot per lane past nobs (or nullptr); the line search reads
-                         // them back through `vals`
+  uint16_t* wout;        // gradient modes: weight per observed entry (fp16), in value order,
+                         // with one slot per lane past nobs (or nullptr)
+  const uint16_t* win;   // line search: those weights
   int64_t nobs;
   float* resid;          // kModeResid: |e| per observed entry, in value order
   uint32_t* qhist;       // kModeResid: first-digit histogram of the |e| keys (or nullptr)

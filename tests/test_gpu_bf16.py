@@ -28,6 +28,8 @@ SHAPES = [
     ((37, 41, 29, 23), (2, 3, 4, 2)),     # non-uniform ranks
     ((70, 60, 50), (5, 5, 5)),            # 3000 columns: several column tiles
     ((21, 19, 17), (8, 8, 8)),            # r_k r_s = 64 -> K = 64
+    ((48, 40, 36), (8, 8, 8)),            # K = 64, full blocks of ~820 entries: eight
+                                          # register rounds and the rounds read past them
     ((300, 257), (4, 3)),                 # N = 2
 ]
 
