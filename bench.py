@@ -254,10 +254,13 @@ def main():
 
     # roofline of the fused gradient pass.  Algorithmic bytes per launch: every observed
     # entry is read once as a 4 B value and a 2 B position (in-tile column for the FP32
-    # sliced-ELL pass, in-block position for the BF16 matrix-core pass).
+    # sliced-ELL pass, in-block position for the BF16 matrix-core pass); the BF16 pass also
+    # writes the entry's weight (2 B, fp16) for the line search, the optional weight term of
+    # the per-entry accounting of the fused pass.
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     ent = prof["entries"] / max(prof["launches"], 1)
-    bytes_per_launch = ent * (4 + 2)
+    bytes_per_entry = 4 + 2 + (2 if prec != "native" else 0)
+    bytes_per_launch = ent * bytes_per_entry
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE) and sk is None:
@@ -269,7 +272,7 @@ def main():
             "kernel": ("k_tpass<K,GradFast> (MFMA bf16 reconstruct+weight+gradient)" if prec != "native"
                        else "k_pass<float,RC,GradFast> (fused reconstruct+weight+gradient)"),
             "avg_launch_ms": round(avg_ms, 5), "launches": prof["launches"],
-            "bytes_per_launch": int(bytes_per_launch)}
+            "bytes_per_entry": bytes_per_entry, "bytes_per_launch": int(bytes_per_launch)}
 
     out = {"metric": METRIC, "value": value, "unit": "observed entries/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
