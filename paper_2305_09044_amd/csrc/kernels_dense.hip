@@ -767,7 +767,8 @@ __global__ __launch_bounds__(256) void k_qhist(const float* __restrict__ keys,
     for (int u = 0; u < 4; ++u) {
       const int64_t i = 4 * i4 + u;
       const bool in = i < n;
-      const uint32_t key = in ? __float_as_uint(full ? kv[u] : keys[i]) : 0u;
+      // the key of a residual is its magnitude: the sign bit is dropped
+      const uint32_t key = in ? (__float_as_uint(full ? kv[u] : keys[i]) & 0x7fffffffu) : 0u;
       const bool match = in && (hi_shift >= 32 || (key >> hi_shift) == prefix);
       if (match) atomicAdd(&lh[(key >> shift) & (nb - 1u)], 1u);
     }

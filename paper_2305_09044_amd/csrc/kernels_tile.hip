@@ -178,6 +178,7 @@ size_t tpass_lds(int mode, int K, int CW) {
   (void)K;
   (void)CW;
   if (mode == kModeGrad || mode == kModeGradFast) return (size_t)kXBytes + kYBytes;
+  if (mode == kModeGradE) return (size_t)kYBytes;  // the y tiles only
   if (mode == kModeLS) return (size_t)kXBytes;  // the q tile only
   if (mode == kModeResid) return (size_t)kXBytes + kQHistBytes;
   return (size_t)kXBytes;
@@ -193,11 +194,13 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
   constexpr int KS = K / 16;       // k-steps of the reconstruction MFMA
   constexpr int MT = K / 32;       // m-tiles of the gradient MFMA
   constexpr int kR = TileRounds<K, SPLIT, WIDE>::v;  // entry rounds of 64 in registers per chunk
-  constexpr bool kGrad = MODE == kModeGrad || MODE == kModeGradFast;
+  constexpr bool kGradE = MODE == kModeGradE;
+  constexpr bool kGrad = MODE == kModeGrad || MODE == kModeGradFast || kGradE;
   constexpr bool kLS = MODE == kModeLS;
   // the line search reads the weights the gradient pass stored (same cores, sigma and
   // layout, so the same values) and needs only the products q, not xhat
-  constexpr bool kRecon = !kLS;
+  // so does the gradient pass that reads the residuals of the residual pass (kGradE)
+  constexpr bool kRecon = !kLS && !kGradE;
   constexpr bool kStats = MODE == kModeGrad || MODE == kModeLoss;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // the wave index is uniform over the wave: keep it (and everything derived from it:
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
   const int l = threadIdx.x & 63, h = l >> 5, li = l & 31;
   float* Xs = reinterpret_cast<float*>(smem_raw) + w * kXTile;
   float* Qs = Xs;  // LS: the q tile in place of the xhat tile
-  uint16_t* Ys = reinterpret_cast<uint16_t*>(smem_raw + kXBytes) + w * kYTile;       // grad
+  uint16_t* Ys = reinterpret_cast<uint16_t*>(smem_raw + (kRecon ? kXBytes : 0)) + w * kYTile;  // grad
   uint32_t* qh = reinterpret_cast<uint32_t*>(smem_raw + kXBytes);                     // resid
   if constexpr (MODE == kModeResid) {
     if (a.qhist) {
@@ -284,8 +287,13 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
       f0 = fmaf(valid ? wv * q : 0.f, q, f0);
       return;
     }
-    const float xh = Xs[pi];
-    const float e = x - xh;
+    float e;
+    if constexpr (kGradE) {
+      e = x;  // the stored residual
+    } else {
+      const float xh = Xs[pi];
+      e = x - xh;
+    }
     const float wgt = __builtin_amdgcn_exp2f(-(e * e * k2));
     if constexpr (kGrad) {
       Ys[valid ? pi : 32] = __builtin_bit_cast(uint16_t, (__bf16)(wgt * e));
@@ -295,8 +303,8 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
       else if (a.wout) a.wout[valid ? idx : a.nobs + l] = f16_bits(wgt);
     }
     if constexpr (MODE == kModeResid) {
-      if (valid) {
-        a.resid[idx] = fabsf(e);
+      if (valid) {  // e itself (a later gradient pass may reuse it); the keys are |e|
+        a.resid[idx] = e;
         if (a.qhist) atomicAdd(&qh[__float_as_uint(fabsf(e)) >> 21], 1u);
       }
     }
@@ -363,6 +371,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
   bf16x8 av[KS];
   bf16x8 avlo[SPLIT ? KS : 1];
   auto load_av = [&](int64_t gc) {
+    if constexpr (!kRecon && !kLS) return;  // no reconstruction-side products
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       av[s] = *reinterpret_cast<const bf16x8*>(a.Vf + gc * 32 * K + s * 512 + l * 8);
@@ -514,7 +523,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
     // interleave: a wave waits at every product it issues while the matrix core is busy
     // with the previous one, so the vector work of the entries goes in between
     // (not in the split form, whose registers are too tight for the longer live ranges)
-    constexpr int kMfma = SPLIT ? 0 : KS * 2 + (kGrad ? 4 * MT : 0);
+    constexpr int kMfma = SPLIT ? 0 : (kRecon || kLS ? KS * 2 : 0) + (kGrad ? 4 * MT : 0);
 #pragma unroll
     for (int i = 0; i < kMfma; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core product
@@ -727,6 +736,9 @@ static hipError_t launch_k(int mode, const TPassArgs& a, hipStream_t st) {
     case kModeResid:
       hipLaunchKernelGGL((k_tpass<K, kModeResid, SPLIT, WIDE>), g, b, lds, st, a);
       break;
+    case kModeGradE:
+      hipLaunchKernelGGL((k_tpass<K, kModeGradE, SPLIT, WIDE>), g, b, lds, st, a);
+      break;
     default: hipLaunchKernelGGL((k_tpass<K, kModeLoss, SPLIT, WIDE>), g, b, lds, st, a); break;
   }
   return hipGetLastError();
@@ -751,7 +763,8 @@ hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {
     return hipErrorInvalidValue;
   // the fragment tables hold n_chunks + 1 chunks (tile_frag_elems), the passes read one
   // chunk ahead; the gradient products need the transposed one
-  if (a.Vf == nullptr || ((mode == kModeGrad || mode == kModeGradFast) && a.VTf == nullptr))
+  if (a.Vf == nullptr ||
+      ((mode == kModeGrad || mode == kModeGradFast || mode == kModeGradE) && a.VTf == nullptr))
     return hipErrorInvalidValue;
   switch (K) {
     case 32: return launch_ks<32>(mode, a, st);

@@ -81,6 +81,9 @@ struct trd_ctx {
   double* scal = nullptr;         // device scalars, see kS* below
   uint32_t* flags = nullptr;      // [0] step flags, [1] fit flags
   float* resid = nullptr; int64_t cap_resid = 0;
+  // core whose current residuals (tile layout, value order) the residual pass left in
+  // resid, or -1: that core's next gradient pass reads them instead of forming xhat
+  int resid_core = -1;
   uint32_t* qhist = nullptr; uint32_t* qstate = nullptr;
   double* Dbuf[2] = {nullptr, nullptr}; double* M = nullptr;
   double* eta_hist = nullptr;     // [N] per sweep
@@ -695,8 +698,6 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   a.resid = ctx->resid;
   // the residual pass also counts the first quantile digit (launch_quantile_init first)
   a.qhist = mode == kModeResid ? ctx->qhist : nullptr;
-  // the residual pass also counts the first quantile digit (launch_quantile_init first)
-  a.qhist = mode == kModeResid ? ctx->qhist : nullptr;
   a.partials = ctx->part_pass;
   a.sigma = ctx->scal + kSigma;
   a.nrows = TL.nrows;
@@ -714,7 +715,12 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   // positions): below that, a block rarely needs a fifth round from memory
   a.rounds = TL.n_blocks > 0 && TL.nobs > 224 * TL.n_blocks ? 8 : 4;
   a.nobs = TL.nobs;
-  if (mode == kModeGrad || mode == kModeGradFast) a.wout = ctx->wts;
+  if (mode == kModeGrad || mode == kModeGradFast || mode == kModeGradE) a.wout = ctx->wts;
+  if (mode == kModeGradE) {  // the residual pass's e; no reconstruction, no split tables
+    a.vals = ctx->resid;
+    a.T_lo = nullptr;
+    a.Vf_lo = nullptr;
+  }
   if (mode == kModeLS) {  // weights of this update's gradient pass; q needs no split tables
     a.win = ctx->wts;
     a.T_lo = nullptr;
@@ -781,7 +787,9 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   TRY(build_rowtable(ctx, up, cores[sp.k], Uref, nB, ctx->T, st));
   TRY(build_coltable(ctx, up, cores, st));
   TRY(ensure_S(ctx, (int64_t)up_nct(up) * L.nrows * sp.RRP));
-  TRY(run_pass(ctx, up, stats_dev ? kModeGrad : kModeGradFast, st));
+  const bool reuse_e = !stats_dev && up.TL && ctx->resid_core == sp.k;
+  TRY(run_pass(ctx, up, stats_dev ? kModeGrad : (reuse_e ? kModeGradE : kModeGradFast), st));
+  ctx->resid_core = -1;  // the core changes with this update
   if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, stats_dev, st));
   // a few column-group partials are added by the contraction as it loads S; many are
   // first summed by a streaming kernel
@@ -1263,10 +1271,13 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
       // residual slots: ELL slots (padding holds +inf) or exactly the observed entries
       const int64_t nkeys = up.TL ? up.TL->nobs : L.slots_cap;
       const int64_t* nkeys_dev = up.TL ? up.TL->total_dev : L.total_dev;
-      if (nkeys > ctx->cap_resid) {
-        TRY(alloc_n(ctx, &ctx->resid, nkeys));
-        ctx->cap_resid = nkeys;
+      // (tile layouts: the same slack as the values, for the gradient pass that reads e)
+      const int64_t need = up.TL ? nkeys + kTileSlack : nkeys;
+      if (need > ctx->cap_resid) {
+        TRY(alloc_n(ctx, &ctx->resid, need));
+        ctx->cap_resid = need;
       }
+      ctx->resid_core = -1;
       int64_t needT, needV, needU, needC;
       table_needs(ctx, up.sp, up.counts, L.nrows, L.ncols, needT, needV, needU, needC);
       TRY(ensure_tables(ctx, needT, needV, needU, needC));
@@ -1278,6 +1289,7 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
       TRY(build_coltable(ctx, up, (const void* const*)cores, st));
       if (up.TL) CK(launch_quantile_init(up_nobs_dev(up), o->q, ctx->qstate, ctx->qhist, st));
       TRY(run_pass(ctx, up, kModeResid, st));
+      if (up.TL) ctx->resid_core = 0;  // core 0's update reads these residuals
       CK(launch_quantile_sigma(ctx->resid, nkeys, nkeys_dev, o->q, o->c, ctx->scal + kSigmaMin,
                                o->shrink, ctx->scal + kSigma, ctx->qhist, ctx->qstate,
                                up_nobs_dev(up), up.TL != nullptr, st));

@@ -144,7 +144,10 @@ hipError_t launch_contract_finish(int dtype, const double* part, int nchunk, int
                                   double* d64, void* d_out, double scale, hipStream_t st);
 
 // fused entry pass
-enum PassMode { kModeGrad = 0, kModeLS = 1, kModeResid = 2, kModeLoss = 3, kModeGradFast = 4 };
+enum PassMode { kModeGrad = 0, kModeLS = 1, kModeResid = 2, kModeLoss = 3, kModeGradFast = 4,
+                // matrix-core passes only: GradFast reading the residuals the residual pass
+                // stored for the same cores and layout (through `vals`) instead of forming xhat
+                kModeGradE = 5 };
 struct PassArgs {
   const void* T;        // [nrows][RRP]
   const void* TH;       // [nrows][RRP] (line search)
@@ -250,7 +253,7 @@ struct TPassArgs {
                          // with one slot per lane past nobs (or nullptr)
   const uint16_t* win;   // line search: those weights
   int64_t nobs;
-  float* resid;          // kModeResid: |e| per observed entry, in value order
+  float* resid;          // kModeResid: e per observed entry, in value order
   uint32_t* qhist;       // kModeResid: first-digit histogram of the |e| keys (or nullptr)
   double* partials;      // [n_wg][3]
   const double* sigma;
