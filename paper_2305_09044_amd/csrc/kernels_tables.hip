@@ -478,9 +478,85 @@ static void contract_real(dim3 g, dim3 b, hipStream_t st, const void* S, int RRP
   else contract_r<real, 16>(g, b, st, S, RRP, n_ct, pstride, Ik, nB, r_k, r_s, r_k1, U, part, nchunk);
 }
 
+// The same contraction for r_k = r_s = r_{k+1} = 8 (FP32 partials, RRP = 64): a work-group
+// takes 32 slices i_k and a range of m_B; per m_B it loads the 32 rows of every partial as
+// whole contiguous kilobytes, adds the partials in the same order as k_contract, and keeps
+// the sum (and the U item) in LDS for the (i_k, a) threads.  Each thread's sums run in the
+// same order as in k_contract, so the results are the same.
+__global__ __launch_bounds__(256) void k_contract8(const float* __restrict__ S, int n_ct,
+                                                   int64_t pstride, int64_t Ik, int64_t nB,
+                                                   const float* __restrict__ U, int64_t Us,
+                                                   const int32_t* __restrict__ Ulist,
+                                                   double* __restrict__ part, int nchunk) {
+  constexpr int RS = 72;  // LDS row stride: lanes (i_k, a) read distinct banks
+  __shared__ __align__(16) float Ss[2][32 * RS];
+  __shared__ float Ush[2][64];
+  const int t = threadIdx.x;
+  const int64_t ik0 = (int64_t)blockIdx.x * 32;
+  const int chunk = blockIdx.y;
+  const int64_t per = (nB + nchunk - 1) / nchunk;
+  const int64_t m0 = chunk * per, m1 = min(nB, m0 + per);
+  const int ikl = t >> 3, a = t & 7;
+  const bool ok = ik0 + ikl < Ik;
+  // this thread's two 16-byte pieces of the 32 x 64 block: rows f / 16, columns 4 (f % 16)
+  float4 pre[2][4];
+  float upre = 0.f;
+  auto load = [&](int64_t m) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int f = t + 256 * u, row = f >> 4, c4 = f & 15;
+      const bool in = m < m1 && ik0 + row < Ik;
+      const float* sp = S + (ik0 + row + Ik * m) * 64 + 4 * c4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        pre[u][q] = (in && q < n_ct) ? *reinterpret_cast<const float4*>(sp + (int64_t)q * pstride)
+                                     : float4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (t < 64) upre = m < m1 ? U[(Ulist ? (int64_t)Ulist[m] : m) * Us + t] : 0.f;
+  };
+  double acc[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) acc[b] = 0.0;
+  load(m0);
+  for (int64_t m = m0; m < m1; ++m) {
+    const int buf = (int)((m - m0) & 1);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int f = t + 256 * u, row = f >> 4, c4 = f & 15;
+      const float4 p0 = pre[u][0], p1 = pre[u][1], p2 = pre[u][2], p3 = pre[u][3];
+      *reinterpret_cast<float4*>(&Ss[buf][row * RS + 4 * c4]) =
+          float4{(p0.x + p1.x) + (p2.x + p3.x), (p0.y + p1.y) + (p2.y + p3.y),
+                 (p0.z + p1.z) + (p2.z + p3.z), (p0.w + p1.w) + (p2.w + p3.w)};
+    }
+    if (t < 64) Ush[buf][t] = upre;
+    __syncthreads();
+    load(m + 1);  // the next m_B's rows in flight while this one is used
+    if (ok) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double sv = (double)Ss[buf][ikl * RS + a + 8 * c];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[b] = fma(sv, (double)Ush[buf][b + 8 * c], acc[b]);
+      }
+    }
+  }
+  if (ok) {
+    double* pp = part + ((int64_t)chunk * Ik + ik0 + ikl) * 64 + a;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) pp[8 * b] = acc[b];
+  }
+}
+
 hipError_t launch_contract(int dtype, const void* S, int RRP, int n_ct, int64_t pstride,
                            int64_t Ik, int64_t nB, int r_k, int r_s, int r_k1, ItemRef U,
                            double* part, int nchunk, hipStream_t st) {
+  if (dtype == 0 && r_k == 8 && r_s == 8 && r_k1 == 8 && RRP == 64 && U.ptr && n_ct >= 1 &&
+      n_ct <= 4 && pstride % 4 == 0 && reinterpret_cast<uintptr_t>(S) % 16 == 0) {
+    dim3 g((unsigned)((Ik + 31) / 32), (unsigned)nchunk), b(256);
+    hipLaunchKernelGGL(k_contract8, g, b, 0, st, (const float*)S, n_ct, pstride, Ik, nB,
+                       (const float*)U.ptr, U.stride, U.list, part, nchunk);
+    return hipGetLastError();
+  }
   if (r_k1 > kMaxRank || r_s > kMaxRank || r_k * r_s > RRP || (!U.ptr && r_s != r_k1) ||
       r_k1 * r_s > 256 || n_ct < 1 || n_ct > 4)
     return hipErrorInvalidValue;
