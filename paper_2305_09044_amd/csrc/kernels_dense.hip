@@ -743,14 +743,22 @@ hipError_t launch_reconstruct(int dtype, int N, const int64_t* dims, const int32
 // (padding slots hold +inf and sort last), digits of 11, 11 and 10 bits.
 // state: [0] prefix, [1] remaining rank (as uint32 pair), [3] valid.
 
+// With cand, the matching keys are also copied to this work-group's segment of cand
+// (seg_cap keys from blockIdx.x * seg_cap; count in cand_cnt[blockIdx.x]), so that the next
+// digit scans only them (k_qhist_seg).
 __global__ __launch_bounds__(256) void k_qhist(const float* __restrict__ keys,
                                                const int64_t* __restrict__ nslots, int shift,
                                                int bits, const uint32_t* __restrict__ state,
-                                               uint32_t* __restrict__ hist) {
+                                               uint32_t* __restrict__ hist,
+                                               float* __restrict__ cand,
+                                               uint32_t* __restrict__ cand_cnt, int64_t seg_cap) {
   __shared__ uint32_t lh[2048];
+  __shared__ uint32_t ncand;
   const uint32_t nb = 1u << bits;
   for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) lh[i] = 0u;
+  if (threadIdx.x == 0) ncand = 0u;
   __syncthreads();
+  float* seg = cand ? cand + (int64_t)blockIdx.x * seg_cap : nullptr;
   const int64_t n = *nslots;
   const uint32_t prefix = state[0];
   const int hi_shift = shift + bits;
@@ -771,7 +779,39 @@ __global__ __launch_bounds__(256) void k_qhist(const float* __restrict__ keys,
       const uint32_t key = in ? (__float_as_uint(full ? kv[u] : keys[i]) & 0x7fffffffu) : 0u;
       const bool match = in && (hi_shift >= 32 || (key >> hi_shift) == prefix);
       if (match) atomicAdd(&lh[(key >> shift) & (nb - 1u)], 1u);
+      if (seg) {  // uniform over the wave: one LDS counter update per wave and key slot
+        const uint64_t bal = __ballot(match);
+        const int lane = threadIdx.x & 63;
+        uint32_t off = 0u;
+        if (lane == 0 && bal) off = atomicAdd(&ncand, (uint32_t)__popcll(bal));
+        off = __shfl(off, 0);
+        if (match) seg[off + __popcll(bal & ((1ull << lane) - 1ull))] = __uint_as_float(key);
+      }
     }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+    if (lh[i]) atomicAdd(&hist[i], lh[i]);
+  if (seg && threadIdx.x == 0) cand_cnt[blockIdx.x] = ncand;
+}
+
+// the same digit histogram over the candidates k_qhist left in the segments
+__global__ __launch_bounds__(256) void k_qhist_seg(const float* __restrict__ cand,
+                                                   const uint32_t* __restrict__ cand_cnt,
+                                                   int64_t seg_cap, int shift, int bits,
+                                                   const uint32_t* __restrict__ state,
+                                                   uint32_t* __restrict__ hist) {
+  __shared__ uint32_t lh[2048];
+  const uint32_t nb = 1u << bits;
+  for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) lh[i] = 0u;
+  __syncthreads();
+  const uint32_t n = cand_cnt[blockIdx.x];
+  const float* seg = cand + (int64_t)blockIdx.x * seg_cap;
+  const uint32_t prefix = state[0];
+  const int hi_shift = shift + bits;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t key = __float_as_uint(seg[i]) & 0x7fffffffu;
+    if (hi_shift >= 32 || (key >> hi_shift) == prefix) atomicAdd(&lh[(key >> shift) & (nb - 1u)], 1u);
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
@@ -838,6 +878,14 @@ __global__ void k_qsigma(const uint32_t* state, double c, const double* sigma_mi
   *sigma = s;
 }
 
+int quantile_grid(int64_t n_slots_hint) { return grid_for(n_slots_hint, 256, 2048); }
+// keys one work-group of the histogram grid can see: its float4 groups times four
+int64_t quantile_seg_cap(int64_t n_slots_hint) {
+  const int64_t g = quantile_grid(n_slots_hint);
+  const int64_t n4 = (n_slots_hint + 3) / 4;
+  return std::max<int64_t>((n4 + g * 256 - 1) / (g * 256), 1) * 1024;
+}
+
 hipError_t launch_quantile_init(const int64_t* nobs, double q, uint32_t* state, uint32_t* hist,
                                 hipStream_t st) {
   hipLaunchKernelGGL(k_qinit, dim3(1), dim3(1), 0, st, nobs, q, state, hist);
@@ -847,15 +895,22 @@ hipError_t launch_quantile_init(const int64_t* nobs, double q, uint32_t* state, 
 hipError_t launch_quantile_sigma(const float* keys, int64_t n_slots_hint, const int64_t* nslots,
                                  double q, double c, const double* sigma_min, double shrink,
                                  double* sigma, uint32_t* hist, uint32_t* state,
-                                 const int64_t* nobs, bool first_digit_done, hipStream_t st) {
+                                 const int64_t* nobs, float* cand, uint32_t* cand_cnt,
+                                 bool first_digit_done, hipStream_t st) {
   if (!first_digit_done) hipLaunchKernelGGL(k_qinit, dim3(1), dim3(1), 0, st, nobs, q, state, hist);
   const int shifts[3] = {21, 10, 0};
   const int bitsv[3] = {11, 11, 10};
-  const int g = grid_for(n_slots_hint, 256, 2048);
+  const int g = quantile_grid(n_slots_hint);
+  const int64_t seg = quantile_seg_cap(n_slots_hint);
   for (int r = 0; r < 3; ++r) {
-    if (r > 0 || !first_digit_done)
+    // the second digit also collects the keys that share the first one (per work-group
+    // segments), the third scans only those
+    if (r == 2 && cand)
+      hipLaunchKernelGGL(k_qhist_seg, dim3(g), dim3(256), 0, st, (const float*)cand,
+                         (const uint32_t*)cand_cnt, seg, shifts[r], bitsv[r], state, hist);
+    else if (r > 0 || !first_digit_done)
       hipLaunchKernelGGL(k_qhist, dim3(g), dim3(256), 0, st, keys, nslots, shifts[r], bitsv[r],
-                         state, hist);
+                         state, hist, r == 1 ? cand : (float*)nullptr, cand_cnt, seg);
     hipLaunchKernelGGL(k_qpick, dim3(1), dim3(1024), 0, st, bitsv[r], state, hist);
   }
   hipLaunchKernelGGL(k_qsigma, dim3(1), dim3(1), 0, st, state, c, sigma_min, shrink, sigma);

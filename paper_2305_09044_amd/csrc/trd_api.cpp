@@ -85,6 +85,7 @@ struct trd_ctx {
   // resid, or -1: that core's next gradient pass reads them instead of forming xhat
   int resid_core = -1;
   uint32_t* qhist = nullptr; uint32_t* qstate = nullptr;
+  float* qcand = nullptr; uint32_t* qcand_cnt = nullptr; int64_t cap_qcand = 0, cap_qcnt = 0;
   double* Dbuf[2] = {nullptr, nullptr}; double* M = nullptr;
   double* eta_hist = nullptr;     // [N] per sweep
   double* host_rep = nullptr;     // mapped pinned host memory for the per-sweep report
@@ -782,12 +783,16 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
     TRY(dev_alloc(ctx, &ctx->h_real, nd * esz(ctx->dtype)));
     ctx->cap_d = nd;
   }
+  // the residual pass of this sweep left e for this core: the gradient pass reads it, needs
+  // no row table, and the column tables that pass built (same cores) are still in place
+  const bool reuse_e = !stats_dev && up.TL && ctx->resid_core == sp.k;
   ItemRef Uref;
   TRY(build_U(ctx, up, cores, Uref, nB, st));
-  TRY(build_rowtable(ctx, up, cores[sp.k], Uref, nB, ctx->T, st));
-  TRY(build_coltable(ctx, up, cores, st));
+  if (!reuse_e) {
+    TRY(build_rowtable(ctx, up, cores[sp.k], Uref, nB, ctx->T, st));
+    TRY(build_coltable(ctx, up, cores, st));
+  }
   TRY(ensure_S(ctx, (int64_t)up_nct(up) * L.nrows * sp.RRP));
-  const bool reuse_e = !stats_dev && up.TL && ctx->resid_core == sp.k;
   TRY(run_pass(ctx, up, stats_dev ? kModeGrad : (reuse_e ? kModeGradE : kModeGradFast), st));
   ctx->resid_core = -1;  // the core changes with this update
   if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, stats_dev, st));
@@ -1277,6 +1282,17 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
         TRY(alloc_n(ctx, &ctx->resid, need));
         ctx->cap_resid = need;
       }
+      {  // per work-group candidate segments of the quantile's third digit
+        const int64_t ng = quantile_grid(nkeys), ncand = ng * quantile_seg_cap(nkeys);
+        if (ncand > ctx->cap_qcand) {
+          TRY(alloc_n(ctx, &ctx->qcand, ncand));
+          ctx->cap_qcand = ncand;
+        }
+        if (ng > ctx->cap_qcnt) {
+          TRY(alloc_n(ctx, &ctx->qcand_cnt, ng));
+          ctx->cap_qcnt = ng;
+        }
+      }
       ctx->resid_core = -1;
       int64_t needT, needV, needU, needC;
       table_needs(ctx, up.sp, up.counts, L.nrows, L.ncols, needT, needV, needU, needC);
@@ -1292,7 +1308,7 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
       if (up.TL) ctx->resid_core = 0;  // core 0's update reads these residuals
       CK(launch_quantile_sigma(ctx->resid, nkeys, nkeys_dev, o->q, o->c, ctx->scal + kSigmaMin,
                                o->shrink, ctx->scal + kSigma, ctx->qhist, ctx->qstate,
-                               up_nobs_dev(up), up.TL != nullptr, st));
+                               up_nobs_dev(up), ctx->qcand, ctx->qcand_cnt, up.TL != nullptr, st));
     }
     for (int k = 0; k < N; ++k) {
       TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st));

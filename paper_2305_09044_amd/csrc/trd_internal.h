@@ -284,9 +284,15 @@ hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st);
 // the state and counts every digit itself.
 hipError_t launch_quantile_init(const int64_t* nobs, double q, uint32_t* state, uint32_t* hist,
                                 hipStream_t st);
+// cand (quantile_grid(n_slots_hint) * quantile_seg_cap(n_slots_hint) keys) and cand_cnt
+// (quantile_grid(n_slots_hint) counts), or nullptr: the keys sharing the first digit,
+// gathered by the second digit's pass for the third
+int quantile_grid(int64_t n_slots_hint);
+int64_t quantile_seg_cap(int64_t n_slots_hint);
 hipError_t launch_quantile_sigma(const float* keys, int64_t n_slots_hint, const int64_t* nslots,
                                  double q, double c, const double* sigma_min, double shrink,
                                  double* sigma, uint32_t* hist, uint32_t* state,
-                                 const int64_t* nobs, bool first_digit_done, hipStream_t st);
+                                 const int64_t* nobs, float* cand, uint32_t* cand_cnt,
+                                 bool first_digit_done, hipStream_t st);
 
 }  // namespace trd
