@@ -124,8 +124,11 @@ def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, s
     sketch: None for the full path (AWRTRD), else index lists I_1..I_N (RStS,
     eqs. 14-18): the gradient and the line search use the subtensor, the Gram matrix
     always uses the full cores.
-    gram: 'fgmc' (eq. 13) or 'explicit' (A^T A).
-    direction: 'scaled' (eq. 10) or 'gradient' (plain steepest descent with d).
+    gram: 'fgmc' (eq. 13) or 'explicit' (A^T A), both of the full cores; or 'local',
+    the ablation of Sec. 6.1 that scales with the Gram matrix of the sampled cores only,
+    A_I^T A_I of the sketched subchain unfolding (the full one without a sketch).
+    direction: 'scaled' (eq. 10 / 16) or 'gradient' (the ablation of Sec. 6.1 that steps
+    along d of eq. 9 / 15 itself, with the same exact line search).
     """
     N = len(cores)
     if sketch is None:
@@ -143,7 +146,12 @@ def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, s
     E = np.where(Pk, Xk - Zk2 @ A.T, 0.0)               # residual on observed entries
     W = np.where(Pk, weights(E, sigma), 0.0)            # eq. (7)
     d = (W * E) @ A                                      # eq. (9) / (15)
-    G = gram_fgmc(cores, k) if gram == "fgmc" else gram_explicit(cores, k)
+    if gram == "local":
+        G = A.T @ A
+    elif gram == "fgmc":
+        G = gram_fgmc(cores, k)
+    else:
+        G = gram_explicit(cores, k)
     if direction == "scaled":
         R2 = G.shape[0]
         lam = lambda_rel * np.trace(G) / R2

@@ -273,6 +273,46 @@ def test_gradient_direction_variant_also_descends():
     assert _wls(X, P, Z, 2, info.W, tr.unfold_core(new)) < _wls(X, P, Z, 2, info.W, tr.unfold_core(Z[2]))
 
 
+def test_gradient_direction_steps_along_d_with_exact_eta():
+    # ablation of Sec. 6.1: h = d of eq. (15); eta of eq. (18) is still the exact minimiser
+    dims, ranks = (4, 3, 3), (2, 2, 3)
+    Z, P, X = _masked_problem(dims, ranks, 37)
+    k = 0
+    sk = orng.sketch_indices(9, 1, k, dims, (4, 2, 2))
+    new, info = aw.core_update(X, P, Z, k, 0.7, sketch=sk, direction="gradient")
+    np.testing.assert_array_equal(info.h, info.d)
+    assert info.num == pytest.approx(float(np.sum(info.d * info.d)), rel=1e-14)
+    Zs = [z[:, s, :] for z, s in zip(Z, sk)]
+    Xs, Ps = X[np.ix_(*sk)], P[np.ix_(*sk)]
+    Zk2 = tr.unfold_core(Z[k])
+    ts = np.array([0.0, 0.5, 1.0]) * 2 * info.eta
+    Ls = [_wls(Xs, Ps, Zs, k, info.W, Zk2 + t * info.d) for t in ts]
+    c2, c1, _ = np.polyfit(ts, Ls, 2)
+    assert -c1 / (2 * c2) == pytest.approx(info.eta, rel=1e-7)
+
+
+def test_local_gram_is_fgmc_of_sampled_cores():
+    # ablation of Sec. 6.1: the scaled term from the sampled cores.  A_I^T A_I must equal
+    # the FGMC product (eq. 13) of the sampled cores' factors (a route through Kronecker
+    # sums, pinned against A^T A above), differ from the global Gram, and equal it when
+    # the sketch takes every index
+    dims, ranks = (5, 4, 6, 3), (2, 3, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 38)
+    k = 2
+    sk = orng.sketch_indices(4, 0, k, dims, (3, 2, 6, 2))
+    _, info = aw.core_update(X, P, Z, k, 0.8, sketch=sk, gram="local")
+    Zs = [z[:, s, :] for z, s in zip(Z, sk)]
+    np.testing.assert_allclose(info.G, aw.gram_fgmc(Zs, k), rtol=1e-12, atol=1e-12)
+    assert np.linalg.norm(info.G - aw.gram_fgmc(Z, k)) > 1e-3 * np.linalg.norm(info.G)
+    full = [list(range(n)) for n in dims]
+    _, infg = aw.core_update(X, P, Z, k, 0.8, sketch=full, gram="local")
+    np.testing.assert_allclose(infg.G, aw.gram_fgmc(Z, k), rtol=1e-12, atol=1e-12)
+    # h solves (G_I + lambda I) h^T = d^T
+    R2 = info.G.shape[0]
+    lam = 1e-9 * np.trace(info.G) / R2
+    np.testing.assert_allclose(info.h @ (info.G + lam * np.eye(R2)), info.d, rtol=1e-8, atol=1e-10)
+
+
 def test_empty_update_gives_zero_step():
     dims, ranks = (3, 3, 3), (2, 2, 2)
     Z, _, X = _masked_problem(dims, ranks, 36)
