@@ -238,6 +238,24 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
 int trd_set_precision(trd_ctx* ctx, int precision);
 
 /*
+ * Variants of the update for the ablations of Sec. 6.1, for later trd_step / trd_fit
+ * calls on ctx (default: TRD_DIR_SCALED, TRD_GRAM_GLOBAL, the method itself).
+ *   direction TRD_DIR_GRADIENT: step along d of eq. (9) / (15) instead of the scaled
+ *     direction h of eq. (10) / (16); eta stays the exact line search of eq. (12) / (18)
+ *     with h = d, and no Gram matrix is formed.
+ *   gram TRD_GRAM_LOCAL: under an RStS sketch, scale with the Gram matrix of the sampled
+ *     cores (the factors of eq. 13 summed over the sampled slices I_j only, which is
+ *     A_I^T A_I of the sketched subchain unfolding) instead of the global one; without a
+ *     sketch the two coincide.  Ignored with TRD_DIR_GRADIENT.
+ * Returns TRD_EINVAL for other values (the context keeps its previous variant).
+ */
+#define TRD_DIR_SCALED   0
+#define TRD_DIR_GRADIENT 1
+#define TRD_GRAM_GLOBAL  0
+#define TRD_GRAM_LOCAL   1
+int trd_set_variant(trd_ctx* ctx, int direction, int gram);
+
+/*
  * Per-launch timing of the fused reconstruct+weight+gradient pass, for measurement:
  * enable != 0 records HIP events around every launch of that kernel on its stream;
  * trd_profile_read returns the number of launches and their summed duration (ms) and

@@ -26,6 +26,10 @@ TRD_EUNSUPPORTED = -6
 TRD_F32, TRD_F64 = 0, 1
 TRD_PREC_NATIVE, TRD_PREC_BF16, TRD_PREC_BF16X3 = 0, 1, 2
 PRECISIONS = {"native": TRD_PREC_NATIVE, "bf16": TRD_PREC_BF16, "bf16x3": TRD_PREC_BF16X3}
+TRD_DIR_SCALED, TRD_DIR_GRADIENT = 0, 1
+TRD_GRAM_GLOBAL, TRD_GRAM_LOCAL = 0, 1
+DIRECTIONS = {"scaled": TRD_DIR_SCALED, "gradient": TRD_DIR_GRADIENT}
+GRAMS = {"global": TRD_GRAM_GLOBAL, "local": TRD_GRAM_LOCAL}
 TRD_FLAG_EMPTY, TRD_FLAG_ZERO_DEN, TRD_FLAG_NOTSPD = 1, 2, 4
 TRD_SIGMA_FIXED, TRD_SIGMA_GIVEN, TRD_SIGMA_QUANTILE = 0, 1, 2
 
@@ -88,6 +92,7 @@ def load() -> C.CDLL:
         "trd_loss_bwd": (i32, [vp, P(vp), dbl, dbl, P(vp), vp]),
         "trd_sample_sketch": (i32, [C.c_uint64, i32, i32, i32, P(i64), P(C.c_int32), P(vp), vp]),
         "trd_set_precision": (i32, [vp, i32]),
+        "trd_set_variant": (i32, [vp, i32, i32]),
         "trd_profile": (i32, [vp, i32]),
         "trd_profile_read": (i32, [vp, P(i64), P(dbl), P(i64), P(i64)]),
     }
@@ -313,6 +318,11 @@ class Problem:
     def set_precision(self, precision: str):
         code = PRECISIONS[precision]
         _check(load().trd_set_precision(self._ctx, code), self._ctx)
+
+    def set_variant(self, direction: str = "scaled", gram: str = "global"):
+        """Update variants of the Sec. 6.1 ablations: direction 'scaled' | 'gradient',
+        gram 'global' | 'local' (the sampled cores' Gram under a sketch)."""
+        _check(load().trd_set_variant(self._ctx, DIRECTIONS[direction], GRAMS[gram]), self._ctx)
 
     def profile(self, enable: bool):
         _check(load().trd_profile(self._ctx, 1 if enable else 0), self._ctx)

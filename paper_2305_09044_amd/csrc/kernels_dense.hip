@@ -18,9 +18,11 @@ static int grid_for(int64_t n, int threads, int64_t cap = 1 << 20) {
 // ---------------------------------------------------------------- FGMC
 
 // K[(al*r0 + al2), (be*r1 + be2)] = sum_i Z(i)[al, be] * Z(i)[al2, be2]
-// one wave per output element; lanes stride over i, then a fixed-order wave reduction
+// one wave per output element; lanes stride over i, then a fixed-order wave reduction.
+// idx (nullptr: slices 0..I-1) lists the I slices to sum: the factor of a sampled core
 template <typename real>
 __global__ __launch_bounds__(256) void k_kron(const real* __restrict__ Z, int r0, int64_t I, int r1,
+                                              const int32_t* __restrict__ idx,
                                               double* __restrict__ K) {
   const int64_t n = (int64_t)r0 * r0 * r1 * r1;
   const int cols = r1 * r1;
@@ -32,7 +34,7 @@ __global__ __launch_bounds__(256) void k_kron(const real* __restrict__ Z, int r0
   const int64_t sl = (int64_t)r0 * r1;
   double s = 0.0;
   for (int64_t i = lane; i < I; i += 64) {
-    const real* zi = Z + i * sl;
+    const real* zi = Z + (idx ? (int64_t)idx[i] : i) * sl;
     s = fma((double)zi[al + r0 * be], (double)zi[al2 + r0 * be2], s);
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
@@ -40,13 +42,14 @@ __global__ __launch_bounds__(256) void k_kron(const real* __restrict__ Z, int r0
 }
 
 hipError_t launch_kron_factor(int dtype, const void* Z, int r0, int64_t I, int r1, double* K,
-                              hipStream_t st) {
+                              hipStream_t st, const int32_t* idx) {
   const int64_t n = (int64_t)r0 * r0 * r1 * r1;
   const unsigned nb = (unsigned)((n + 3) / 4);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_kron<float>, dim3(nb), dim3(256), 0, st, (const float*)Z, r0, I, r1, K);
+    hipLaunchKernelGGL(k_kron<float>, dim3(nb), dim3(256), 0, st, (const float*)Z, r0, I, r1, idx, K);
   else
-    hipLaunchKernelGGL(k_kron<double>, dim3(nb), dim3(256), 0, st, (const double*)Z, r0, I, r1, K);
+    hipLaunchKernelGGL(k_kron<double>, dim3(nb), dim3(256), 0, st, (const double*)Z, r0, I, r1, idx,
+                       K);
   return hipGetLastError();
 }
 
@@ -342,7 +345,8 @@ __global__ __launch_bounds__(256) void k_inverse64(const double* __restrict__ G,
 }
 
 // h = d Cinv (I_k x n), written in FP64 and in the problem dtype; per-block partial
-// sums of <d, h> (fixed order).  A NOTSPD flag zeroes h.
+// sums of <d, h> (fixed order).  A NOTSPD flag zeroes h.  Cinv == nullptr: h = d (the
+// unscaled direction).
 template <typename real>
 __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict__ d64,
                                                        const double* __restrict__ Cinv, int64_t Ik,
@@ -354,7 +358,7 @@ __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict_
   __shared__ double Cs[64 * 64];  // Cinv staged when n <= 64
   const int64_t total = Ik * n;
   const bool bad = (*flags & TRD_FLAG_NOTSPD_BIT) != 0;
-  const bool staged = n <= 64;
+  const bool staged = Cinv && n <= 64;
   if (staged) {  // 256 threads, at most 16 elements each, all loads in flight first
     double v[16];
 #pragma unroll
@@ -376,7 +380,9 @@ __global__ __launch_bounds__(256) void k_apply_inverse(const double* __restrict_
     const int64_t i = t / n;
     const int c = (int)(t % n);
     double s = 0.0;
-    if (!bad)
+    if (!Cinv)
+      s = d64[t];
+    else if (!bad)
       for (int l = 0; l < n; ++l) s = fma(d64[i * n + l], Cp[(int64_t)l * n + c], s);
     h64[t] = s;
     if (h_real) h_real[t] = (real)s;

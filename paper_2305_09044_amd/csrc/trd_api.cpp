@@ -55,6 +55,8 @@ struct trd_ctx {
   std::vector<Layout> layouts;    // full-path layout per core
   std::vector<TLayout> tlayouts;  // bitmask-tile layout per core (BF16 form, built on demand)
   int prec = TRD_PREC_NATIVE;     // precision of the entry passes
+  int direction = TRD_DIR_SCALED;  // step direction and Gram of later updates
+  int gram = TRD_GRAM_GLOBAL;
   uint16_t* Tb = nullptr; uint16_t* THb = nullptr; uint16_t* Vb = nullptr;
   uint16_t* Tb_lo = nullptr; uint16_t* Vb_lo = nullptr;  // split (BF16X3) remainders
   // Vb (and Vb_lo) in operand-fragment order, and Vb transposed in fragment order
@@ -69,6 +71,7 @@ struct trd_ctx {
   void* U = nullptr; void* chainA = nullptr; void* chainB = nullptr;
   int64_t cap_T = 0, cap_V = 0, cap_U = 0, cap_chain = 0, cap_S = 0;
   double* K[kMaxN] = {nullptr};
+  double* Kl[kMaxN] = {nullptr};  // factors of the sampled cores (local Gram)
   double* P0 = nullptr; double* P1 = nullptr; double* G = nullptr; double* Cinv = nullptr;
   // second stream (default priority) for the FGMC Gram and its inverse, which depend only
   // on the other cores and so run beside the gradient pass; fork / join events
@@ -822,6 +825,7 @@ int ensure_dense(trd_ctx* ctx) {
   }
   // K_j is r_j^2 x r_{j+1}^2; ring partial products are r_{k+1}^2 x r_m^2
   for (int j = 0; j < ctx->N; ++j) TRY(alloc_n(ctx, &ctx->K[j], maxR2));
+  for (int j = 0; j < ctx->N; ++j) TRY(alloc_n(ctx, &ctx->Kl[j], maxR2));
   TRY(alloc_n(ctx, &ctx->P0, maxr2 * maxr2));
   TRY(alloc_n(ctx, &ctx->P1, maxr2 * maxr2));
   TRY(alloc_n(ctx, &ctx->G, maxR2));
@@ -835,11 +839,13 @@ int refresh_K(trd_ctx* ctx, const void* const* cores, int j, hipStream_t st) {
   return TRD_OK;
 }
 
-// G^{!=k} from the cached factors (eq. 13): ring product in cyclic order, realigned
-int ring_gram(trd_ctx* ctx, int k, double* G_out, hipStream_t st) {
+// G^{!=k} from the cached factors (eq. 13): ring product in cyclic order, realigned.
+// Ks: other factors (those of sampled cores), nullptr: the cached ones of the full cores
+int ring_gram(trd_ctx* ctx, int k, double* G_out, hipStream_t st, double* const* Ks = nullptr) {
   const int N = ctx->N;
   const int s1 = (k + 1) % N;
-  const double* cur = ctx->K[s1];
+  double* const* KK = Ks ? Ks : ctx->K;
+  const double* cur = KK[s1];
   int rows = ctx->ranks[s1] * ctx->ranks[s1];
   int inner = ctx->ranks[(s1 + 1) % N] * ctx->ranks[(s1 + 1) % N];
   double* bufs[2] = {ctx->P0, ctx->P1};
@@ -856,7 +862,7 @@ int ring_gram(trd_ctx* ctx, int k, double* G_out, hipStream_t st) {
     ra.nf = N - 1;
     for (int t = 1; t <= N - 1; ++t) {
       const int m = (k + t) % N;
-      ra.K[t - 1] = ctx->K[m];
+      ra.K[t - 1] = KK[m];
       ra.rows[t - 1] = ctx->ranks[m] * ctx->ranks[m];
       ra.cols[t - 1] = ctx->ranks[(m + 1) % N] * ctx->ranks[(m + 1) % N];
       fits = fits && ra.rows[t - 1] <= 64 && ra.cols[t - 1] <= 64;
@@ -873,9 +879,9 @@ int ring_gram(trd_ctx* ctx, int k, double* G_out, hipStream_t st) {
     const int m = (k + t) % N;
     const int cols = ctx->ranks[(m + 1) % N] * ctx->ranks[(m + 1) % N];
     if (t == N - 1) {  // last factor: write G realigned
-      CK(launch_gemm64(cur, ctx->K[m], G_out, rows, inner, cols, st, ctx->ranks[k], ctx->ranks[s1]));
+      CK(launch_gemm64(cur, KK[m], G_out, rows, inner, cols, st, ctx->ranks[k], ctx->ranks[s1]));
     } else {
-      CK(launch_gemm64(cur, ctx->K[m], bufs[which], rows, inner, cols, st));
+      CK(launch_gemm64(cur, KK[m], bufs[which], rows, inner, cols, st));
       cur = bufs[which];
       which ^= 1;
     }
@@ -906,22 +912,34 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
   const int64_t Ik = ctx->dims[k];
   const int R = sp.r_k * sp.r_k1;
   CK(launch_zero(ctx->flags, sizeof(uint32_t), st));
-  // G (eq. 13) and (G + lambda I)^{-1} need only the factors of the other cores: on the
-  // side stream, after everything queued so far, while the gradient runs here
-  TRY(ensure_side(ctx));
-  CK(hipEventRecord(ctx->ev_fork, st));
-  CK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-  TRY(ring_gram(ctx, k, ctx->G, ctx->side));
-  CK(launch_inverse(ctx->G, ctx->Cinv, R, lambda_rel, ctx->flags, ctx->side));
-  CK(hipEventRecord(ctx->ev_join, ctx->side));
+  // the unscaled direction (h = d) needs no Gram; the local Gram (sampled cores) differs
+  // from the global one only under a sketch
+  const bool scaled = ctx->direction == TRD_DIR_SCALED;
+  const bool local = scaled && ctx->gram == TRD_GRAM_LOCAL && sk;
+  if (scaled) {
+    // G (eq. 13) and (G + lambda I)^{-1} need only the factors of the other cores: on the
+    // side stream, after everything queued so far, while the gradient runs here
+    TRY(ensure_side(ctx));
+    CK(hipEventRecord(ctx->ev_fork, st));
+    CK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    if (local) {  // factors of the sampled slices I_j of every other core (Sec. 6.1)
+      for (int j = 0; j < ctx->N; ++j)
+        if (j != k)
+          CK(launch_kron_factor(ctx->dtype, cores[j], ctx->ranks[j], up.cnt[j],
+                                ctx->ranks[(j + 1) % ctx->N], ctx->Kl[j], ctx->side, up.lst[j]));
+    }
+    TRY(ring_gram(ctx, k, ctx->G, ctx->side, local ? ctx->Kl : nullptr));
+    CK(launch_inverse(ctx->G, ctx->Cinv, R, lambda_rel, ctx->flags, ctx->side));
+    CK(hipEventRecord(ctx->ev_join, ctx->side));
+  }
   ItemRef Uref;
   int64_t nB;
   TRY(do_grad(ctx, up, (const void* const*)cores, nullptr, 1.0, nullptr, st, &Uref, &nB));
-  CK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+  if (scaled) CK(hipStreamWaitEvent(st, ctx->ev_join, 0));
   const int64_t nbl = (Ik * R + 255) / 256;
   TRY(ensure_part(ctx, 0, nbl));
-  CK(launch_apply_inverse(ctx->d64, ctx->Cinv, Ik, R, ctx->h64, ctx->h_real, ctx->dtype,
-                          ctx->part_misc, ctx->flags, st));
+  CK(launch_apply_inverse(ctx->d64, scaled ? ctx->Cinv : nullptr, Ik, R, ctx->h64, ctx->h_real,
+                          ctx->dtype, ctx->part_misc, ctx->flags, st));
   TRY(build_rowtable(ctx, up, ctx->h_real, Uref, nB, ctx->TH, st));
   TRY(run_pass(ctx, up, kModeLS, st));
   CK(launch_finish_step(ctx->dtype, ctx->part_misc, nbl, ctx->part_pass, up_nwg(up),
@@ -1417,6 +1435,16 @@ int trd_set_precision(trd_ctx* ctx, int precision) {
     if (ctx->dtype != TRD_F32) return fail(ctx, TRD_EUNSUPPORTED, "the BF16 form needs an FP32 problem");
   }
   ctx->prec = precision;
+  return TRD_OK;
+}
+
+int trd_set_variant(trd_ctx* ctx, int direction, int gram) {
+  if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
+  if (direction != TRD_DIR_SCALED && direction != TRD_DIR_GRADIENT)
+    return fail(ctx, TRD_EINVAL, "unknown direction");
+  if (gram != TRD_GRAM_GLOBAL && gram != TRD_GRAM_LOCAL) return fail(ctx, TRD_EINVAL, "unknown gram");
+  ctx->direction = direction;
+  ctx->gram = gram;
   return TRD_OK;
 }
 

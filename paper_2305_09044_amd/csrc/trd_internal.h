@@ -171,8 +171,9 @@ int pass_rrp(int RR);
 int64_t pass_ct_w(int dtype, int prec, int RRP);
 
 // dense FP64 pieces
+// K = sum over slices i of Z(i) (x) Z(i); idx: the I slices to sum (nullptr: all I)
 hipError_t launch_kron_factor(int dtype, const void* Z, int r0, int64_t I, int r1, double* K,
-                              hipStream_t st);
+                              hipStream_t st, const int32_t* idx = nullptr);
 hipError_t launch_gemm64(const double* A, const double* B, double* C, int m, int kk, int n,
                          hipStream_t st, int r_k = 0, int r_k1 = 0);
 hipError_t launch_finish_step(int dtype, const double* pnum, int64_t n_num, const double* pden,
@@ -191,6 +192,7 @@ struct RingArgs {
 hipError_t launch_ring(const RingArgs& a, hipStream_t st);
 hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
                           uint32_t* flags, hipStream_t st);
+// Cinv == nullptr: h = d
 hipError_t launch_apply_inverse(const double* d64, const double* Cinv, int64_t Ik, int n,
                                 double* h64, void* h_real, int dtype, double* part_num,
                                 const uint32_t* flags, hipStream_t st);

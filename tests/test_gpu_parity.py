@@ -146,6 +146,78 @@ def test_step_sketch(explicit):
         assert float(eta) == pytest.approx(info.eta, rel=1e-4)
 
 
+ORACLE_GRAM = {"global": "fgmc", "local": "local"}
+
+
+@pytest.mark.parametrize("direction,gram", [("gradient", "global"), ("scaled", "local"),
+                                            ("gradient", "local")])
+def test_step_sketch_ablation_variants(direction, gram):
+    # Sec. 6.1 ablations: h = d, or the Gram matrix of the sampled cores
+    dims, ranks = (60, 50, 40, 30), (3, 4, 3, 2)
+    X, P, Z0, prob = _setup(dims, ranks, rho=0.5)
+    sizes = (12, 9, 17, 8)
+    sigma, seed, t = 0.9, 42, 3
+    prob.set_variant(direction, gram)
+    for k in range(4):
+        idx = orng.sketch_indices(seed, t, k, dims, sizes)
+        sk, keep = trd.make_sketch(sizes, seed, t)
+        cores = device_cores(Z0, F32)
+        eta, flags = prob.step(cores, k, sigma, 1e-9, sketch=sk)
+        ref, info = aw.core_update(X, P, Z0, k, sigma, 1e-9, sketch=idx, gram=ORACLE_GRAM[gram],
+                                   direction=direction)
+        got = host_cores(cores, dims, ranks)
+        assert int(flags) == 0
+        assert rel(got[k], ref) <= 1e-5, (k, rel(got[k], ref))
+        assert float(eta) == pytest.approx(info.eta, rel=1e-4)
+
+
+@pytest.mark.parametrize("dims,ranks", SHAPES)
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_step_full_gradient_direction(dims, ranks, dtype):
+    X, P, Z0, prob = _setup(dims, ranks, dtype=dtype)
+    prob.set_variant("gradient", "global")
+    for k in range(len(dims)):
+        cores = device_cores(Z0, dtype)
+        eta, flags = prob.step(cores, k, 1.1, 1e-9)
+        ref, info = aw.core_update(X, P, Z0, k, 1.1, 1e-9, direction="gradient")
+        got = host_cores(cores, dims, ranks)
+        assert int(flags) == 0
+        assert rel(got[k], ref) <= TOL[dtype], (k, rel(got[k], ref))
+        assert float(eta) == pytest.approx(info.eta, rel=1e-4 if dtype == F32 else 1e-9)
+
+
+def test_local_gram_without_sketch_is_the_method():
+    dims, ranks = (37, 41, 29, 23), (2, 3, 4, 2)
+    X, P, Z0, prob = _setup(dims, ranks)
+    for k in range(4):
+        a, b = device_cores(Z0, F32), device_cores(Z0, F32)
+        prob.set_variant("scaled", "global")
+        prob.step(a, k, 0.9)
+        prob.set_variant("scaled", "local")
+        prob.step(b, k, 0.9)
+        assert torch.equal(a[k], b[k])
+    lib = trd._lib.load()
+    assert lib.trd_set_variant(prob._ctx, 2, 0) == -1   # TRD_EINVAL
+    assert lib.trd_set_variant(prob._ctx, 0, 2) == -1
+
+
+@pytest.mark.parametrize("direction,gram", [("gradient", "global"), ("scaled", "local")])
+def test_fit_rsts_ablation_variants(direction, gram):
+    dims, ranks = (40, 36, 30, 24), (3, 3, 2, 2)
+    X, P, Z0, prob = _setup(dims, ranks, rho=0.5)
+    sizes, seed, sig = (10, 8, 9, 7), 7, [2.0, 1.2, 0.9]
+    prob.set_variant(direction, gram)
+    cores = device_cores(Z0, F32)
+    prob.fit(cores, max_sweeps=len(sig), tol=0.0, sigma_mode="given", sigma_given=sig,
+             sketch_sizes=sizes, seed=seed)
+    ref, _ = aw.fit(X, P, Z0, aw.FitOptions(max_sweeps=len(sig), tol=0.0, sigma_mode="given",
+                                            sigma_given=sig, sketch_sizes=sizes, seed=seed,
+                                            gram=ORACLE_GRAM[gram], direction=direction))
+    got = host_cores(cores, dims, ranks)
+    err = max(rel(g, r) for g, r in zip(got, ref))
+    assert err <= 1e-4, err
+
+
 def test_sketch_with_full_sizes_equals_full_step():
     dims, ranks = (20, 15, 12), (2, 3, 2)
     X, P, Z0, prob = _setup(dims, ranks, rho=0.5)
