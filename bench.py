@@ -146,6 +146,38 @@ def equal_accuracy(prob, Z0_flat, xstar_d, sweeps, checkpoints, band=0.03, n_sam
     return out
 
 
+ABLATION_VARIANTS = (("method", "scaled", "global"), ("gradient descent", "gradient", "global"),
+                     ("local scaled term", "scaled", "local"))
+
+
+def ablation(prob, Z0_flat, xstar_d, dims, sizes, sweeps, seed=0, n_sample=1 << 20):
+    """The ablations of Sec. 6.1 on the RStS path: the method, the plain gradient direction
+    and the local scaled term, each fitted for `sweeps` sweeps from the same start with the
+    same sketches, for several per-mode sample sizes s (J = s^(N-1) sampled columns per
+    update); recovery error over a fixed uniform sample of entries, and the fit's time."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    n = xstar_d.numel()
+    idx = torch.randint(0, n, (min(n_sample, n),), generator=g, dtype=torch.int64).cuda()
+    rows = []
+    for s in sizes:
+        sk = [min(s, d) for d in dims]
+        for name, direction, gram in ABLATION_VARIANTS:
+            prob.set_variant(direction, gram)
+            prob.fit([z.clone() for z in Z0_flat], max_sweeps=1, tol=0.0, sketch_sizes=sk, seed=seed)
+            cores = [z.clone() for z in Z0_flat]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prob.fit(cores, max_sweeps=sweeps, tol=0.0, sketch_sizes=sk, seed=seed)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rows.append({"variant": name, "s": s, "J": math.prod(sk[1:]), "ms": round(dt * 1e3, 3),
+                         "rel_error": recovery_error(prob, cores, xstar_d, idx)})
+            log(f"ablation {name} s={s}: {dt * 1e3:.1f} ms, rel. error {rows[-1]['rel_error']:.4g}")
+    prob.set_variant("scaled", "global")
+    return {"sweeps": sweeps, "rows": rows}
+
+
 def cpu_baseline(wname: str, seed: int, sample_dims):
     """FP64 oracle, one sweep (quantile kernel width), on a bounded sample of the recipe."""
     import numpy as np
@@ -187,6 +219,10 @@ def main():
     ap.add_argument("--no-equal-accuracy", action="store_true",
                     help="skip the FP32-vs-BF16 time-to-equal-recovery-error comparison")
     ap.add_argument("--accuracy-sweeps", type=int, default=30)
+    ap.add_argument("--ablation", default=None,
+                    help="comma-separated per-mode sample sizes: also run the Sec. 6.1 ablations "
+                         "(method, gradient descent, local scaled term) on the RStS path")
+    ap.add_argument("--ablation-sweeps", type=int, default=20)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "bf16x3"],
                     help="bf16: matrix-core passes with bf16 subchain tables (FP32 residuals); "
                          "bf16x3: the same with the reconstruction from split bf16 tables")
@@ -226,6 +262,9 @@ def main():
         f"workspace={info['workspace_bytes'] / 2**20:.0f} MiB")
 
     prec = {"fp32": "native", "bf16": "bf16", "bf16x3": "bf16x3"}[args.precision]
+    if sk is not None and prec != "native":  # RStS sketches run the native passes
+        log("RStS path: native (fp32) passes")
+        prec, args.precision = "native", "fp32"
     if args.warmup > 0:
         prob.fit(cores, max_sweeps=args.warmup, tol=0.0, sketch_sizes=sk, precision=prec)
     torch.cuda.synchronize()
@@ -279,8 +318,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w.dtype == "f64" else ("f32" if prec == "native" else "bf16"),
            "data": "synthetic",
            "config": {"workload": args.workload, "dims": list(dims), "tr_ranks": list(w.ranks),
-                      "observed_fraction": w.rho, "n_obs": n_obs, "path": "AWRTRD full sweep, FGMC, "
-                      "quantile kernel width", "precision": args.precision},
+                      "observed_fraction": w.rho, "n_obs": n_obs, "path": ("SAWRTRD sweep (RStS sketches), FGMC, " if sk else "AWRTRD full sweep, FGMC, ") +
+                      "quantile kernel width", "sketch_sizes": sk, "precision": args.precision},
            "roofline": roof}
     if not args.no_equal_accuracy and sk is None and w.dtype != "f64":
         C = args.accuracy_sweeps
@@ -289,6 +328,11 @@ def main():
         out["equal_accuracy"] = equal_accuracy(prob, Z0_flat, xstar_d, C, cps)
         log("equal accuracy:", json.dumps({k: v for k, v in out["equal_accuracy"].items()
                                            if k not in ("trace", "levels")}))
+    if args.ablation:
+        sizes = [int(v) for v in args.ablation.split(",")]
+        Z0_flat = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(Z0, npdt)]
+        out["ablation"] = ablation(prob, Z0_flat, xstar_d, dims, sizes, args.ablation_sweeps,
+                                   args.seed)
     if not args.no_cpu_baseline:
         if args.cpu_sample:
             sample = tuple(int(v) for v in args.cpu_sample.split(","))
