@@ -218,6 +218,25 @@ def test_fit_rsts_ablation_variants(direction, gram):
     assert err <= 1e-4, err
 
 
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_full_observation_ls_step_is_tr_als(dtype):
+    # TR-ALS as a special case of the step: P = 1, sigma = inf, lambda = 0 give eta = 1 and
+    # the least-squares solution of each core given the others (textbook lstsq)
+    dims, ranks = (21, 17, 13, 9), (2, 3, 2, 3)
+    X, _, Z0, _ = _setup(dims, ranks, dtype=dtype)
+    P = np.ones(dims, dtype=np.uint8)
+    prob = device_problem(X, P, dims, ranks, dtype)
+    for k in range(4):
+        cores = device_cores(Z0, dtype)
+        eta, flags = prob.step(cores, k, math.inf, 0.0)
+        got = host_cores(cores, dims, ranks)
+        A = tr.subchain_unfolding(Z0, k)
+        sol = np.linalg.lstsq(A, tr.unfold_cyclic(X, k).T, rcond=None)[0].T
+        assert int(flags) == 0
+        assert float(eta) == pytest.approx(1.0, abs=1e-5 if dtype == F32 else 1e-10)
+        assert rel(tr.unfold_core(got[k]), sol) <= (1e-5 if dtype == F32 else 1e-9), k
+
+
 def test_sketch_with_full_sizes_equals_full_step():
     dims, ranks = (20, 15, 12), (2, 3, 2)
     X, P, Z0, prob = _setup(dims, ranks, rho=0.5)
