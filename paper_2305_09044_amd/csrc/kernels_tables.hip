@@ -145,7 +145,10 @@ __global__ void k_merge(const real* __restrict__ L, int64_t Ls, const int32_t* _
 // the sums run over b in order, as in the kernels above, so the results are the same.
 // R consecutive threads write one item row, so every store instruction of a wave writes
 // one contiguous run.  With STAGE the nL left items are first copied to LDS (row stride
-// R*R + 4 floats, so that the eight items a wave reads fall in different banks).
+// R*R + 4 floats, so that the eight items a wave reads fall in different banks), and a
+// work-group then forms kMergeReps consecutive groups of 256 / R items, so that one copy
+// serves them all.
+constexpr int kMergeReps = 4;
 template <bool BF, int R, bool STAGE>
 __global__ __launch_bounds__(256) void k_merge_item(
     const float* __restrict__ L, int64_t Ls, const int32_t* __restrict__ Llist, uint32_t nL,
@@ -163,7 +166,10 @@ __global__ __launch_bounds__(256) void k_merge_item(
     }
     __syncthreads();
   }
-  const uint64_t t = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  constexpr int reps = STAGE ? kMergeReps : 1;
+#pragma unroll
+  for (int rp = 0; rp < reps; ++rp) {
+  const uint64_t t = ((uint64_t)blockIdx.x * reps + rp) * 256u + threadIdx.x;
   const uint32_t item = (uint32_t)(t / R), c = (uint32_t)(t % R);
   if (item >= nItems) return;
   const uint32_t j = nLdiv.div(item), l = item - j * nL;
@@ -221,6 +227,7 @@ __global__ __launch_bounds__(256) void k_merge_item(
       *reinterpret_cast<float4*>(o + z + 4) = float4{0.f, 0.f, 0.f, 0.f};
     }
   }
+  }
 }
 
 template <typename real, bool BF>
@@ -239,7 +246,8 @@ static void merge_idx(dim3 g, dim3 b, hipStream_t st, bool small, const ItemRef&
       const size_t lds = (size_t)nL * (64 + 4) * sizeof(float);
       const unsigned ng = (unsigned)(((uint64_t)items * 8 + 255) / 256);
       if ((int64_t)lds <= 32768) {
-        hipLaunchKernelGGL((k_merge_item<BF, 8, true>), dim3(ng), b, lds, st,
+        hipLaunchKernelGGL((k_merge_item<BF, 8, true>), dim3((ng + kMergeReps - 1) / kMergeReps), b,
+                           lds, st,
                            (const float*)L.ptr, L.stride, L.list, (uint32_t)nL,
                            (const float*)R.ptr, R.stride, R.list, items, out, out_lo,
                            (int)out_stride, FastDiv((uint32_t)nL));
