@@ -38,8 +38,14 @@ def log(*a):
 
 
 def src_hash(precision: str = "fp32") -> str:
+    """Hash of the gradient pass's source and of the host code that plans its launches
+    (grid, column groups, tables): the stored traffic is valid only for these sources."""
     src = PASS_SRC if precision == "fp32" else PASS_SRC.replace("kernels_pass", "kernels_tile")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in (src, os.path.join(os.path.dirname(src), "trd_api.cpp"),
+              os.path.join(os.path.dirname(src), "trd_internal.h")):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def build_inputs(wname: str, seed: int, dims=None):

@@ -410,6 +410,11 @@ int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStr
   return TRD_OK;
 }
 
+// work-groups per compute unit the matrix-core passes aim for: each column group adds a
+// partial of the gradient row factors (written by the pass, read by the contraction), so
+// fewer, longer walks are preferred to the denser grid of the other passes
+constexpr int kTileWGPerCU = 6;
+
 // bitmask-tile layout of core k (same split as the ELL layout), built once on first use
 int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   TLayout& T = ctx->tlayouts[k];
@@ -427,7 +432,7 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   T.n_ct = (int)((T.n_chunks + T.n_chpt - 1) / T.n_chpt);
   T.n_rb = (T.nrows + 63) / 64;
   T.n_rg = (T.n_rb + 3) / 4;
-  column_groups(T.n_rg, T.n_ct, T.n_cg, T.cpg);
+  column_groups(T.n_rg, T.n_ct, T.n_cg, T.cpg, (int64_t)g_num_cu * kTileWGPerCU);
   if (T.cpg * T.n_chpt > 63) {  // a wave's walk keeps its block offsets in one register
     T.cpg = std::max(1, 63 / T.n_chpt);
     T.n_cg = (T.n_ct + T.cpg - 1) / T.cpg;

@@ -35,8 +35,9 @@ extern int g_num_cu;
 // work-groups a pass launch aims for: enough resident groups per CU to balance the tail
 inline int64_t wg_target() { return (int64_t)g_num_cu * 8; }
 // column groups for a row-group count and tile count: as few as give wg_target() groups
-inline void column_groups(int64_t n_rg, int n_ct, int& n_cg, int& cpg) {
-  int64_t want = (wg_target() + n_rg - 1) / (n_rg > 0 ? n_rg : 1);
+inline void column_groups(int64_t n_rg, int n_ct, int& n_cg, int& cpg,
+                          int64_t target = wg_target()) {
+  int64_t want = (target + n_rg - 1) / (n_rg > 0 ? n_rg : 1);
   if (want < 1) want = 1;
   if (want > n_ct) want = n_ct;
   cpg = (int)((n_ct + want - 1) / want);
