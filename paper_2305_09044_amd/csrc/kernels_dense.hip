@@ -777,6 +777,8 @@ __global__ __launch_bounds__(256) void k_qhist(const float* __restrict__ keys,
     const bool full = 4 * i4 + 3 < n;
     if (full) k4 = reinterpret_cast<const float4*>(keys)[i4];
     const float kv[4] = {k4.x, k4.y, k4.z, k4.w};
+    uint32_t keyv[4];
+    bool matchv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t i = 4 * i4 + u;
@@ -785,13 +787,28 @@ __global__ __launch_bounds__(256) void k_qhist(const float* __restrict__ keys,
       const uint32_t key = in ? (__float_as_uint(full ? kv[u] : keys[i]) & 0x7fffffffu) : 0u;
       const bool match = in && (hi_shift >= 32 || (key >> hi_shift) == prefix);
       if (match) atomicAdd(&lh[(key >> shift) & (nb - 1u)], 1u);
-      if (seg) {  // uniform over the wave: one LDS counter update per wave and key slot
-        const uint64_t bal = __ballot(match);
+      keyv[u] = key;
+      matchv[u] = match;
+    }
+    if (seg) {  // uniform over the wave: one LDS counter update per wave and round
+      uint64_t bal[4];
+      uint32_t tot = 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bal[u] = __ballot(matchv[u]);
+        tot += (uint32_t)__popcll(bal[u]);
+      }
+      if (tot) {  // uniform (from the ballots); every lane is active, lane 0 included
         const int lane = threadIdx.x & 63;
+        const uint64_t below = (1ull << lane) - 1ull;
         uint32_t off = 0u;
-        if (lane == 0 && bal) off = atomicAdd(&ncand, (uint32_t)__popcll(bal));
-        off = __shfl(off, 0);
-        if (match) seg[off + __popcll(bal & ((1ull << lane) - 1ull))] = __uint_as_float(key);
+        if (lane == 0) off = atomicAdd(&ncand, tot);
+        off = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (matchv[u]) seg[off + __popcll(bal[u] & below)] = __uint_as_float(keyv[u]);
+          off += (uint32_t)__popcll(bal[u]);
+        }
       }
     }
   }
