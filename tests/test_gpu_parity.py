@@ -316,6 +316,23 @@ def test_fit_quantile_sigma_first_sweep():
     assert rep["sigma"][0] == pytest.approx(s_ref, rel=1e-5)
 
 
+@pytest.mark.parametrize("precision,tol", [("native", 1e-5), ("bf16", 1e-2)])
+@pytest.mark.parametrize("q", [0.5, 0.9])
+def test_quantile_sigma_when_most_keys_share_the_top_digit(precision, tol, q):
+    # residuals all close to 1.125 (X = reconstruction of the start + 1.125): every key
+    # shares the first radix digit, so the candidate segments of the third digit fill up
+    dims, ranks = (64, 48, 40), (3, 4, 3)
+    _, P, Z0, _ = _setup(dims, ranks, rho=0.6)
+    X = (tr.reconstruct(Z0) + 1.125).astype(np.float32).astype(np.float64)
+    prob = device_problem(X, P, dims, ranks, F32)
+    cores = device_cores(Z0, F32)
+    rep = prob.fit(cores, max_sweeps=1, tol=0.0, q=q, precision=precision)
+    e = aw.residual_abs(X, P, Z0)
+    assert np.mean((e >= 1.0) & (e < 1.25)) > 0.9   # one first digit: 0x3f8 in bits 31..21
+    s_ref = aw.quantile_sigma(e, q, 5.0, 1e-6 * float(np.max(np.abs(X[P.astype(bool)]))))
+    assert rep["sigma"][0] == pytest.approx(s_ref, rel=tol)
+
+
 @pytest.mark.parametrize("sigma", [0.7, math.inf])
 def test_loss_fwd_bwd(sigma):
     dims, ranks = (23, 19, 21, 6), (2, 3, 2, 2)
