@@ -19,7 +19,7 @@ def test_header_declares_the_documented_calls():
     for n in ["trd_create", "trd_destroy", "trd_last_error", "trd_set_problem", "trd_reconstruct",
               "trd_weights", "trd_grad", "trd_fgmc_gram", "trd_step", "trd_fit", "trd_loss_fwd",
               "trd_loss_bwd", "trd_sample_sketch", "trd_problem_info", "trd_profile",
-              "trd_profile_read"]:
+              "trd_profile_read", "trd_set_precision", "trd_set_variant"]:
         assert n in names
 
 
@@ -79,7 +79,29 @@ def test_context_calls_reject_null_context():
     assert lib.trd_step(None, None, 0, 1.0, 0.0, None, None, None, None) == _lib.TRD_EINVAL
     assert lib.trd_fit(None, None, None, None, None) == _lib.TRD_EINVAL
     assert lib.trd_profile(None, 1) == _lib.TRD_EINVAL
+    assert lib.trd_set_precision(None, 0) == _lib.TRD_EINVAL
+    assert lib.trd_set_variant(None, 0, 0) == _lib.TRD_EINVAL
     lib.trd_destroy(None)  # ignored
+
+
+def test_header_constants_match_the_binding():
+    txt = open(HEADER).read()
+    consts = dict((m.group(1), int(m.group(2)))
+                  for m in re.finditer(r"#define\s+(TRD_\w+)\s+(-?\d+)", txt))
+    for name in ("TRD_OK", "TRD_EINVAL", "TRD_PREC_NATIVE", "TRD_PREC_BF16", "TRD_PREC_BF16X3",
+                 "TRD_SIGMA_FIXED", "TRD_SIGMA_GIVEN", "TRD_SIGMA_QUANTILE", "TRD_DIR_SCALED",
+                 "TRD_DIR_GRADIENT", "TRD_GRAM_GLOBAL", "TRD_GRAM_LOCAL"):
+        assert getattr(_lib, name) == consts[name], name
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    bench = os.path.join(os.path.dirname(HERE), "bench.py")
+    r = subprocess.run([sys.executable, bench, "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
 
 
 def test_product_package_does_not_import_the_oracle():
