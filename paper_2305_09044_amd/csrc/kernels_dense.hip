@@ -563,16 +563,24 @@ hipError_t launch_pack_report(const double* sigma, const double* conv, const uin
 
 // ---------------------------------------------------------------- convergence (Alg. 1)
 
+// M = Z G (I_N x n); G is staged in LDS when n <= 64 (the sums are the same either way)
 template <typename real>
-__global__ void k_zg(const real* __restrict__ Z, const double* __restrict__ G, int64_t IN, int n,
-                     double* __restrict__ M) {
+__global__ __launch_bounds__(256) void k_zg(const real* __restrict__ Z, const double* __restrict__ G,
+                                            int64_t IN, int n, double* __restrict__ M) {
+  __shared__ double Gs[64 * 64];
+  const bool staged = n <= 64;  // uniform over the grid
+  if (staged) {
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) Gs[t] = G[t];
+    __syncthreads();
+  }
+  const double* Gp = staged ? Gs : G;
   const int64_t total = IN * n;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = t / n;
     const int c = (int)(t % n);
     double s = 0.0;
-    for (int l = 0; l < n; ++l) s = fma((double)Z[i * n + l], G[(int64_t)l * n + c], s);
+    for (int l = 0; l < n; ++l) s = fma((double)Z[i * n + l], Gp[(int64_t)l * n + c], s);
     M[t] = s;
   }
 }
