@@ -111,3 +111,13 @@ def test_product_package_does_not_import_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 txt = open(os.path.join(root, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", txt).replace("oracle-free", ""), f
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no fallback: without libtrd.so every entry point raises instead of computing elsewhere
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libtrd.so"))
+    with pytest.raises(ImportError, match="missing"):
+        _lib.load()
+    with pytest.raises(ImportError):
+        _lib.trd_weights(__import__("torch").zeros(4), 1.0)
