@@ -447,3 +447,84 @@ def test_gradient_row_matches_unfolded_gradient(dims, ranks, k):
         sel = obs[obs[:, k] == i]
         row = aw.gradient_row(Z, k, sel, X[tuple(sel.T)], sigma, chunk=7)
         np.testing.assert_allclose(row, info.d[i], rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------- kernel-width schedule (own rule)
+#
+# The quantile rule is this project's reading of the adaptive kernel width the paper leaves to
+# an earlier work; nothing in the paper fixes its values.  These pins fix the rule as stated:
+# rank floor((n-1) q) of the sorted |e| over the observed entries of the sweep's first update,
+# scaled by c, floored at sigma_min and at shrink * sigma_{t-1}.  Residuals are made exact by
+# rank-1 cores of ones (every reconstructed entry is 1) and X = 1 + e with e(i, j, l) =
+# i + 3 j + 6 l on a 3 x 2 x 2 tensor, so the sorted residuals can be written down by hand.
+
+def _ones_problem():
+    dims, ranks = (3, 2, 2), (1, 1, 1)
+    Z = [np.ones((1, I, 1)) for I in dims]
+    i, j, l = np.meshgrid(np.arange(3), np.arange(2), np.arange(2), indexing="ij")
+    E = (i + 3 * j + 6 * l).astype(np.float64)          # residuals 0..11, each once
+    return dims, Z, 1.0 + E, E
+
+
+def test_sweep_sigma_by_hand_full_path():
+    dims, Z, X, E = _ones_problem()
+    P = np.ones(dims, dtype=np.uint8)
+    o = aw.FitOptions(q=0.5, c=2.0, shrink=0.5)
+    # 12 residuals 0..11: rank floor(11 * 0.5) = 5 -> |e| = 5, sigma = 2 * 5
+    assert aw.sweep_sigma(X, P, Z, o, 0, 0.0) == 10.0
+    # q = 0.9: rank floor(9.9) = 9 -> 9, sigma 18; q = 0 -> smallest residual 0 -> sigma_min
+    assert aw.sweep_sigma(X, P, Z, aw.FitOptions(q=0.9, c=2.0), 0, 0.0) == 18.0
+    assert aw.sweep_sigma(X, P, Z, aw.FitOptions(q=0.0, c=2.0), 0, 0.25) == 0.25
+    # floor sigma_min above the quantile
+    assert aw.sweep_sigma(X, P, Z, o, 0, 12.0) == 12.0
+    # shrink limit: active when shrink * sigma_prev exceeds c * Q (30 * 0.5 = 15 > 10) ...
+    assert aw.sweep_sigma(X, P, Z, o, 1, 0.0, sigma_prev=30.0) == 15.0
+    # ... inactive when it does not (16 * 0.5 = 8 < 10), and absent at the first sweep
+    assert aw.sweep_sigma(X, P, Z, o, 1, 0.0, sigma_prev=16.0) == 10.0
+    assert aw.sweep_sigma(X, P, Z, o, 0, 0.0, sigma_prev=math.inf) == 10.0
+    # shrink = 0 disables the limit
+    assert aw.sweep_sigma(X, P, Z, aw.FitOptions(q=0.5, c=2.0, shrink=0.0), 1, 0.0, 30.0) == 10.0
+
+
+def test_sweep_sigma_by_hand_masked_and_fixed_modes():
+    dims, Z, X, E = _ones_problem()
+    P = np.ones(dims, dtype=np.uint8)
+    P[:, 0, 0] = 0                                       # drops residuals 0, 1, 2
+    X = X.copy()
+    X[P == 0] = 1e6                                      # never read
+    # 9 residuals 3..11: rank floor(8 * 0.5) = 4 -> 7, sigma 2 * 7
+    assert aw.sweep_sigma(X, P, Z, aw.FitOptions(q=0.5, c=2.0), 0, 0.0) == 14.0
+    assert aw.sweep_sigma(X, P, Z, aw.FitOptions(sigma_mode="fixed", sigma=0.7), 3, 0.0, 9.0) == 0.7
+    o = aw.FitOptions(sigma_mode="given", sigma_given=(3.0, 2.5, 1.0))
+    assert [aw.sweep_sigma(X, P, Z, o, t, 0.0, 99.0) for t in range(3)] == [3.0, 2.5, 1.0]
+
+
+@pytest.mark.parametrize("t", [0, 1, 4])
+def test_sweep_sigma_by_hand_under_rsts(t):
+    # under a sketch the quantile runs over the observed entries of the sweep's first update
+    # (core 0: mode 0 whole, one sampled index in each of modes 1 and 2), so its residuals are
+    # i + 3 j + 6 l for i = 0, 1, 2 at the drawn (j, l): median 1 + 3 j + 6 l
+    dims, Z, X, E = _ones_problem()
+    P = np.ones(dims, dtype=np.uint8)
+    o = aw.FitOptions(q=0.5, c=2.0, sketch_sizes=(3, 1, 1), seed=17)
+    sk = orng.sketch_indices(17, t, 0, dims, (3, 1, 1))
+    assert sk[0] == [0, 1, 2] and len(sk[1]) == 1 and len(sk[2]) == 1
+    j, l = sk[1][0], sk[2][0]
+    assert aw.sweep_sigma(X, P, Z, o, t, 0.0) == 2.0 * (1 + 3 * j + 6 * l)
+
+
+def test_fit_records_the_schedule_it_used():
+    # the fit's sigma history follows the rule step by step: sweep 0 has no shrink limit;
+    # later sweeps never fall below half the previous width
+    import synth
+    w = synth.scaled(synth.WORKLOADS["tr3_30_r3"], (12, 11, 10))
+    Zt, xstar, mask, X = synth.make_workload(w, 2, tr.reconstruct)
+    Z0 = synth.perturbed_cores(Zt, 2, rel=0.2)
+    o = aw.FitOptions(max_sweeps=8, tol=0.0)
+    Z, hist = aw.fit(X, mask, Z0, o)
+    smin = 1e-6 * float(np.max(np.abs(X[mask.astype(bool)])))
+    assert hist["sigma"][0] == aw.quantile_sigma(aw.residual_abs(X, mask, Z0), 0.5, 5.0, smin)
+    for a, b in zip(hist["sigma"], hist["sigma"][1:]):
+        assert b >= 0.5 * a
+    # exact data with a shrinking residual: the limit is reached at least once
+    assert any(b == 0.5 * a for a, b in zip(hist["sigma"], hist["sigma"][1:]))
