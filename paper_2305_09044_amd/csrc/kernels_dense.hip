@@ -5,6 +5,7 @@
 #include "trd_internal.h"
 
 #include <cmath>
+#include <cstring>
 
 namespace trd {
 
@@ -181,6 +182,51 @@ hipError_t launch_ring(const RingArgs& a, hipStream_t st) {
   if (a.rows[0] != a.r_k1 * a.r_k1 || a.cols[a.nf - 1] != a.r_k * a.r_k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ring, dim3(1), dim3(256), 3 * 4096 * sizeof(double), st, a);
   return hipGetLastError();
+}
+
+// G^{!=k} from the factors K[j] of the other cores (eq. 13): the ring product
+// K_{k+1} ... K_N K_1 ... K_{k-1} in cyclic order, realigned.  Factor sides <= 64: the
+// whole ring in one work-group when its three 64 x 64 tiles fit lds_max bytes of LDS;
+// otherwise one FP64 product per factor through P0 / P1.
+hipError_t launch_ring_gram(int N, const int32_t* ranks, int k, const double* const* K, double* P0,
+                            double* P1, double* G, int64_t lds_max, hipStream_t st) {
+  const int s1 = (k + 1) % N;
+  const double* cur = K[s1];
+  const int rows = ranks[s1] * ranks[s1];
+  int inner = ranks[(s1 + 1) % N] * ranks[(s1 + 1) % N];
+  if (N == 2) return launch_realign(cur, G, ranks[k], ranks[s1], st);
+  RingArgs ra;
+  memset(&ra, 0, sizeof(ra));
+  bool fits = true;
+  ra.nf = N - 1;
+  for (int t = 1; t <= N - 1; ++t) {
+    const int m = (k + t) % N;
+    ra.K[t - 1] = K[m];
+    ra.rows[t - 1] = ranks[m] * ranks[m];
+    ra.cols[t - 1] = ranks[(m + 1) % N] * ranks[(m + 1) % N];
+    fits = fits && ra.rows[t - 1] <= 64 && ra.cols[t - 1] <= 64;
+  }
+  ra.r_k = ranks[k];
+  ra.r_k1 = ranks[s1];
+  ra.G = G;
+  if (fits && (int64_t)3 * 4096 * sizeof(double) <= lds_max) return launch_ring(ra, st);
+  double* bufs[2] = {P0, P1};
+  int which = 0;
+  for (int t = 2; t <= N - 1; ++t) {
+    const int m = (k + t) % N;
+    const int cols = ranks[(m + 1) % N] * ranks[(m + 1) % N];
+    hipError_t e;
+    if (t == N - 1) {  // last factor: G realigned
+      e = launch_gemm64(cur, K[m], G, rows, inner, cols, st, ranks[k], ranks[s1]);
+    } else {
+      e = launch_gemm64(cur, K[m], bufs[which], rows, inner, cols, st);
+      cur = bufs[which];
+      which ^= 1;
+    }
+    if (e != hipSuccess) return e;
+    inner = cols;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------- scaled direction

@@ -114,6 +114,12 @@ int fail(trd_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+int trd::fail_free(int code, const std::string& msg) { return fail(nullptr, code, msg); }
+
+namespace {
+
 #define CK(expr)                                                                          \
   do {                                                                                    \
     hipError_t _e = (expr);                                                               \
@@ -423,7 +429,7 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   const Layout& L = ctx->layouts[k];
   T.nrows = L.nrows;
   T.ncols = L.ncols;
-  T.K = tile_k(sp.RR);
+  T.K = tile_k(sp.RRP);  // covers the padded width the row-factor partials are stored with
   T.n_chunks = (T.ncols + 31) / 32;
   const int64_t cwmax = tile_cw(T.K);
   T.n_ct = (int)((T.n_chunks * 32 + cwmax - 1) / cwmax);
@@ -847,51 +853,7 @@ int refresh_K(trd_ctx* ctx, const void* const* cores, int j, hipStream_t st) {
 // G^{!=k} from the cached factors (eq. 13): ring product in cyclic order, realigned.
 // Ks: other factors (those of sampled cores), nullptr: the cached ones of the full cores
 int ring_gram(trd_ctx* ctx, int k, double* G_out, hipStream_t st, double* const* Ks = nullptr) {
-  const int N = ctx->N;
-  const int s1 = (k + 1) % N;
-  double* const* KK = Ks ? Ks : ctx->K;
-  const double* cur = KK[s1];
-  int rows = ctx->ranks[s1] * ctx->ranks[s1];
-  int inner = ctx->ranks[(s1 + 1) % N] * ctx->ranks[(s1 + 1) % N];
-  double* bufs[2] = {ctx->P0, ctx->P1};
-  int which = 0;
-  if (N == 2) {
-    CK(launch_realign(cur, G_out, ctx->ranks[k], ctx->ranks[s1], st));
-    return TRD_OK;
-  }
-  // small ranks: the whole ring in one work-group
-  {
-    RingArgs ra;
-    memset(&ra, 0, sizeof(ra));
-    bool fits = true;
-    ra.nf = N - 1;
-    for (int t = 1; t <= N - 1; ++t) {
-      const int m = (k + t) % N;
-      ra.K[t - 1] = KK[m];
-      ra.rows[t - 1] = ctx->ranks[m] * ctx->ranks[m];
-      ra.cols[t - 1] = ctx->ranks[(m + 1) % N] * ctx->ranks[(m + 1) % N];
-      fits = fits && ra.rows[t - 1] <= 64 && ra.cols[t - 1] <= 64;
-    }
-    ra.r_k = ctx->ranks[k];
-    ra.r_k1 = ctx->ranks[s1];
-    ra.G = G_out;
-    if (fits && (int64_t)3 * 4096 * sizeof(double) <= g_lds_max) {
-      CK(launch_ring(ra, st));
-      return TRD_OK;
-    }
-  }
-  for (int t = 2; t <= N - 1; ++t) {
-    const int m = (k + t) % N;
-    const int cols = ctx->ranks[(m + 1) % N] * ctx->ranks[(m + 1) % N];
-    if (t == N - 1) {  // last factor: write G realigned
-      CK(launch_gemm64(cur, KK[m], G_out, rows, inner, cols, st, ctx->ranks[k], ctx->ranks[s1]));
-    } else {
-      CK(launch_gemm64(cur, KK[m], bufs[which], rows, inner, cols, st));
-      cur = bufs[which];
-      which ^= 1;
-    }
-    inner = cols;
-  }
+  CK(launch_ring_gram(ctx->N, ctx->ranks, k, Ks ? Ks : ctx->K, ctx->P0, ctx->P1, G_out, g_lds_max, st));
   return TRD_OK;
 }
 
@@ -1045,6 +1007,9 @@ int trd_set_shape(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ranks
   free_all(ctx);
   const int device = ctx->device;
   for (hipEvent_t ev : ctx->ev_pairs) hipEventDestroy(ev);
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
+  if (ctx->side) hipStreamDestroy(ctx->side);
   *ctx = trd_ctx();
   ctx->device = device;
   ctx->N = N;
@@ -1276,9 +1241,11 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
     rep->last_sigma = 0;
     rep->flags = 0;
   }
-  struct PrecGuard {
+  // on every exit: the caller's precision comes back, and no stored residuals outlive the
+  // fit (a later step or backward on core 0 must form its own)
+  struct FitGuard {
     trd_ctx* c; int saved;
-    ~PrecGuard() { c->prec = saved; }
+    ~FitGuard() { c->prec = saved; c->resid_core = -1; }
   } guard{ctx, ctx->prec};
   ctx->prec = o->precision;
   int cur = 0;
@@ -1337,10 +1304,14 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
       TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st));
       TRY(refresh_K(ctx, (const void* const*)cores, k, st));
     }
-    // convergence matrix with G^{!=N} of the last update (it does not involve core N)
+    // convergence matrix with G^{!=N} of the full cores (it does not involve core N): the
+    // last update left it in G unless that update formed no Gram (gradient direction) or the
+    // Gram of the sampled cores (local ablation); then it is formed here from the factors
     {
       const int64_t IN = ctx->dims[N - 1];
       const int R = ctx->ranks[N - 1] * ctx->ranks[0];
+      if (ctx->direction != TRD_DIR_SCALED || (ctx->gram == TRD_GRAM_LOCAL && sk))
+        TRY(ring_gram(ctx, N - 1, ctx->G, st));
       CK(launch_convergence(ctx->dtype, cores[N - 1], ctx->G, IN, R, ctx->M, ctx->Dbuf[cur],
                             ctx->Dbuf[cur ^ 1], t > 0 ? 1 : 0, ctx->part_misc, st));
       CK(launch_reduce_partials(ctx->part_misc, (IN * IN + 255) / 256, 2, ctx->scal + kConv, st));

@@ -191,6 +191,12 @@ struct RingArgs {
   double* G;
 };
 hipError_t launch_ring(const RingArgs& a, hipStream_t st);
+// G^{!=k} (eq. 13) from the factors K[j], j != k (r_j^2 x r_{j+1}^2 FP64, row-major); P0 and P1
+// hold r_{k+1}^2 * max_m r_m^2 doubles each (read only when a factor side exceeds 64)
+hipError_t launch_ring_gram(int N, const int32_t* ranks, int k, const double* const* K, double* P0,
+                            double* P1, double* G, int64_t lds_max, hipStream_t st);
+// message of the last failure of a context-free call (trd_last_error(NULL)); returns code
+int fail_free(int code, const std::string& msg);
 hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
                           uint32_t* flags, hipStream_t st);
 // Cinv == nullptr: h = d

@@ -208,14 +208,25 @@ def test_fit_rsts_ablation_variants(direction, gram):
     sizes, seed, sig = (10, 8, 9, 7), 7, [2.0, 1.2, 0.9]
     prob.set_variant(direction, gram)
     cores = device_cores(Z0, F32)
-    prob.fit(cores, max_sweeps=len(sig), tol=0.0, sigma_mode="given", sigma_given=sig,
-             sketch_sizes=sizes, seed=seed)
-    ref, _ = aw.fit(X, P, Z0, aw.FitOptions(max_sweeps=len(sig), tol=0.0, sigma_mode="given",
-                                            sigma_given=sig, sketch_sizes=sizes, seed=seed,
-                                            gram=ORACLE_GRAM[gram], direction=direction))
+    rep = prob.fit(cores, max_sweeps=len(sig), tol=0.0, sigma_mode="given", sigma_given=sig,
+                   sketch_sizes=sizes, seed=seed)
+    ref, hist = aw.fit(X, P, Z0, aw.FitOptions(max_sweeps=len(sig), tol=0.0, sigma_mode="given",
+                                               sigma_given=sig, sketch_sizes=sizes, seed=seed,
+                                               gram=ORACLE_GRAM[gram], direction=direction))
     got = host_cores(cores, dims, ranks)
     err = max(rel(g, r) for g, r in zip(got, ref))
     assert err <= 1e-4, err
+    # the stop test uses D^t with the Gram of the full cores whatever the variant
+    for a, b in zip(rep["e"][1:], hist["e"][1:]):
+        assert a == pytest.approx(b, rel=1e-3)
+    # and stops where the oracle stops: a tolerance just above the change after sweep 2
+    tol = 1.01 * max(hist["e"][1:])
+    rep = prob.fit(device_cores(Z0, F32), max_sweeps=len(sig), tol=tol, sigma_mode="given",
+                   sigma_given=sig, sketch_sizes=sizes, seed=seed)
+    _, hist = aw.fit(X, P, Z0, aw.FitOptions(max_sweeps=len(sig), tol=tol, sigma_mode="given",
+                                             sigma_given=sig, sketch_sizes=sizes, seed=seed,
+                                             gram=ORACLE_GRAM[gram], direction=direction))
+    assert rep["sweeps"] == len(hist["e"]) == 2
 
 
 @pytest.mark.parametrize("dtype", [F32, F64])
