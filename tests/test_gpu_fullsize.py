@@ -89,7 +89,7 @@ def test_precision_workload_gradient_rows(cfg_prec, prec, bar):
     f = cfg_prec
     sigma = 1.0
     worst = 0.0
-    for k, rows in ((0, (0, 37)), (2, (59,))):
+    for k, rows in ((0, (0, 37)), (1, (59,)), (2, (59,)), (3, (11,)), (4, (30,))):
         pairs, stats = _grad_rows(f, k, rows, sigma, prec)
         for got, ref in pairs:
             e = rel(got, ref)
@@ -109,6 +109,31 @@ def test_precision_workload_reconstruction_and_gram(cfg_prec):
     for k in (0, 3):
         G = f.prob.fgmc_gram(f.cores, k).cpu().numpy()
         assert rel(G, aw.gram_fgmc(f.Z, k)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,bar", [("native", 1e-3), ("bf16x3", 2e-2), ("bf16", 2e-2)])
+def test_precision_workload_step_rows_follow_the_scaled_direction(cfg_prec, prec, bar):
+    # one full-size step on core 1: the change of a sampled row is eta times that row of the
+    # oracle's scaled direction h = d (G + lambda I)^{-1} (eq. 10), with d the oracle's
+    # gradient row and G its FGMC Gram; the common factor is the step's eta (eq. 11)
+    f = cfg_prec
+    sigma, k, lam_rel = 1.0, 1, 1e-9
+    G = aw.gram_fgmc(f.Z, k)
+    C = G + lam_rel * np.trace(G) / G.shape[0] * np.eye(G.shape[0])
+    cores = [c.clone() for c in f.cores]
+    f.prob.set_precision(prec)
+    eta, flags = f.prob.step(cores, k, sigma, lam_rel)
+    f.prob.set_precision("native")
+    assert int(flags) == 0
+    r, r2 = f.w.ranks[k], f.w.ranks[(k + 1) % len(f.dims)]
+    new = cores[k].cpu().numpy().astype(np.float64).reshape(f.dims[k], r2 * r)
+    old = f.cores[k].cpu().numpy().astype(np.float64).reshape(f.dims[k], r2 * r)
+    for i in (59,):
+        h = np.linalg.solve(C, f.oracle_row(k, i, sigma))   # C symmetric: d C^{-1} row-wise
+        delta = new[i] - old[i]
+        est = float(delta @ h / (h @ h))
+        assert rel(delta, est * h) <= bar, (prec, i, rel(delta, est * h))
+        assert est == pytest.approx(float(eta), rel=bar), (prec, est, float(eta))
 
 
 def test_precision_workload_step_decreases_loss(cfg_prec):
