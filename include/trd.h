@@ -176,6 +176,21 @@ int trd_grad(trd_ctx* ctx, const void* const* cores, int k, double sigma, const 
 int trd_fgmc_gram(trd_ctx* ctx, const void* const* cores, int k, double* G_out, void* stream);
 
 /*
+ * trd_fgmc_gram without a context and without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same result as trd_fgmc_gram for the same cores (the same kernels, in
+ * the same order), on the current HIP device and `stream`.  dims, ranks: host arrays of N;
+ * cores: host array of N device pointers (cores[k] is not read); G_out as for
+ * trd_fgmc_gram.  Its factors and ring partials live in a fixed 2 MiB device array held by
+ * each device the call runs on until the process ends: shapes that need more (the N - 1
+ * factors r_j^2 r_{j+1}^2 doubles, plus 2 r_{k+1}^2 max_j r_j^2 when a factor side exceeds
+ * 64; ranks <= 12 always fit) return TRD_EUNSUPPORTED.  Calls on one device share that
+ * array: calls that overlap on a device race, so serialise them.  Errors: trd_last_error(NULL).
+ */
+int trd_fgmc_gram_noalloc(int N, const int64_t* dims, const int32_t* ranks, int dtype,
+                          const void* const* cores, int k, double* G_out, void* stream);
+
+/*
  * One core update (Alg. 1 body, eqs. 9-12 or 15-18): gradient, FGMC Gram of the
  * full cores, h = d (G + lambda I)^{-1} with lambda = lambda_rel * tr(G)/R^2,
  * exact line search eta = <d, h> / ||sqrt(W) o P o (h A^T)||^2, and the update

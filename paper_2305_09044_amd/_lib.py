@@ -91,6 +91,7 @@ def load() -> C.CDLL:
         "trd_loss_fwd": (i32, [vp, P(vp), dbl, vp, vp]),
         "trd_loss_bwd": (i32, [vp, P(vp), dbl, dbl, P(vp), vp]),
         "trd_sample_sketch": (i32, [C.c_uint64, i32, i32, i32, P(i64), P(C.c_int32), P(vp), vp]),
+        "trd_fgmc_gram_noalloc": (i32, [i32, P(i64), P(C.c_int32), i32, P(vp), i32, vp, vp]),
         "trd_set_precision": (i32, [vp, i32]),
         "trd_set_variant": (i32, [vp, i32, i32]),
         "trd_profile": (i32, [vp, i32]),
@@ -163,6 +164,22 @@ def trd_weights(resid: torch.Tensor, sigma: float, out: Optional[torch.Tensor] =
     out = torch.empty_like(resid) if out is None else out
     _check(lib.trd_weights(_ptr(resid), resid.numel(), _dtype_code(resid.dtype), float(sigma),
                            _ptr(out), C.c_void_p(_stream())))
+    return out
+
+
+def trd_fgmc_gram_noalloc(cores: Sequence[torch.Tensor], dims: Sequence[int], ranks: Sequence[int],
+                          k: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """G^{!=k} of eq. 13 by the context-free entry point that allocates no device memory
+    (its factors live in the library's fixed per-device scratch array)."""
+    lib = load()
+    N = len(dims)
+    R = int(ranks[k]) * int(ranks[(k + 1) % N])
+    dev = cores[(k + 1) % N].device
+    out = torch.empty((R, R), dtype=torch.float64, device=dev) if out is None else out
+    d = (C.c_int64 * N)(*[int(v) for v in dims])
+    r = (C.c_int32 * N)(*[int(v) for v in ranks])
+    _check(lib.trd_fgmc_gram_noalloc(N, d, r, _dtype_code(cores[(k + 1) % N].dtype),
+                                     _ptr_array(cores), int(k), _ptr(out), C.c_void_p(_stream())))
     return out
 
 

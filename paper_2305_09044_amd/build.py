@@ -30,7 +30,7 @@ FLAGS = [
 ]
 
 SOURCES = ["kernels_layout.hip", "kernels_tables.hip", "kernels_pass.hip", "kernels_dense.hip",
-           "kernels_tile.hip", "trd_api.cpp"]
+           "kernels_tile.hip", "trd_api.cpp", "trd_noalloc.hip"]
 
 
 def _compile(src: str) -> str:
