@@ -240,6 +240,26 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
                       int32_t* const* idx_out, void* stream);
 
 /*
+ * Seeded synthetic observation pattern on the device, bit-exact for a given seed:
+ * mask_out[l] = 1 for an observed entry (column-major l), drawn with probability rho per
+ * entry (block == 0) or per tile (block > 0: block x block tiles of modes 0 and 1, one draw
+ * per tile and per index of modes 3.., shared by every index of mode 2: the missing-block
+ * pattern of a video with mode 2 as the colour channel); outlier_out[l] (optional) = 1 for
+ * an observed entry chosen with probability outlier_frac; u_out[l] (optional) = a uniform
+ * double in [0, 1) per entry (53 bits), for an outlier's value or sign.  These are the
+ * observation model of eq. (2) with gross outliers (Sec. 3-4); the paper does not fix a law.
+ * Generator: the SplitMix64 counter form of trd_sample_sketch with keys
+ * u(seed ^ 0x4D41534B00000000, 0 / 1 / 2) for mask / selection / uniform; an event of
+ * probability p happens when the draw u(key, c) < floor(p * 2^64) (p >= 1: always, p <= 0:
+ * never), with c = l, or the tile index i0/block + nbh*(i1/block + nbw*f) for the mask
+ * (nbh, nbw tiles along modes 0 and 1, f the linear index of modes 3..); u = (draw >> 11) * 2^-53.
+ * Device buffers of prod(dims) elements.  Needs no context.
+ */
+int trd_sample_mask(uint64_t seed, int N, const int64_t* dims, double rho, int block,
+                    double outlier_frac, uint8_t* mask_out, uint8_t* outlier_out, double* u_out,
+                    void* stream);
+
+/*
  * Precision of the entry-wise passes of later trd_grad / trd_step / trd_loss_* calls
  * (trd_fit uses its own opts.precision).  TRD_PREC_BF16 (FP32 problems only): the
  * subchain tables are rounded to bf16 and the reconstruction and gradient contractions

@@ -16,7 +16,10 @@ Everything is integer-only, so any two faithful implementations agree bit for bi
 """
 from __future__ import annotations
 
+import math
 from typing import List, Sequence
+
+import numpy as np
 
 M64 = (1 << 64) - 1
 GOLDEN = 0x9E3779B97F4A7C15
@@ -103,3 +106,85 @@ def sizes_from_J(J: int, dims: Sequence[int]) -> List[int]:
         else:
             lo = mid + 1
     return [min(I, lo) for I in dims]
+
+
+# ----------------------------------------------------------------------------------
+# observation pattern: mask, outlier selection, per-entry uniforms
+#
+# Same generator, other keys: u(seed ^ "MASK", 0) for the mask, 1 for the outlier
+# selection, 2 for the uniforms.  An event of probability p happens when the draw is below
+# floor(p 2^64) (p >= 1: always; p <= 0: never).  Entry l is the column-major linear index.
+# The mask draws once per entry, or once per block x block tile of modes 0 and 1 at each
+# index of modes 3.. (shared by every index of mode 2, the colour channel of a video).
+
+DOMAIN_MASK = 0x4D41534B00000000  # "MASK"
+
+
+def mix64_np(z):
+    """mix64 over a numpy uint64 array (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def counter_u64_np(key: int, ctr):
+    """counter_u64(key, c) for a numpy array of counters c."""
+    c = np.asarray(ctr, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(key & M64) + (c + np.uint64(1)) * np.uint64(GOLDEN)
+    return mix64_np(z)
+
+
+def threshold(p: float):
+    """floor(p 2^64) as a Python int, or None for an event that always happens."""
+    if p >= 1.0:
+        return None
+    if not p > 0.0:
+        return 0
+    return int(math.ldexp(p, 64))
+
+
+def _below(draws, p: float):
+    thr = threshold(p)
+    if thr is None:
+        return np.ones(draws.shape, dtype=bool)
+    return draws < np.uint64(thr)
+
+
+def mask_keys(seed: int):
+    base = (seed ^ DOMAIN_MASK) & M64
+    return counter_u64(base, 0), counter_u64(base, 1), counter_u64(base, 2)
+
+
+def mask_draw_index(lin, dims: Sequence[int], block: int):
+    """Counter of the mask draw for entries lin: lin itself, or the entry's tile."""
+    lin = np.asarray(lin, dtype=np.int64)
+    if block <= 0:
+        return lin.astype(np.uint64)
+    i0 = lin % dims[0]
+    rest = lin // dims[0]
+    i1 = rest % dims[1]
+    rest = rest // dims[1]
+    if len(dims) >= 3:
+        rest = rest // dims[2]
+    nbh = -(-dims[0] // block)
+    nbw = -(-dims[1] // block)
+    return (i0 // block + nbh * (i1 // block + nbw * rest)).astype(np.uint64)
+
+
+def sample_mask_at(seed: int, dims: Sequence[int], rho: float, block: int, frac: float, lin):
+    """(mask, outlier selection, uniform) at the linear indices lin."""
+    km, ko, ku = mask_keys(seed)
+    lin = np.asarray(lin, dtype=np.int64)
+    obs = _below(counter_u64_np(km, mask_draw_index(lin, dims, block)), rho)
+    sel = obs & _below(counter_u64_np(ko, lin.astype(np.uint64)), frac) if frac > 0 else np.zeros_like(obs)
+    u = (counter_u64_np(ku, lin.astype(np.uint64)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return obs.astype(np.uint8), sel.astype(np.uint8), u
+
+
+def sample_mask(seed: int, dims: Sequence[int], rho: float, block: int = 0, frac: float = 0.0):
+    """The whole pattern as flat column-major arrays (small tensors only)."""
+    n = int(np.prod(dims))
+    return sample_mask_at(seed, dims, rho, block, frac, np.arange(n, dtype=np.int64))

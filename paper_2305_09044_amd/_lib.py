@@ -91,6 +91,7 @@ def load() -> C.CDLL:
         "trd_loss_fwd": (i32, [vp, P(vp), dbl, vp, vp]),
         "trd_loss_bwd": (i32, [vp, P(vp), dbl, dbl, P(vp), vp]),
         "trd_sample_sketch": (i32, [C.c_uint64, i32, i32, i32, P(i64), P(C.c_int32), P(vp), vp]),
+        "trd_sample_mask": (i32, [C.c_uint64, i32, P(i64), dbl, i32, dbl, vp, vp, vp, vp]),
         "trd_fgmc_gram_noalloc": (i32, [i32, P(i64), P(C.c_int32), i32, P(vp), i32, vp, vp]),
         "trd_set_precision": (i32, [vp, i32]),
         "trd_set_variant": (i32, [vp, i32, i32]),
@@ -165,6 +166,23 @@ def trd_weights(resid: torch.Tensor, sigma: float, out: Optional[torch.Tensor] =
     _check(lib.trd_weights(_ptr(resid), resid.numel(), _dtype_code(resid.dtype), float(sigma),
                            _ptr(out), C.c_void_p(_stream())))
     return out
+
+
+def trd_sample_mask(seed: int, dims: Sequence[int], rho: float, block: int = 0,
+                    outlier_frac: float = 0.0, outliers: bool = False, uniforms: bool = False,
+                    device="cuda"):
+    """Observation mask (uint8, column-major flat), and optionally the outlier selection
+    (uint8) and the per-entry uniforms (float64), drawn on the device (trd_sample_mask)."""
+    lib = load()
+    N = len(dims)
+    n = math.prod(int(v) for v in dims)
+    mask = torch.empty(n, dtype=torch.uint8, device=device)
+    sel = torch.empty(n, dtype=torch.uint8, device=device) if outliers else None
+    u = torch.empty(n, dtype=torch.float64, device=device) if uniforms else None
+    d = (C.c_int64 * N)(*[int(v) for v in dims])
+    _check(lib.trd_sample_mask(int(seed), N, d, float(rho), int(block), float(outlier_frac),
+                               _ptr(mask), _ptr(sel), _ptr(u), C.c_void_p(_stream())))
+    return mask, sel, u
 
 
 def trd_fgmc_gram_noalloc(cores: Sequence[torch.Tensor], dims: Sequence[int], ranks: Sequence[int],

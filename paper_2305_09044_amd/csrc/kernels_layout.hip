@@ -1,6 +1,10 @@
 // Observed-entry layouts (sliced ELL per core-k matrix) and RStS index sampling.
 #include "trd_internal.h"
 
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
 namespace trd {
 
 // ---------------------------------------------------------------- small utilities
@@ -346,6 +350,90 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
     o[pos] = (int32_t)v;
     ++m;
   }
+}
+
+// ---------------------------------------------------------------- masks and outliers
+// Per-entry (or per-tile) Bernoulli draws from the same counter generator: an event of
+// probability p happens when the draw is below floor(p 2^64) (integer compare; p >= 1:
+// always).  Keys: u(seed ^ "MASK", 0) for the mask, 1 for the outlier selection, 2 for the
+// per-entry uniform u = (draw >> 11) 2^-53 in [0, 1).
+
+struct MaskArgs {
+  uint64_t key_m, key_o, key_u;
+  uint64_t thr_m, thr_o;
+  int all_m, all_o, none_o;
+  int N, block;
+  int64_t dims[kMaxN];
+  int64_t n;
+  int64_t nbh, nbw;
+  uint8_t* mask;
+  uint8_t* sel;
+  double* u;
+};
+
+__global__ __launch_bounds__(256) void k_sample_mask(MaskArgs a) {
+  for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < a.n;
+       l += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t draw_at = (uint64_t)l;
+    if (a.block > 0) {  // tile of modes 0 and 1 at this index of modes 3.. (mode 2 shared)
+      int64_t rem = l;
+      const int64_t i0 = rem % a.dims[0];
+      rem /= a.dims[0];
+      const int64_t i1 = rem % a.dims[1];
+      rem /= a.dims[1];
+      if (a.N >= 3) rem /= a.dims[2];
+      draw_at = (uint64_t)(i0 / a.block + a.nbh * (i1 / a.block + a.nbw * rem));
+    }
+    const bool obs = a.all_m || counter_u64(a.key_m, draw_at) < a.thr_m;
+    a.mask[l] = obs ? 1 : 0;
+    if (a.sel) {
+      const bool pick = obs && !a.none_o && (a.all_o || counter_u64(a.key_o, (uint64_t)l) < a.thr_o);
+      a.sel[l] = pick ? 1 : 0;
+    }
+    if (a.u) a.u[l] = (double)(counter_u64(a.key_u, (uint64_t)l) >> 11) * 0x1p-53;
+  }
+}
+
+// floor(p 2^64) for 0 < p < 1 (exact: p 2^64 is a double with the same mantissa)
+static uint64_t prob_threshold(double p) { return (uint64_t)ldexp(p, 64); }
+
+hipError_t launch_sample_mask(uint64_t seed, int N, const int64_t* dims, double rho, int block,
+                              double frac, uint8_t* mask, uint8_t* sel, double* u, hipStream_t st) {
+  MaskArgs a;
+  memset(&a, 0, sizeof(a));
+  const uint64_t base = seed ^ 0x4D41534B00000000ull;  // "MASK"
+  auto host_u = [](uint64_t key, uint64_t c) {
+    uint64_t z = key + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  a.key_m = host_u(base, 0);
+  a.key_o = host_u(base, 1);
+  a.key_u = host_u(base, 2);
+  a.all_m = rho >= 1.0;
+  a.thr_m = (rho > 0.0 && rho < 1.0) ? prob_threshold(rho) : 0;
+  a.all_o = frac >= 1.0;
+  a.none_o = !(frac > 0.0);
+  a.thr_o = (frac > 0.0 && frac < 1.0) ? prob_threshold(frac) : 0;
+  a.N = N;
+  a.block = block;
+  a.n = 1;
+  for (int j = 0; j < N; ++j) {
+    a.dims[j] = dims[j];
+    a.n *= dims[j];
+  }
+  if (block > 0) {
+    a.nbh = (dims[0] + block - 1) / block;
+    a.nbw = (dims[1] + block - 1) / block;
+  }
+  a.mask = mask;
+  a.sel = sel;
+  a.u = u;
+  if (a.n <= 0) return hipSuccess;
+  const int64_t g = std::min<int64_t>((a.n + 255) / 256, (int64_t)g_num_cu * 64);
+  hipLaunchKernelGGL(k_sample_mask, dim3((unsigned)g), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_sample(uint64_t seed, int t, int k, int N, const int64_t* dims,

@@ -2,6 +2,8 @@
 // one core update (Alg. 1 body) and of the sweep loop.  Every compute step runs in a
 // kernel on the caller's stream; the host only plans sizes and launches.
 #include <math.h>
+
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -693,7 +695,8 @@ int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStr
 }
 
 // matrix-core pass (its bf16 tables are written by the table builders)
-int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
+// keep_w: a gradient pass stores each entry's weight for the line search that follows it
+int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w) {
   const TLayout& TL = *up.TL;
   const Split& sp = up.sp;
   TPassArgs a;
@@ -730,7 +733,7 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   // positions): below that, a block rarely needs a fifth round from memory
   a.rounds = TL.n_blocks > 0 && TL.nobs > 224 * TL.n_blocks ? 8 : 4;
   a.nobs = TL.nobs;
-  if (mode == kModeGrad || mode == kModeGradFast || mode == kModeGradE) a.wout = ctx->wts;
+  if (keep_w && (mode == kModeGrad || mode == kModeGradFast || mode == kModeGradE)) a.wout = ctx->wts;
   if (mode == kModeGradE) {  // the residual pass's e; no reconstruction, no split tables
     a.vals = ctx->resid;
     a.T_lo = nullptr;
@@ -745,7 +748,7 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
   return TRD_OK;
 }
 
-int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
+int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w = false) {
   const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
@@ -754,7 +757,7 @@ int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
     CK(hipEventRecord(e0, st));
   }
   if (up.TL) {
-    TRY(launch_tile_pass(ctx, up, mode, st));
+    TRY(launch_tile_pass(ctx, up, mode, st, keep_w));
   } else {
     PassArgs a = pass_args(ctx, up);
     CK(launch_pass(ctx->dtype, 0, mode, a, st));
@@ -778,8 +781,9 @@ int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st) {
 }
 
 // gradient of eq. (9)/(15) for the prepared update: tables, pass, contraction -> d64
+// keep_w: a line search of the same update follows (the matrix-core pass keeps the weights)
 int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_out, double scale,
-            double* stats_dev, hipStream_t st, ItemRef* Uout, int64_t* nBout) {
+            double* stats_dev, hipStream_t st, ItemRef* Uout, int64_t* nBout, bool keep_w = false) {
   const Split& sp = up.sp;
   const Layout& L = *up.L;
   int64_t needT, needV, needU, needC;
@@ -807,7 +811,7 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
     TRY(build_coltable(ctx, up, cores, st));
   }
   TRY(ensure_S(ctx, (int64_t)up_nct(up) * L.nrows * sp.RRP));
-  TRY(run_pass(ctx, up, stats_dev ? kModeGrad : (reuse_e ? kModeGradE : kModeGradFast), st));
+  TRY(run_pass(ctx, up, stats_dev ? kModeGrad : (reuse_e ? kModeGradE : kModeGradFast), st, keep_w));
   ctx->resid_core = -1;  // the core changes with this update
   if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, stats_dev, st));
   // a few column-group partials are added by the contraction as it loads S; many are
@@ -901,7 +905,7 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
   }
   ItemRef Uref;
   int64_t nB;
-  TRY(do_grad(ctx, up, (const void* const*)cores, nullptr, 1.0, nullptr, st, &Uref, &nB));
+  TRY(do_grad(ctx, up, (const void* const*)cores, nullptr, 1.0, nullptr, st, &Uref, &nB, true));
   if (scaled) CK(hipStreamWaitEvent(st, ctx->ev_join, 0));
   const int64_t nbl = (Ik * R + 255) / 256;
   TRY(ensure_part(ctx, 0, nbl));
@@ -1399,6 +1403,25 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
     s[j] = (int32_t)std::min<int64_t>(j == k ? dims[j] : sizes[j], dims[j]);
   }
   CK(launch_sample(seed, t, k, N, dims, s, idx_out, (hipStream_t)stream));
+  return TRD_OK;
+}
+
+int trd_sample_mask(uint64_t seed, int N, const int64_t* dims, double rho, int block,
+                    double outlier_frac, uint8_t* mask_out, uint8_t* outlier_out, double* u_out,
+                    void* stream) {
+  trd_ctx* ctx = nullptr;
+  if (N < 2 || N > kMaxN) return fail(nullptr, TRD_EINVAL, "N must be in [2, 8]");
+  if (!dims || !mask_out) return fail(nullptr, TRD_EINVAL, "NULL argument");
+  double total = 1.0;
+  for (int j = 0; j < N; ++j) {
+    if (dims[j] < 1) return fail(nullptr, TRD_EINVAL, "dims must be >= 1");
+    total *= (double)dims[j];
+  }
+  if (total >= 4.6e18) return fail(nullptr, TRD_EUNSUPPORTED, "prod(dims) must be < 2^62");
+  if (std::isnan(rho) || std::isnan(outlier_frac)) return fail(nullptr, TRD_EINVAL, "rho / outlier_frac is NaN");
+  if (block < 0) return fail(nullptr, TRD_EINVAL, "block must be >= 0");
+  CK(launch_sample_mask(seed, N, dims, rho, block, outlier_frac, mask_out, outlier_out, u_out,
+                        (hipStream_t)stream));
   return TRD_OK;
 }
 

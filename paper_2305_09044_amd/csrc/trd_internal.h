@@ -121,6 +121,11 @@ hipError_t launch_fill(const Layout& L, const uint8_t* mask, const void* X, int 
                        hipStream_t st);
 hipError_t launch_sample(uint64_t seed, int t, int k, int N, const int64_t* dims,
                          const int32_t* sizes, int32_t* const* out, hipStream_t st);
+// mask (Bernoulli rho per entry, or per block x block tile of modes 0-1 at each index of
+// modes 3.., shared by mode 2), outlier selection (observed and Bernoulli frac) and per-entry
+// uniforms; sel and u may be nullptr
+hipError_t launch_sample_mask(uint64_t seed, int N, const int64_t* dims, double rho, int block,
+                              double frac, uint8_t* mask, uint8_t* sel, double* u, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 hipError_t launch_copy_clamp(const int32_t* in, int64_t n, int64_t dim, int32_t* out,
                              uint32_t* bad, hipStream_t st);

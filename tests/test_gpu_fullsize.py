@@ -33,14 +33,15 @@ import paper_2305_09044_amd as trd  # noqa: E402
 class Full:
     """One workload at full size: device problem plus host copies for the oracle."""
 
-    def __init__(self, name, seed=0):
-        w, dims, Xd, Pd, mask, xs = bench.build_inputs(name, seed)
-        self.w, self.dims = w, tuple(dims)
+    def __init__(self, name, seed=0, perturbed=False):
+        w, dims, Xd, Pd, xs, cores_t = bench.build_inputs(name, seed)
+        self.w, self.dims, self.seed = w, tuple(dims), seed
         self.prob = trd.Problem(Xd, Pd, dims, w.ranks)
         self.Xd, self.Pd, self.xs = Xd, Pd, xs
         self.X = Xd.cpu().numpy()               # column-major flat, FP32
-        self.mask = mask                        # host, shaped
-        Z = synth.init_cores(dims, w.ranks, seed)
+        self.mask = Pd.cpu().numpy().reshape(dims, order="F")   # host, shaped
+        # the start of a fit, or (the differentiation form) the true cores perturbed
+        Z = synth.perturbed_cores(cores_t, seed, rel=0.1) if perturbed else synth.init_cores(dims, w.ranks, seed)
         self.Z = [z.astype(np.float32).astype(np.float64) for z in Z]
         self.cores = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(self.Z, np.float32)]
         self.strides = np.cumprod((1,) + self.dims[:-1])
@@ -183,3 +184,45 @@ def test_sketch_workloads_full_size(name):
             assert int(stats[2].item()) == int(Ps.sum())
     finally:
         f.close()
+
+
+@pytest.fixture(scope="module")
+def cfg_diff():
+    f = Full("tr4_200_r10", perturbed=True)
+    yield f
+    f.close()
+
+
+def test_differentiation_workload_pattern_bit_exact(cfg_diff):
+    # 200^4 mask and outlier selection from the device sampler, against the oracle's
+    # generator at a uniform sample of entries (and the observed count it implies)
+    f = cfg_diff
+    w = f.w
+    g = np.random.default_rng(3)
+    lin = g.integers(0, f.X.size, 1 << 16)
+    m, sel, u = orng.sample_mask_at(f.seed, f.dims, w.rho, 0, w.outlier_frac, lin)
+    np.testing.assert_array_equal(f.mask.ravel(order="F")[lin], m)
+    xs = f.xs.cpu().numpy()
+    # where an observed entry was not selected as an outlier it keeps its clean value
+    keep = (m == 1) & (sel == 0)
+    np.testing.assert_array_equal(f.X[lin][keep], xs[lin][keep])
+    assert abs(f.prob.info()["n_obs"] / f.X.size - w.rho) < 1e-4
+
+
+@pytest.mark.parametrize("prec,bar", [("native", 1e-4), ("bf16", 2e-2)])
+def test_differentiation_workload_backward_rows(cfg_diff, prec, bar):
+    # the all-core backward at 200^4, rank 10 (r_k r_{k+1} = 100, K = 128): rows of dL/dZ_k
+    # for every core against minus the oracle's gradient row at the same point
+    f = cfg_diff
+    sigma = 0.8
+    f.prob.set_precision(prec)
+    grads = f.prob.loss_bwd(f.cores, sigma)
+    f.prob.set_precision("native")
+    worst = 0.0
+    for k, i in ((0, 0), (1, 117), (2, 199), (3, 64)):
+        r, r2 = f.w.ranks[k], f.w.ranks[(k + 1) % 4]
+        G = grads[k].cpu().numpy().astype(np.float64).reshape(f.dims[k], r2 * r)
+        e = rel(-G[i], f.oracle_row(k, i, sigma))
+        worst = max(worst, e)
+        assert e <= bar, (prec, k, i, e)
+    print(f"{prec}: 200^4 rank-10 backward, worst row error {worst:.2e}")

@@ -377,3 +377,23 @@ def test_autograd_function_fd():
                 cm[k][idx] -= h
                 fd = (float(prob.loss_fwd(cp, sigma)) - float(prob.loss_fwd(cm, sigma))) / (2 * h)
             assert abs(g[k][idx] - fd) <= 1e-6 * max(1.0, abs(fd)), (k, idx, g[k][idx], fd)
+
+
+@pytest.mark.parametrize("seed,dims,rho,block,frac", [
+    (0, (30, 30, 30), 0.5, 0, 0.1),
+    (7, (37, 41, 29, 23), 0.3, 0, 0.2),
+    (2**63 + 11, (40, 36, 3, 7), 0.2, 16, 0.1),      # ragged 16 x 16 tiles, channel mode
+    (5, (300, 257), 0.05, 0, 0.0),
+    (9, (9, 10, 11, 8, 7), 1.0, 0, 1.0),
+    (9, (9, 10, 11, 8, 7), 0.0, 0, 0.5),
+    (4, (17, 33, 5), 0.4, 4, 0.15),
+])
+def test_sample_mask_bit_exact(seed, dims, rho, block, frac):
+    m, s, u = trd.trd_sample_mask(seed, dims, rho, block, frac, outliers=True, uniforms=True)
+    rm, rs, ru = orng.sample_mask(seed, dims, rho, block, frac)
+    np.testing.assert_array_equal(m.cpu().numpy(), rm)
+    np.testing.assert_array_equal(s.cpu().numpy(), rs)
+    np.testing.assert_array_equal(u.cpu().numpy(), ru)
+    # the mask alone (no optional outputs) is the same
+    m2, _, _ = trd.trd_sample_mask(seed, dims, rho, block, frac)
+    assert torch.equal(m, m2)

@@ -528,3 +528,53 @@ def test_fit_records_the_schedule_it_used():
         assert b >= 0.5 * a
     # exact data with a shrinking residual: the limit is reached at least once
     assert any(b == 0.5 * a for a, b in zip(hist["sigma"], hist["sigma"][1:]))
+
+
+# ---------------------------------------------------------------- observation pattern sampler
+
+def test_vector_counter_generator_matches_published_outputs():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "splitmix64_kat.txt")) if l[0] != "#"]
+    for seed, n, val in rows:
+        assert int(orng.counter_u64_np(int(seed), np.array([int(n) - 1]))[0]) == int(val, 16)
+
+
+def test_probability_thresholds_are_exact():
+    assert orng.threshold(0.5) == 1 << 63
+    assert orng.threshold(0.25) == 1 << 62
+    assert orng.threshold(0.1) == int(math.ldexp(0.1, 64)) == 1844674407370955264
+    assert orng.threshold(1.0) is None and orng.threshold(0.0) == 0 and orng.threshold(-1.0) == 0
+
+
+def test_bernoulli_mask_density_and_outliers():
+    dims = (101, 99, 100)                                # 999,900 entries
+    m, s, u = orng.sample_mask(7, dims, 0.3, 0, 0.2)
+    n = m.size
+    assert abs(m.mean() - 0.3) < 5 * math.sqrt(0.3 * 0.7 / n)
+    assert np.all(s <= m)                                # outliers only where observed
+    k = int(m.sum())
+    assert abs(s.sum() / k - 0.2) < 5 * math.sqrt(0.2 * 0.8 / k)
+    assert u.min() >= 0.0 and u.max() < 1.0 and abs(u.mean() - 0.5) < 0.002
+    assert np.all(np.floor(u * 2.0 ** 53) == u * 2.0 ** 53)   # 53-bit grid
+    # seeds and keys are independent streams
+    m2, _, _ = orng.sample_mask(8, dims, 0.3)
+    assert np.mean(m == m2) < 0.6
+    assert orng.sample_mask(7, dims, 1.0)[0].all() and not orng.sample_mask(7, dims, 0.0)[0].any()
+
+
+def test_block_mask_is_tiled_and_shared_by_the_channel_mode():
+    dims, B = (40, 36, 3, 7), 16                         # ragged tiles along both modes
+    m, _, _ = orng.sample_mask(3, dims, 0.2, B)
+    M = m.reshape(dims, order="F")
+    assert np.all(M == M[:, :, :1, :])                   # shared by mode 2
+    nbh, nbw = 3, 3
+    tiles = []
+    for f in range(dims[3]):
+        for bh in range(nbh):
+            for bw in range(nbw):
+                t = M[bh * B:(bh + 1) * B, bw * B:(bw + 1) * B, 0, f]
+                assert t.min() == t.max()                # a tile is all observed or all missing
+                tiles.append(int(t[0, 0]))
+    assert len(tiles) == 63
+    big, _, _ = orng.sample_mask(3, (16 * 50, 16 * 40, 3, 20), 0.2, B)
+    Mb = big.reshape((16 * 50, 16 * 40, 3, 20), order="F")[::B, ::B, 0, :]
+    assert abs(Mb.mean() - 0.2) < 5 * math.sqrt(0.2 * 0.8 / Mb.size)
