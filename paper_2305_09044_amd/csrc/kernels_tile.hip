@@ -277,13 +277,19 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
   // a padding column and their sums are dropped).  No branches, so a group of rounds issues its LDS reads
   // together.  In the least-squares limit k2 = 0 and the weight is exactly 1.
   // wkeep: where a gradient pass leaves the weight for a later store (nullptr: store now)
-  auto entry = [&](float x, uint32_t p, bool valid, int64_t idx, float* wkeep) {
-    // bits 0..11 of p: the tile index (< 64 kTS for every slot read: positions of this
-    // or a later block, or zero slack); the bits above are ignored
+  // g: the entry's value in the wave's xhat (or q) tile, read beforehand by gather() so
+  // that the tile reads of a group of rounds are in flight together
+  // bits 0..11 of p: the tile index (< 64 kTS for every slot read: positions of this or a
+  // later block, or zero slack); the bits above are ignored
+  auto gather = [&](uint32_t p) -> float {
+    if constexpr (kGradE) return 0.f;  // no tile: the stored residual is the entry's value
+    else return Xs[(int)(p & 4095u)];
+  };
+  auto entry = [&](float x, uint32_t p, bool valid, int64_t idx, float* wkeep, float g) {
     const int pi = (int)(p & 4095u);
     if constexpr (kLS) {  // the low 16 bits of x hold the entry's weight (fp16)
       const float wv = (float)__builtin_bit_cast(_Float16, (uint16_t)(__float_as_uint(x) & 0xffffu));
-      const float q = Qs[pi];
+      const float q = g;
       f0 = fmaf(valid ? wv * q : 0.f, q, f0);
       return;
     }
@@ -291,8 +297,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
     if constexpr (kGradE) {
       e = x;  // the stored residual
     } else {
-      const float xh = Xs[pi];
-      e = x - xh;
+      e = x - g;
     }
     const float wgt = __builtin_amdgcn_exp2f(-(e * e * k2));
     if constexpr (kGrad) {
@@ -389,16 +394,22 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
   };
 
   // A operand of the gradient product (V^T rows of one chunk), read from the transposed
-  // table: loaded for the next chunk right after the current chunk's products
-  bf16x8 aw[kGrad ? 2 : 1][kGrad ? MT : 1];
-  auto load_aw = [&](int64_t gc) {
+  // table.  Plain form with K <= 64: two buffers, the step that consumes one loads the next
+  // chunk's rows into the other at its start, a whole step before their use (the buffer
+  // index is a compile-time constant after unrolling).  The split and wide forms, K > 64
+  // and the pass that reads stored residuals (which would lose a wave per SIMD) have no
+  // registers to spare: one buffer, loaded at the end of the step before its use.
+  constexpr bool kDB = kGrad && !kGradE && !SPLIT && !WIDE && K <= 64;
+  bf16x8 aw[kDB ? 2 : 1][kGrad ? 2 : 1][kGrad ? MT : 1];
+  auto load_aw = [&](int64_t gc, int buf) {
+    if constexpr (!kDB) buf = 0;
     if constexpr (kGrad) {
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          aw[s2][mt] = *reinterpret_cast<const bf16x8*>(a.VTf + gc * 32 * K +
-                                                        (s2 * MT + mt) * 512 + l * 8);
+          aw[buf][s2][mt] = *reinterpret_cast<const bf16x8*>(a.VTf + gc * 32 * K +
+                                                             (s2 * MT + mt) * 512 + l * 8);
     }
   };
 
@@ -459,7 +470,8 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
     }
   };
   // S^T += V^T-items^T . Y^T over a chunk's 32 columns (two k-steps of 16)
-  auto grad_products = [&]() {
+  auto grad_products = [&](int buf) {
+    if constexpr (!kDB) buf = 0;
     if constexpr (kGrad) {
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2)
@@ -467,16 +479,17 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
           for (int n = 0; n < 2; ++n)
-            sacc[mt][n] =
-                __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[s2][mt], yb[s2][n], sacc[mt][n], 0, 0, 0);
+            sacc[mt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[buf][s2][mt], yb[s2][n],
+                                                                  sacc[mt][n], 0, 0, 0);
     }
   };
 
   // [bo_cur, bo_end): entries of chunk gc; bo_nend: start of chunk gc + 2
   int64_t bo_cur = 0, bo_end = 0, bo_nend = 0;
   int nent_prev = 0;  // entries of chunk gc - 1 (0 before the first chunk)
-  // P: set of chunk gc - 1 on entry, of chunk gc + 2 on exit; C: set of chunk gc
-  auto step = [&](int64_t gc, const Set& C, Set& P) {
+  // P: set of chunk gc - 1 on entry, of chunk gc + 2 on exit; C: set of chunk gc; ab: the
+  // gradient operand buffer holding the V^T rows of chunk gc - 1
+  auto step = [&](int64_t gc, const Set& C, Set& P, int ab) {
     if (!rb_ok) return;  // uniform over the wave
     const int64_t bo_nn = boff_at(min(gc + 3, gc_end));
     const int nent = (int)(bo_end - bo_cur);
@@ -503,22 +516,27 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
     // the set of chunk gc - 1 is free: load the entries of chunk gc + 2 (offset
     // bo_nend <= nobs)
     load_set(P, bo_nend);
+    // (two-buffer form: the V^T rows of chunk gc, for the next step, into the other buffer)
+    if constexpr (kDB) load_aw(gc, ab ^ 1);
 
     // 2. matrix-core products of Xhat(gc + 1) and S(gc - 1), with the first four rounds
     //    of entries of chunk gc in the same straight-line block
     // (the gradient products first: their operands are then free before the
     // reconstruction accumulators are live)
-    grad_products();
+    grad_products(ab);
     recon();
     // without gradient products the registers allow loading the next reconstruction
     // operands here, a whole chunk ahead of their use
     if constexpr (!kGrad) load_av(min(gc + 2, a.n_chunks));
+    float g[4];  // the tile reads of the first four rounds, issued together
+#pragma unroll
+    for (int t = 0; t < 4 && t < kR; ++t) g[t] = gather(C.pw[t] >> C.sh);
     float wk[4];  // weights of the first four rounds, stored after the operand loads below
 #pragma unroll
     for (int t = 0; t < 4 && t < kR; ++t) {
       const int i = 64 * t + l;
       entry(kLS ? __uint_as_float(__float_as_uint(C.x[t]) >> C.sh) : C.x[t], C.pw[t] >> C.sh,
-            i < nent, bo_cur + i, &wk[t]);
+            i < nent, bo_cur + i, &wk[t], g[t]);
     }
     // interleave: a wave waits at every product it issues while the matrix core is busy
     // with the previous one, so the vector work of the entries goes in between
@@ -532,11 +550,14 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
 #pragma unroll
     for (int t0 = 4; t0 < kR; t0 += 4) {
       if (64 * t0 < nent) {
+        float g4[4];
+#pragma unroll
+        for (int t = t0; t < t0 + 4; ++t) g4[t - t0] = gather(C.pw[t] >> C.sh);
 #pragma unroll
         for (int t = t0; t < t0 + 4; ++t) {
           const int i = 64 * t + l;
           entry(kLS ? __uint_as_float(__float_as_uint(C.x[t]) >> C.sh) : C.x[t], C.pw[t] >> C.sh,
-                i < nent, bo_cur + i, nullptr);
+                i < nent, bo_cur + i, nullptr, g4[t - t0]);
         }
       }
     }
@@ -547,7 +568,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
       if constexpr (kLS) x = valid ? __uint_as_float((uint32_t)a.win[bo_cur + i]) : 0.f;
       else x = valid ? a.vals[bo_cur + i] : 0.f;
       const uint32_t p = valid ? (uint32_t)a.pos[bo_cur + i] : 0u;
-      entry(x, p, valid, bo_cur + i, nullptr);
+      entry(x, p, valid, bo_cur + i, nullptr, gather(p));
     }
     wave_sync();
 
@@ -558,7 +579,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
     //    V^T rows of chunk gc and V^T items of chunk gc + 2 (clamped: the fragment tables
     //    end with one padding chunk)
     if constexpr (kGrad) {
-      load_aw(gc);
+      if constexpr (!kDB) load_aw(gc, 0);
       load_av(min(gc + 2, a.n_chunks));
       // the weights last: memory operations retire in order, so stores issued before the
       // operand loads would hold up the next step's wait for those operands
@@ -590,7 +611,7 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
 #pragma unroll
     for (int s2 = 0; s2 < (kGrad ? 2 : 1); ++s2)
 #pragma unroll
-      for (int mt = 0; mt < (kGrad ? MT : 1); ++mt) aw[s2][mt] = bf16x8{};  // no chunk gc_beg - 1
+      for (int mt = 0; mt < (kGrad ? MT : 1); ++mt) aw[0][s2][mt] = bf16x8{};  // no chunk gc_beg - 1
     recon();
     load_av(gc_beg + 1);  // <= n_chunks
     spill();
@@ -599,14 +620,19 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && 
   // the first loads land before the walk: otherwise the counted waits at the top of the
   // chunk loop must also cover these (register assignment differs between the two paths)
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-  for (int64_t gc = gc_beg; gc < gc_end; gc += 3) {
-    step(gc, A, C);
-    if (gc + 1 < gc_end) step(gc + 1, B, A);
-    if (gc + 2 < gc_end) step(gc + 2, C, B);
+  // three entry sets and two gradient operand buffers rotate: unrolled by six
+  for (int64_t gc = gc_beg; gc < gc_end; gc += 6) {
+    step(gc, A, C, 0);
+    if (gc + 1 < gc_end) step(gc + 1, B, A, 1);
+    if (gc + 2 < gc_end) step(gc + 2, C, B, 0);
+    if (gc + 3 < gc_end) step(gc + 3, A, C, 1);
+    if (gc + 4 < gc_end) step(gc + 4, B, A, 0);
+    if (gc + 5 < gc_end) step(gc + 5, C, B, 1);
   }
-  if (walk) {  // S of the last chunk
+  if (walk) {  // S of the last chunk: its V^T rows are in buffer (gc_end - gc_beg) & 1
     read_y();
-    grad_products();
+    if (!kDB || ((gc_end - gc_beg) & 1) == 0) grad_products(0);
+    else grad_products(1);
   }
 
   if constexpr (kGrad) {
