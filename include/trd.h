@@ -136,6 +136,23 @@ int trd_set_shape(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ranks
 int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ranks, int dtype,
                     const void* X, const uint8_t* mask, void* stream);
 
+/*
+ * Device workspace of a problem of this shape, before binding it (needs no context and
+ * allocates nothing): the buffers trd_set_problem allocates (observed-entry layouts,
+ * subchain tables, FGMC factors, Gram and partial sums) plus those a full-path trd_fit,
+ * trd_step or trd_grad in `precision` adds (block layouts, bf16 tables, stored weights,
+ * gradient partials, quantile buffers).  RStS sketch buffers are not included.  The tensor
+ * has n_obs observed entries (0 <= n_obs <= prod(dims)) out of the mask of eq. (2).
+ *  bound (optional): an upper bound for any mask with n_obs observed entries (at worst a
+ *    64-row slice of a layout pads every row to its longest one);
+ *  typical (optional): the same for a mask drawn uniformly at random (observed with
+ *    probability n_obs / prod(dims) independently), <= bound.
+ * `device` (HIP device index) fixes the planning (LDS per work-group, compute units), as
+ * for trd_create.  TRD_EDEVICE without a device; message: trd_last_error(NULL).
+ */
+int trd_workspace_bytes(int device, int N, const int64_t* dims, const int32_t* ranks, int dtype,
+                        int precision, int64_t n_obs, size_t* bound, size_t* typical);
+
 /* Host-side query: observed count, bytes of device workspace held, and the
  * subchain split chosen for core k (rows = I_k times the first `split` modes). */
 int trd_problem_info(const trd_ctx* ctx, int64_t* n_obs, size_t* workspace_bytes, int32_t* split);

@@ -91,6 +91,8 @@ def load() -> C.CDLL:
         "trd_loss_fwd": (i32, [vp, P(vp), dbl, vp, vp]),
         "trd_loss_bwd": (i32, [vp, P(vp), dbl, dbl, P(vp), vp]),
         "trd_sample_sketch": (i32, [C.c_uint64, i32, i32, i32, P(i64), P(C.c_int32), P(vp), vp]),
+        "trd_workspace_bytes": (i32, [i32, i32, P(i64), P(C.c_int32), i32, i32, i64, P(C.c_size_t),
+                                      P(C.c_size_t)]),
         "trd_sample_mask": (i32, [C.c_uint64, i32, P(i64), dbl, i32, dbl, vp, vp, vp, vp]),
         "trd_fgmc_gram_noalloc": (i32, [i32, P(i64), P(C.c_int32), i32, P(vp), i32, vp, vp]),
         "trd_set_precision": (i32, [vp, i32]),
@@ -166,6 +168,21 @@ def trd_weights(resid: torch.Tensor, sigma: float, out: Optional[torch.Tensor] =
     _check(lib.trd_weights(_ptr(resid), resid.numel(), _dtype_code(resid.dtype), float(sigma),
                            _ptr(out), C.c_void_p(_stream())))
     return out
+
+
+def trd_workspace_bytes(dims: Sequence[int], ranks: Sequence[int], n_obs: int,
+                        dtype: torch.dtype = torch.float32, precision: str = "native",
+                        device: int = 0) -> dict:
+    """Device workspace of a problem of this shape before binding it: {'bound', 'typical'}
+    (bytes; see include/trd.h)."""
+    lib = load()
+    N = len(dims)
+    d = (C.c_int64 * N)(*[int(v) for v in dims])
+    r = (C.c_int32 * N)(*[int(v) for v in ranks])
+    b, t = C.c_size_t(), C.c_size_t()
+    _check(lib.trd_workspace_bytes(int(device), N, d, r, _dtype_code(dtype), PRECISIONS[precision],
+                                   int(n_obs), C.byref(b), C.byref(t)))
+    return {"bound": b.value, "typical": t.value}
 
 
 def trd_sample_mask(seed: int, dims: Sequence[int], rho: float, block: int = 0,

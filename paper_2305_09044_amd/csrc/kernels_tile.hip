@@ -184,12 +184,8 @@ size_t tpass_lds(int mode, int K, int CW) {
   return (size_t)kXBytes;
 }
 
-// (the line search keeps only q and the TH operands: four waves per SIMD for K = 64)
-#ifndef LS_WAVES
-#define LS_WAVES 2
-#endif
 template <int K, int MODE, bool SPLIT, bool WIDE>
-__global__ __launch_bounds__(256, (K >= 96 ? 1 : (MODE == kModeLS && K == 64 && !WIDE ? LS_WAVES : 2))) void k_tpass(
+__global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(
     TPassArgs a) {
   constexpr int KS = K / 16;       // k-steps of the reconstruction MFMA
   constexpr int MT = K / 32;       // m-tiles of the gradient MFMA

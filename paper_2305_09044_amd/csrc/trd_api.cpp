@@ -423,14 +423,11 @@ int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStr
 // fewer, longer walks are preferred to the denser grid of the other passes
 constexpr int kTileWGPerCU = 6;
 
-// bitmask-tile layout of core k (same split as the ELL layout), built once on first use
-int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
-  TLayout& T = ctx->tlayouts[k];
-  if (T.ready) return TRD_OK;
-  const Split& sp = ctx->splits[k];
-  const Layout& L = ctx->layouts[k];
-  T.nrows = L.nrows;
-  T.ncols = L.ncols;
+// shape of the bitmask-tile layout of a core-k matrix (nrows x ncols, split sp): block and
+// column-tile counts and the column groups of the matrix-core passes (no device work)
+void plan_tile(const Split& sp, int64_t nrows, int64_t ncols, TLayout& T) {
+  T.nrows = nrows;
+  T.ncols = ncols;
   T.K = tile_k(sp.RRP);  // covers the padded width the row-factor partials are stored with
   T.n_chunks = (T.ncols + 31) / 32;
   const int64_t cwmax = tile_cw(T.K);
@@ -446,6 +443,15 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
     T.n_cg = (T.n_ct + T.cpg - 1) / T.cpg;
   }
   T.n_blocks = T.n_rb * T.n_chunks;
+}
+
+// bitmask-tile layout of core k (same split as the ELL layout), built once on first use
+int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
+  TLayout& T = ctx->tlayouts[k];
+  if (T.ready) return TRD_OK;
+  const Split& sp = ctx->splits[k];
+  const Layout& L = ctx->layouts[k];
+  plan_tile(sp, L.nrows, L.ncols, T);
   if ((int64_t)tpass_lds(kModeGradFast, T.K, T.CW) > g_lds_max)
     return fail(ctx, TRD_EUNSUPPORTED, "matrix-core pass does not fit the device LDS");
   T.rowoff = L.rowoff;
@@ -1127,6 +1133,145 @@ int trd_problem_info(const trd_ctx* ctx, int64_t* n_obs, size_t* workspace_bytes
   if (workspace_bytes) *workspace_bytes = ctx->ws_bytes;
   if (split)
     for (int k = 0; k < ctx->N; ++k) split[k] = ctx->splits[k].p;
+  return TRD_OK;
+}
+
+int trd_workspace_bytes(int device, int N, const int64_t* dims, const int32_t* ranks, int dtype,
+                        int precision, int64_t n_obs, size_t* bound, size_t* typical) {
+  if (N < 2 || N > kMaxN) return fail(nullptr, TRD_EUNSUPPORTED, "N must be in [2, 8]");
+  if (!dims || !ranks || (!bound && !typical)) return fail(nullptr, TRD_EINVAL, "NULL argument");
+  if (dtype != TRD_F32 && dtype != TRD_F64) return fail(nullptr, TRD_EINVAL, "dtype must be TRD_F32 or TRD_F64");
+  if (precision != TRD_PREC_NATIVE && !bf16_form(precision)) return fail(nullptr, TRD_EINVAL, "unknown precision");
+  if (bf16_form(precision) && dtype != TRD_F32)
+    return fail(nullptr, TRD_EUNSUPPORTED, "the BF16 form needs an FP32 problem");
+  double total = 1.0;
+  for (int j = 0; j < N; ++j) {
+    if (dims[j] < 1) return fail(nullptr, TRD_EINVAL, "dims must be >= 1");
+    if (ranks[j] < 1 || ranks[j] > kMaxRank) return fail(nullptr, TRD_EUNSUPPORTED, "ranks must be in [1, 16]");
+    total *= (double)dims[j];
+  }
+  if (total >= 4.6e18) return fail(nullptr, TRD_EUNSUPPORTED, "prod(dims) must be < 2^62");
+  int64_t nent = 1;
+  for (int j = 0; j < N; ++j) nent *= dims[j];
+  if (n_obs < 0 || n_obs > nent) return fail(nullptr, TRD_EINVAL, "n_obs must be in [0, prod(dims)]");
+  // the planning depends on the device (LDS per work-group, compute units) as in trd_create
+  {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n)
+      return fail(nullptr, TRD_EDEVICE, std::string("no HIP device ") + std::to_string(device));
+    int lds = 0, cus = 0;
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return fail(nullptr, TRD_EDEVICE, hipGetErrorString(e));
+    g_lds_max = lds;
+    if (cus > 0) g_num_cu = cus;
+  }
+  // a host-only context holding the shape, for the planning functions
+  trd_ctx c;
+  c.N = N;
+  c.dtype = dtype;
+  for (int j = 0; j < N; ++j) {
+    c.dims[j] = dims[j];
+    c.ranks[j] = ranks[j];
+  }
+  const int64_t e = (int64_t)esz(dtype);
+  auto al = [](int64_t bytes) -> int64_t { return bytes > 0 ? bytes : 256; };  // dev_alloc
+  int64_t fixed = 0, ell_bound = 0, ell_typ = 0;
+  // trd_set_shape: scalars, flags, FGMC factors (full and sampled), ring partials, G, inverse
+  int64_t maxR2 = 1, maxr2 = 1;
+  for (int j = 0; j < N; ++j) {
+    const int64_t R = (int64_t)ranks[j] * ranks[(j + 1) % N];
+    maxR2 = std::max(maxR2, R * R);
+    maxr2 = std::max<int64_t>(maxr2, (int64_t)ranks[j] * ranks[j]);
+  }
+  fixed += al(16 * 8) + al(4 * 4) + 2 * N * al(maxR2 * 8) + 2 * al(maxr2 * maxr2 * 8) + 2 * al(maxR2 * 8);
+  // trd_set_problem
+  fixed += al(2048 * 4) + al(4 * 4) + al(N * 8) + al(8);  // (+ trd_profile's counter)
+  int64_t needT = 0, needV = 0, needU = 0, needC = 0, needPass = 0, needMisc = 8, needD = 0;
+  int64_t growS = 0, growPass = 0, slots0 = 0, slots0_typ = 0;
+  std::vector<Split> sps(N);
+  std::vector<int64_t> nr(N), nc(N);
+  for (int k = 0; k < N; ++k) {
+    int ct_w, n_ct;
+    const int r = plan_split(&c, k, dims, sps[k], nr[k], nc[k], ct_w, n_ct);
+    if (r != TRD_OK) return fail(nullptr, r, c.err);
+    Layout L;
+    layout_dims(L, nr[k], nc[k], ct_w, n_ct);
+    fixed += al(L.nrows * 8) + al(L.ncols * 8) + al((int64_t)L.n_ct * L.n_rg * kRowsPerWG * 4) +
+             al(L.n_slices * 4) + al((L.n_slices + 1) * 8) + 2 * al(8);
+    // sliced ELL: 64 x (longest row of the 64-row slice, rounded up to kGroup) per slice;
+    // at worst every observed entry of a slice sits in one row
+    const int64_t wpad = (ct_w + kGroup - 1) / kGroup * kGroup;
+    const int64_t dense = L.n_slices * kWave * wpad;
+    const int64_t worst = std::min(dense, (int64_t)kWave * n_obs + (int64_t)kWave * (kGroup - 1) *
+                                                                    std::min(L.n_slices, n_obs));
+    // a uniformly random mask: row counts ~ Binomial(ct_w, rho); their maximum over 64 rows
+    // stays below mean + 3 standard deviations + 1 with high probability
+    const double rho = (double)n_obs / (double)nent;
+    const double mu = rho * ct_w, sd = std::sqrt(std::max(0.0, mu * (1.0 - rho)));
+    const int64_t mx = std::min<int64_t>(ct_w, (int64_t)std::ceil(mu + 3.0 * sd + 1.0));
+    const int64_t typ = n_obs == 0 ? 0 : std::min(dense, L.n_slices * kWave * ((mx + kGroup - 1) / kGroup * kGroup));
+    ell_bound += worst > 0 ? al(worst * e) + al(worst * 2) : 0;
+    ell_typ += typ > 0 ? al(typ * e) + al(typ * 2) : 0;
+    if (k == 0) {
+      slots0 = worst;
+      slots0_typ = typ;
+    }
+    int64_t a, b, c2, d;
+    table_needs(&c, sps[k], dims, nr[k], nc[k], a, b, c2, d);
+    needT = std::max(needT, a);
+    needV = std::max(needV, b);
+    needU = std::max(needU, c2);
+    needC = std::max(needC, d);
+    needPass = std::max(needPass, n_wg(L) * 3);
+    int64_t nB = 1;
+    for (int t = 0; t < sps[k].p; ++t) nB *= dims[sps[k].B[t]];
+    const int64_t R = (int64_t)sps[k].r_k * sps[k].r_k1;
+    needMisc = std::max(needMisc, (int64_t)contract_chunks(dims[k], nB, sps[k].r_k) * dims[k] * R);
+    needMisc = std::max(needMisc, (dims[k] * R + 255) / 256);
+    needD = std::max(needD, dims[k] * R);
+    // gradient partials (grown per core on first use: summed, an upper bound)
+    growS += al((int64_t)L.n_cg * L.nrows * sps[k].RRP * e);
+  }
+  {
+    const int64_t IN = dims[N - 1], R = (int64_t)ranks[N - 1] * ranks[0];
+    fixed += 2 * al(IN * IN * 8) + al(IN * R * 8);
+    needMisc = std::max(needMisc, 2 * ((IN * IN + 255) / 256));
+  }
+  fixed += 2 * al(needT * e) + al(needV * e) + (needU > 0 ? al(needU * e) : 0) + 2 * al(needC * e);
+  fixed += al(needPass * 8) + al(needMisc * 8) + 2 * al(needD * 8) + al(needD * e);
+  int64_t bnd = fixed + ell_bound + growS, typ = fixed + ell_typ + growS;
+  bnd += al(std::max<int64_t>(slots0, 1) * 4);      // residual keys (layout of core 0)
+  typ += al(std::max<int64_t>(slots0_typ, 1) * 4);
+  auto quantile_bytes = [&](int64_t nkeys) {
+    const int64_t ng = quantile_grid(nkeys);
+    return al(ng * quantile_seg_cap(nkeys) * 4) + al(ng * 4);
+  };
+  if (!bf16_form(precision)) {
+    bnd += quantile_bytes(slots0);
+    typ += quantile_bytes(slots0_typ);
+  } else {
+    // matrix-core passes: block layouts per core, stored weights, bf16 tables (grown per
+    // core: summed), their gradient partials and stats, the residuals of the quantile pass
+    const bool split = precision == TRD_PREC_BF16X3;
+    int64_t tiles = 0;
+    for (int k = 0; k < N; ++k) {
+      TLayout T;
+      plan_tile(sps[k], nr[k], nc[k], T);
+      tiles += al(T.n_blocks * 4) + al((T.n_blocks + 1) * 8) + al(8) + al((n_obs + kTileSlack) * 4) +
+               al((n_obs + kTileSlack) * 2);
+      const int64_t K = T.K, nf = tile_frag_elems(nc[k], K);
+      tiles += 2 * al(nr[k] * K * 2) + al(nc[k] * K * 2) + 2 * al(nf * 2);
+      if (split) tiles += al(nr[k] * K * 2) + al(nc[k] * K * 2) + al(nf * 2);
+      tiles += al((int64_t)T.n_cg * nr[k] * sps[k].RRP * e) + al(T.n_rg * T.n_cg * 3 * 8);
+    }
+    tiles += al((n_obs + kTileSlack + 1) * 2) + al((n_obs + kTileSlack) * 4) + quantile_bytes(n_obs);
+    bnd += tiles;
+    typ += tiles;
+  }
+  if (bound) *bound = (size_t)bnd;
+  if (typical) *typical = (size_t)std::min(bnd, typ);
   return TRD_OK;
 }
 

@@ -73,6 +73,34 @@ def test_sample_sketch_rejects_bad_arguments():
     assert lib.trd_sample_sketch(0, 0, 0, 2, d, s, outs, None) == _lib.TRD_EINVAL   # NULL outputs
 
 
+def test_workspace_query_checks_arguments_before_the_device():
+    lib = trd.load()
+    d = (C.c_int64 * 3)(10, 10, 10)
+    r = (C.c_int32 * 3)(3, 3, 3)
+    b = C.c_size_t()
+    f32, f64 = _lib.TRD_F32, _lib.TRD_F64
+    nat, bf = _lib.TRD_PREC_NATIVE, _lib.TRD_PREC_BF16
+    q = lib.trd_workspace_bytes
+    assert q(0, 1, d, r, f32, nat, 5, C.byref(b), None) == _lib.TRD_EUNSUPPORTED   # N < 2
+    assert q(0, 3, None, r, f32, nat, 5, C.byref(b), None) == _lib.TRD_EINVAL      # NULL dims
+    assert q(0, 3, d, r, f32, nat, 5, None, None) == _lib.TRD_EINVAL               # no output
+    assert q(0, 3, d, r, 7, nat, 5, C.byref(b), None) == _lib.TRD_EINVAL           # dtype
+    assert q(0, 3, d, r, f32, 9, 5, C.byref(b), None) == _lib.TRD_EINVAL           # precision
+    assert q(0, 3, d, r, f64, bf, 5, C.byref(b), None) == _lib.TRD_EUNSUPPORTED    # BF16 on FP64
+    assert q(0, 3, d, r, f32, nat, -1, C.byref(b), None) == _lib.TRD_EINVAL        # n_obs < 0
+    assert q(0, 3, d, r, f32, nat, 1001, C.byref(b), None) == _lib.TRD_EINVAL      # > prod(dims)
+    assert b"n_obs" in lib.trd_last_error(None)
+    r[1] = 17
+    assert q(0, 3, d, r, f32, nat, 5, C.byref(b), None) == _lib.TRD_EUNSUPPORTED   # rank > 16
+    r[1] = 3
+    import torch
+    rc = q(0, 3, d, r, f32, nat, 500, C.byref(b), None)
+    if torch.cuda.is_available():
+        assert rc == _lib.TRD_OK and b.value > 0
+    else:
+        assert rc == _lib.TRD_EDEVICE   # planning needs the device's LDS and unit counts
+
+
 def test_context_calls_reject_null_context():
     lib = trd.load()
     assert lib.trd_set_problem(None, 3, None, None, 0, None, None, None) == _lib.TRD_EINVAL
