@@ -22,6 +22,10 @@ with its justification in the design notes):
   * W is recomputed from the current cores at every core update.
   * eta = 0 (core unchanged) when the line-search denominator is 0.
   * convergence (Alg. 1): no stop test after the first sweep.
+  * uniform row sampling (ablation of Sec. 6.1): J rows of Z^{!=k}_{[2]} drawn
+    independently and uniformly with replacement, J = the row count of the RStS sketch
+    of the same sizes; no rescaling of the sampled rows (a common factor on them leaves
+    the step eta h unchanged); the Gram matrix stays the global one.
   * sigma schedule: 'fixed', 'given' (one value per sweep) or 'quantile'.  The paper
     defers to an external adaptive rule that is not reproduced in its text; the
     quantile rule is this project's own choice: PARITY UNPINNED beyond the
@@ -116,14 +120,25 @@ def _sub(cores, idx):
     return [Z[:, ix, :] for Z, ix in zip(cores, idx)]
 
 
+def _sampled_rows(X, P, cores, k, rows):
+    """X_[k], P_[k] and A = Z^{!=k}_{[2]} restricted to the sampled rows of A (and the
+    same columns of the unfoldings), duplicates kept."""
+    rows = np.asarray(rows, dtype=np.int64)
+    A = subchain_unfolding(cores, k)[rows]
+    return unfold_cyclic(X, k)[:, rows], unfold_cyclic(P, k)[:, rows], A
+
+
 def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, sigma: float,
                 lambda_rel: float = 1e-9, sketch: Optional[Sequence[Sequence[int]]] = None,
-                gram: str = "fgmc", direction: str = "scaled"):
+                gram: str = "fgmc", direction: str = "scaled", rows: Optional[np.ndarray] = None):
     """One update of core k (Alg. 1 body).  Returns (new core k, StepInfo).
 
     sketch: None for the full path (AWRTRD), else index lists I_1..I_N (RStS,
     eqs. 14-18): the gradient and the line search use the subtensor, the Gram matrix
     always uses the full cores.
+    rows: the uniform-row-sampling ablation of Sec. 6.1 instead of a sketch: indices of
+    rows of A = Z^{!=k}_{[2]} (with repeats); the gradient and the line search use those
+    rows of A and the same columns of X_[k], P_[k], the Gram matrix the full cores.
     gram: 'fgmc' (eq. 13) or 'explicit' (A^T A), both of the full cores; or 'local',
     the ablation of Sec. 6.1 that scales with the Gram matrix of the sampled cores only,
     A_I^T A_I of the sketched subchain unfolding (the full one without a sketch).
@@ -131,17 +146,23 @@ def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, s
     along d of eq. 9 / 15 itself, with the same exact line search).
     """
     N = len(cores)
-    if sketch is None:
-        Xs, Ps, cs = X, P, cores
-    else:
-        ix = np.ix_(*[np.asarray(s, dtype=np.int64) for s in sketch])
-        Xs, Ps = X[ix], P[ix]
-        cs = _sub(cores, sketch)
-        assert len(sketch[k]) == cores[k].shape[1], "mode k must be taken whole"
     rk, rk1 = cores[k].shape[0], cores[k].shape[2]
-    A = subchain_unfolding(cs, k)                       # (M x R^2)
-    Pk = unfold_cyclic(Ps, k).astype(bool)
-    Xk = np.where(Pk, unfold_cyclic(Xs, k), 0.0)        # unobserved values never used
+    if rows is not None:
+        assert sketch is None and gram != "local", "row sampling replaces the sketch"
+        Xr, Pr, A = _sampled_rows(X, P, cores, k, rows)
+        Pk = Pr.astype(bool)
+        Xk = np.where(Pk, Xr, 0.0)
+    else:
+        if sketch is None:
+            Xs, Ps, cs = X, P, cores
+        else:
+            ix = np.ix_(*[np.asarray(s, dtype=np.int64) for s in sketch])
+            Xs, Ps = X[ix], P[ix]
+            cs = _sub(cores, sketch)
+            assert len(sketch[k]) == cores[k].shape[1], "mode k must be taken whole"
+        A = subchain_unfolding(cs, k)                   # (M x R^2)
+        Pk = unfold_cyclic(Ps, k).astype(bool)
+        Xk = np.where(Pk, unfold_cyclic(Xs, k), 0.0)    # unobserved values never used
     Zk2 = unfold_core(cores[k])
     E = np.where(Pk, Xk - Zk2 @ A.T, 0.0)               # residual on observed entries
     W = np.where(Pk, weights(E, sigma), 0.0)            # eq. (7)
@@ -210,8 +231,13 @@ def convergence_matrix(cores: Sequence[np.ndarray]) -> np.ndarray:
     return Z @ gram_fgmc(cores, N - 1) @ Z.T
 
 
-def residual_abs(X, P, cores, sketch=None) -> np.ndarray:
-    """|x - xhat| on the observed entries (of the sketch, if given), in a fixed order."""
+def residual_abs(X, P, cores, sketch=None, rows=None, k=0) -> np.ndarray:
+    """|x - xhat| on the observed entries (of the sketch, or of update k's sampled rows,
+    if given), in a fixed order."""
+    if rows is not None:
+        Xr, Pr, A = _sampled_rows(X, P, cores, k, rows)
+        m = Pr.astype(bool)
+        return np.abs(Xr - unfold_core(cores[k]) @ A.T)[m]
     if sketch is None:
         Xs, Ps, cs = X, P, cores
     else:
@@ -248,26 +274,39 @@ class FitOptions:
     seed: int = 0
     gram: str = "fgmc"
     direction: str = "scaled"
+    sampling: str = "rsts"          # with sketch_sizes: 'rsts' or 'rows' (Sec. 6.1 ablation)
 
 
 def sketch_for(opts: FitOptions, t: int, k: int, dims):
-    if opts.sketch_sizes is None:
+    if opts.sketch_sizes is None or opts.sampling != "rsts":
         return None
     return _rng.sketch_indices(opts.seed, t, k, dims, opts.sketch_sizes)
+
+
+def rows_for(opts: FitOptions, t: int, k: int, dims):
+    """Uniform row sample of update (t, k): as many rows as the RStS sketch of the same
+    sizes holds (the product of the other modes' clamped sizes)."""
+    if opts.sketch_sizes is None or opts.sampling != "rows":
+        return None
+    J = 1
+    for j, (I, s) in enumerate(zip(dims, opts.sketch_sizes)):
+        if j != k:
+            J *= min(max(1, int(s)), int(I))
+    return _rng.uniform_rows(opts.seed, t, k, dims, J)
 
 
 def sweep_sigma(X, P, cores, opts: FitOptions, t: int, sigma_min: float,
                 sigma_prev: float = math.inf) -> float:
     """Kernel width for sweep t.  'quantile' (own rule, parity unpinned): over the
     observed entries the sweep's first update touches (all of them on the full path,
-    its sketch under RStS), sigma_t = max(c * Q_q(|e|), sigma_min, shrink * sigma_{t-1})
+    its sketch under RStS, its sampled rows under uniform row sampling), sigma_t = max(c * Q_q(|e|), sigma_min, shrink * sigma_{t-1})
     with the cores as they stand at the start of the sweep."""
     if opts.sigma_mode == "fixed":
         return float(opts.sigma)
     if opts.sigma_mode == "given":
         return float(opts.sigma_given[t])
     dims = [Z.shape[1] for Z in cores]
-    e = residual_abs(X, P, cores, sketch_for(opts, t, 0, dims))
+    e = residual_abs(X, P, cores, sketch_for(opts, t, 0, dims), rows_for(opts, t, 0, dims))
     s = quantile_sigma(e, opts.q, opts.c, sigma_min)
     if math.isfinite(sigma_prev):
         s = max(s, opts.shrink * sigma_prev)
@@ -281,7 +320,8 @@ def sweep(X, P, cores: List[np.ndarray], sigma: float, opts: FitOptions, t: int 
     cores = list(cores)
     for k in range(len(cores)):
         new, info = core_update(X, P, cores, k, sigma, opts.lambda_rel,
-                                sketch_for(opts, t, k, dims), opts.gram, opts.direction)
+                                sketch_for(opts, t, k, dims), opts.gram, opts.direction,
+                                rows_for(opts, t, k, dims))
         cores[k] = new
         infos.append(info)
     return cores, infos

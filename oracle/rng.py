@@ -91,6 +91,51 @@ def sketch_indices(seed: int, t: int, k: int, dims: Sequence[int], sizes: Sequen
     return out
 
 
+# ----------------------------------------------------------------------------------
+# uniform row sampling (the ablation of Sec. 6.1 that replaces RStS)
+#
+# Update k of sweep t draws J rows of Z^{!=k}_{[2]} independently and uniformly, with
+# replacement: sample n takes, for every mode j != k, the index
+# bounded(counter_u64(row_key(seed, t, k, j), n), 0, I_j) -- a fresh stream per (sample,
+# mode), so every sample can be drawn on its own.  The row is the little-endian index over
+# the cyclic modes k+1, ..., k-1 (the row order of Thm. 1).
+
+DOMAIN_ROWS = 0x55524F5700000000  # "UROW"
+
+
+def row_key(seed: int, t: int, k: int, j: int) -> int:
+    """Stream key for sweep t, core update k, mode j of the uniform row sampler."""
+    a = counter_u64((seed ^ DOMAIN_ROWS) & M64, t)
+    b = counter_u64(a, k)
+    return counter_u64(b, j)
+
+
+def uniform_row_indices(seed: int, t: int, k: int, dims: Sequence[int], J: int) -> np.ndarray:
+    """(J, N) per-mode indices of the sampled rows; column k is 0."""
+    N = len(dims)
+    out = np.zeros((J, N), dtype=np.int64)
+    for j in range(N):
+        if j == k:
+            continue
+        key = row_key(seed, t, k, j)
+        for n in range(J):
+            out[n, j] = bounded(counter_u64(key, n), 0, int(dims[j]))[0]
+    return out
+
+
+def uniform_rows(seed: int, t: int, k: int, dims: Sequence[int], J: int) -> np.ndarray:
+    """(J,) row indices m of Z^{!=k}_{[2]} (little-endian over modes k+1, ..., k-1)."""
+    N = len(dims)
+    idx = uniform_row_indices(seed, t, k, dims, J)
+    m = np.zeros(J, dtype=np.int64)
+    stride = 1
+    for s in range(1, N):
+        j = (k + s) % N
+        m += idx[:, j] * stride
+        stride *= int(dims[j])
+    return m
+
+
 def sizes_from_J(J: int, dims: Sequence[int]) -> List[int]:
     """Per-mode sample size from the sample parameter J.
 

@@ -578,3 +578,107 @@ def test_block_mask_is_tiled_and_shared_by_the_channel_mode():
     big, _, _ = orng.sample_mask(3, (16 * 50, 16 * 40, 3, 20), 0.2, B)
     Mb = big.reshape((16 * 50, 16 * 40, 3, 20), order="F")[::B, ::B, 0, :]
     assert abs(Mb.mean() - 0.2) < 5 * math.sqrt(0.2 * 0.8 / Mb.size)
+
+
+# ---------------------------------------------------------------- uniform row sampling (Sec. 6.1)
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_row_sampling_every_row_once_is_the_full_step(k):
+    # every row of Z^{!=k}_{[2]} once, in any order: the sampled update is the full update
+    dims, ranks = (4, 3, 5), (2, 3, 2)
+    Z, P, X = _masked_problem(dims, ranks, 61)
+    M = int(np.prod(dims)) // dims[k]
+    full, fi = aw.core_update(X, P, Z, k, 0.8)
+    for rows in (np.arange(M), np.random.default_rng(k).permutation(M)):
+        new, info = aw.core_update(X, P, Z, k, 0.8, rows=rows)
+        np.testing.assert_allclose(new, full, rtol=1e-12, atol=1e-12)
+        assert info.n_obs == fi.n_obs and info.eta == pytest.approx(fi.eta, rel=1e-12)
+
+
+def test_row_sampling_repeated_rows_leave_the_step_unchanged():
+    # every row twice: d and h double, eta halves, the step eta h is the full one
+    dims, ranks = (4, 3, 5), (2, 3, 2)
+    Z, P, X = _masked_problem(dims, ranks, 62)
+    M = int(np.prod(dims)) // dims[1]
+    full, fi = aw.core_update(X, P, Z, 1, 1.1)
+    new, info = aw.core_update(X, P, Z, 1, 1.1, rows=np.repeat(np.arange(M), 2))
+    np.testing.assert_allclose(info.d, 2 * fi.d, rtol=1e-12, atol=1e-12)
+    assert info.eta == pytest.approx(fi.eta / 2, rel=1e-12)
+    np.testing.assert_allclose(new, full, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("k", [0, 2, 3])
+def test_row_sampled_gradient_by_brute_force(k):
+    # eq. (9) on the sampled rows, summed entry by entry with A(m) multiplied out from the
+    # slices and x-hat from Def. 1, repeated rows counted each time they are drawn
+    dims, ranks = (3, 2, 4, 3), (2, 3, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 63)
+    N, sigma = len(dims), 0.7
+    idx = orng.uniform_row_indices(5, 1, k, dims, 40)
+    rows = orng.uniform_rows(5, 1, k, dims, 40)
+    _, info = aw.core_update(X, P, Z, k, sigma, rows=rows)
+    rk, rk1 = ranks[k], ranks[(k + 1) % N]
+    d = np.zeros((dims[k], rk * rk1))
+    for n in range(40):
+        Am = np.eye(rk1)
+        for s in range(1, N):
+            j = (k + s) % N
+            Am = Am @ Z[j][:, idx[n, j], :]
+        for i in range(dims[k]):
+            full = [int(v) for v in idx[n]]
+            full[k] = i
+            if not P[tuple(full)]:
+                continue
+            e = X[tuple(full)] - tr.reconstruct_entry(Z, full)
+            y = np.exp(-e * e / (2 * sigma * sigma)) * e
+            for a in range(rk):
+                for b in range(rk1):
+                    d[i, a + b * rk] += y * Am[b, a]
+    np.testing.assert_allclose(info.d, d, rtol=1e-12, atol=1e-12)
+
+
+def test_uniform_rows_decode_and_range():
+    dims = (5, 3, 7, 2)
+    for k in range(4):
+        idx = orng.uniform_row_indices(11, 2, k, dims, 300)
+        rows = orng.uniform_rows(11, 2, k, dims, 300)
+        M = int(np.prod(dims)) // dims[k]
+        assert rows.min() >= 0 and rows.max() < M
+        for j in range(4):
+            assert (idx[:, j] >= 0).all() and (idx[:, j] < dims[j]).all()
+        assert (idx[:, k] == 0).all()
+        # the row index is little-endian over modes k+1, ..., k-1
+        rest = rows.copy()
+        for s in range(1, 4):
+            j = (k + s) % 4
+            np.testing.assert_array_equal(rest % dims[j], idx[:, j])
+            rest //= dims[j]
+    # streams differ by sweep and by update
+    assert not np.array_equal(orng.uniform_rows(11, 0, 1, dims, 50), orng.uniform_rows(11, 1, 1, dims, 50))
+
+
+def test_uniform_rows_are_uniform():
+    dims = (2, 3, 5, 2)      # k = 0: M = 30 rows
+    rows = orng.uniform_rows(3, 0, 0, dims, 15000)
+    cnt = np.bincount(rows, minlength=30)
+    chi2 = np.sum((cnt - 500.0) ** 2 / 500.0)
+    assert chi2 < 58.3       # 29 dof; p ~ 1e-3 threshold
+
+
+def test_row_sampled_fit_and_quantile_use_the_update_rows():
+    dims, ranks = (5, 4, 6), (2, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 64)
+    opts = aw.FitOptions(max_sweeps=2, tol=0, sketch_sizes=(3, 2, 4), sampling="rows", seed=9)
+    rows = aw.rows_for(opts, 1, 2, dims)
+    assert rows.size == 3 * 2                                 # the RStS sketch's row count
+    np.testing.assert_array_equal(rows, orng.uniform_rows(9, 1, 2, dims, 6))
+    e = aw.residual_abs(X, P, Z, rows=aw.rows_for(opts, 0, 0, dims), k=0)
+    sig = aw.sweep_sigma(X, P, Z, opts, 0, 1e-12)
+    assert sig == aw.quantile_sigma(e, 0.5, 5.0, 1e-12)
+    # the sampled residuals are those of the explicit reconstruction at those fibres
+    r0 = aw.rows_for(opts, 0, 0, dims)
+    Xk, Pk = tr.unfold_cyclic(X, 0)[:, r0], tr.unfold_cyclic(P, 0)[:, r0].astype(bool)
+    Xh = tr.unfold_cyclic(tr.reconstruct(Z), 0)[:, r0]
+    np.testing.assert_allclose(np.sort(e), np.sort(np.abs(Xk - Xh)[Pk]), rtol=1e-12, atol=1e-14)
+    cores, hist = aw.fit(X, P, Z, opts)
+    assert len(hist["sigma"]) == 2 and all(np.isfinite(cores[0]).ravel())
