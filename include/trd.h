@@ -257,6 +257,19 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
                       int32_t* const* idx_out, void* stream);
 
 /*
+ * Draw the uniform row sample of update k in sweep t on the device (the row-sampling
+ * ablation of Sec. 6.1, used in place of RStS under TRD_SAMPLE_ROWS): J rows of the
+ * subchain unfolding Z^{!=k}_{[2]} (Thm. 1), independently and uniformly, with replacement.
+ * Sample n takes index bounded(u(key_j, n), 0, I_j) of every mode j != k, where
+ * key_j = u(u(u(seed ^ 0x55524F5700000000, t), k), j) and u and bounded are the generator
+ * and the bounded draw described at trd_sample_sketch (the draw's own counter starting
+ * at 0).  rows_out (device, J int64): the row index, little-endian over the modes
+ * k+1, ..., N, 1, ..., k-1, in sample order.  Needs no context.
+ */
+int trd_sample_rows(uint64_t seed, int t, int k, int N, const int64_t* dims, int64_t J, int64_t* rows_out,
+                    void* stream);
+
+/*
  * Seeded synthetic observation pattern on the device, bit-exact for a given seed:
  * mask_out[l] = 1 for an observed entry (column-major l), drawn with probability rho per
  * entry (block == 0) or per tile (block > 0: block x block tiles of modes 0 and 1, one draw
@@ -299,13 +312,22 @@ int trd_set_precision(trd_ctx* ctx, int precision);
  *     cores (the factors of eq. 13 summed over the sampled slices I_j only, which is
  *     A_I^T A_I of the sketched subchain unfolding) instead of the global one; without a
  *     sketch the two coincide.  Ignored with TRD_DIR_GRADIENT.
+ *   sampling TRD_SAMPLE_ROWS: a sketch (trd_step / trd_grad / trd_fit with sizes) takes
+ *     J = prod_{j != k} min(sizes[j], I_j) rows of Z^{!=k}_{[2]} drawn uniformly with
+ *     replacement (trd_sample_rows, same seed and sweep) instead of the RStS index sets:
+ *     the gradient, line search and kernel-width residuals use the mode-k fibres of the
+ *     tensor at those rows (a row drawn twice counts twice), the Gram matrix stays global.
+ *     Caller index lists (trd_sketch.idx) are rejected; with TRD_GRAM_LOCAL and the scaled
+ *     direction it is TRD_EUNSUPPORTED.
  * Returns TRD_EINVAL for other values (the context keeps its previous variant).
  */
 #define TRD_DIR_SCALED   0
 #define TRD_DIR_GRADIENT 1
 #define TRD_GRAM_GLOBAL  0
 #define TRD_GRAM_LOCAL   1
-int trd_set_variant(trd_ctx* ctx, int direction, int gram);
+#define TRD_SAMPLE_RSTS  0
+#define TRD_SAMPLE_ROWS  1
+int trd_set_variant(trd_ctx* ctx, int direction, int gram, int sampling);
 
 /*
  * Per-launch timing of the fused reconstruct+weight+gradient pass, for measurement:

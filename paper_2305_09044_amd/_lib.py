@@ -30,6 +30,8 @@ TRD_DIR_SCALED, TRD_DIR_GRADIENT = 0, 1
 TRD_GRAM_GLOBAL, TRD_GRAM_LOCAL = 0, 1
 DIRECTIONS = {"scaled": TRD_DIR_SCALED, "gradient": TRD_DIR_GRADIENT}
 GRAMS = {"global": TRD_GRAM_GLOBAL, "local": TRD_GRAM_LOCAL}
+TRD_SAMPLE_RSTS, TRD_SAMPLE_ROWS = 0, 1
+SAMPLINGS = {"rsts": TRD_SAMPLE_RSTS, "rows": TRD_SAMPLE_ROWS}
 TRD_FLAG_EMPTY, TRD_FLAG_ZERO_DEN, TRD_FLAG_NOTSPD = 1, 2, 4
 TRD_SIGMA_FIXED, TRD_SIGMA_GIVEN, TRD_SIGMA_QUANTILE = 0, 1, 2
 
@@ -91,12 +93,13 @@ def load() -> C.CDLL:
         "trd_loss_fwd": (i32, [vp, P(vp), dbl, vp, vp]),
         "trd_loss_bwd": (i32, [vp, P(vp), dbl, dbl, P(vp), vp]),
         "trd_sample_sketch": (i32, [C.c_uint64, i32, i32, i32, P(i64), P(C.c_int32), P(vp), vp]),
+        "trd_sample_rows": (i32, [C.c_uint64, i32, i32, i32, P(i64), i64, vp, vp]),
         "trd_workspace_bytes": (i32, [i32, i32, P(i64), P(C.c_int32), i32, i32, i64, P(C.c_size_t),
                                       P(C.c_size_t)]),
         "trd_sample_mask": (i32, [C.c_uint64, i32, P(i64), dbl, i32, dbl, vp, vp, vp, vp]),
         "trd_fgmc_gram_noalloc": (i32, [i32, P(i64), P(C.c_int32), i32, P(vp), i32, vp, vp]),
         "trd_set_precision": (i32, [vp, i32]),
-        "trd_set_variant": (i32, [vp, i32, i32]),
+        "trd_set_variant": (i32, [vp, i32, i32, i32]),
         "trd_profile": (i32, [vp, i32]),
         "trd_profile_read": (i32, [vp, P(i64), P(dbl), P(i64), P(i64)]),
     }
@@ -229,6 +232,18 @@ def trd_sample_sketch(seed: int, t: int, k: int, dims: Sequence[int], sizes: Seq
     _check(lib.trd_sample_sketch(int(seed), int(t), int(k), N, d, s, _ptr_array(outs),
                                  C.c_void_p(_stream())))
     return outs
+
+
+def trd_sample_rows(seed: int, t: int, k: int, dims: Sequence[int], J: int, device="cuda"):
+    """The uniform row sample of update k in sweep t: (J,) int64 row indices of the
+    subchain unfolding (see include/trd.h)."""
+    lib = load()
+    N = len(dims)
+    out = torch.empty(int(J), dtype=torch.int64, device=device)
+    d = (C.c_int64 * N)(*[int(v) for v in dims])
+    _check(lib.trd_sample_rows(int(seed), int(t), int(k), N, d, int(J), C.c_void_p(out.data_ptr()),
+                               C.c_void_p(_stream())))
+    return out
 
 
 class Problem:
@@ -371,10 +386,12 @@ class Problem:
         code = PRECISIONS[precision]
         _check(load().trd_set_precision(self._ctx, code), self._ctx)
 
-    def set_variant(self, direction: str = "scaled", gram: str = "global"):
+    def set_variant(self, direction: str = "scaled", gram: str = "global", sampling: str = "rsts"):
         """Update variants of the Sec. 6.1 ablations: direction 'scaled' | 'gradient',
-        gram 'global' | 'local' (the sampled cores' Gram under a sketch)."""
-        _check(load().trd_set_variant(self._ctx, DIRECTIONS[direction], GRAMS[gram]), self._ctx)
+        gram 'global' | 'local' (the sampled cores' Gram under a sketch), sampling 'rsts' |
+        'rows' (a sketch draws uniform rows of the subchain unfolding instead)."""
+        _check(load().trd_set_variant(self._ctx, DIRECTIONS[direction], GRAMS[gram], SAMPLINGS[sampling]),
+               self._ctx)
 
     def profile(self, enable: bool):
         _check(load().trd_profile(self._ctx, 1 if enable else 0), self._ctx)

@@ -352,6 +352,42 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- uniform row sampling
+// J rows of the subchain unfolding of core k, drawn independently and uniformly with
+// replacement: sample n takes index bounded(u(key_j, n), 0, I_j) of every mode j != k, with
+// key_j = u(u(u(seed ^ "UROW", t), k), j), and u(key, c) the counter form of SplitMix64.
+// Out: the tensor offset of the sampled mode-k fibre (at i_k = 0) and/or the row index
+// (little-endian over the cyclic modes k+1, ..., k-1).
+
+struct RowSampleArgs {
+  uint64_t seed;
+  int t, k, N;
+  int64_t dims[kMaxN];
+  int64_t strides[kMaxN];
+  int64_t J;
+  int64_t* off;
+  int64_t* row;
+};
+
+__global__ __launch_bounds__(256) void k_sample_rows(RowSampleArgs a) {
+  const uint64_t base = counter_u64(counter_u64(a.seed ^ 0x55524F5700000000ull, (uint64_t)a.t), (uint64_t)a.k);
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.J;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    int64_t off = 0, row = 0, rs = 1;
+    for (int s = 1; s < a.N; ++s) {
+      const int j = (a.k + s) % a.N;
+      uint64_t ctr = 0;
+      const int64_t i = (int64_t)bounded(counter_u64(counter_u64(base, (uint64_t)j), (uint64_t)n), &ctr,
+                                         (uint64_t)a.dims[j]);
+      off += i * a.strides[j];
+      row += i * rs;
+      rs *= a.dims[j];
+    }
+    if (a.off) a.off[n] = off;
+    if (a.row) a.row[n] = row;
+  }
+}
+
 // ---------------------------------------------------------------- masks and outliers
 // Per-entry (or per-tile) Bernoulli draws from the same counter generator: an event of
 // probability p happens when the draw is below floor(p 2^64) (integer compare; p >= 1:
@@ -433,6 +469,22 @@ hipError_t launch_sample_mask(uint64_t seed, int N, const int64_t* dims, double 
   if (a.n <= 0) return hipSuccess;
   const int64_t g = std::min<int64_t>((a.n + 255) / 256, (int64_t)g_num_cu * 64);
   hipLaunchKernelGGL(k_sample_mask, dim3((unsigned)g), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_rows(uint64_t seed, int t, int k, int N, const int64_t* dims, int64_t J,
+                              int64_t* off, int64_t* row, hipStream_t st) {
+  if (J <= 0) return hipSuccess;
+  RowSampleArgs a;
+  a.seed = seed; a.t = t; a.k = k; a.N = N; a.J = J; a.off = off; a.row = row;
+  int64_t stride = 1;
+  for (int j = 0; j < kMaxN; ++j) {
+    a.dims[j] = j < N ? dims[j] : 1;
+    a.strides[j] = stride;
+    if (j < N) stride *= dims[j];
+  }
+  const int64_t blocks = std::min<int64_t>((J + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_sample_rows, dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

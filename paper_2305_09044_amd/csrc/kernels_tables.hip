@@ -337,6 +337,93 @@ __global__ void k_pack(const real* __restrict__ in, int64_t is, const int32_t* _
   }
 }
 
+// ---------------------------------------------------------------- sampled-fibre chains
+// Column table of a uniform row sample: every sampled column n carries its own multi-index,
+// so the product of the N - 1 slices is formed per column (no shared partial products).
+// One thread per (column, row a of the product): the row vector is carried through the
+// chain in registers (ranks <= 16) and written in the transposed table layout.
+
+struct ChainArgs {
+  const void* cores[kMaxN];
+  int ranks[kMaxN];
+  int64_t dims[kMaxN], strides[kMaxN];
+  int N, k;
+  const int64_t* off;
+  int64_t J;
+  void* out;
+  int64_t out_stride;
+};
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_chain_cols(ChainArgs a) {
+  const int N = a.N, k = a.k;
+  const int m0 = (k + 1) % N;
+  const int rs = a.ranks[m0], rk = a.ranks[k];
+  const int64_t total = a.J * rs;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = t / rs;
+    const int ar = (int)(t - n * rs);
+    const int64_t off = a.off[n];
+    real v[kMaxRank], w[kMaxRank];
+    {  // row ar of the first slice Z_{k+1}(i_{k+1})
+      const int r0 = rs, r1 = a.ranks[(m0 + 1) % N];
+      const int64_t i = (off / a.strides[m0]) % a.dims[m0];
+      const real* Z = (const real*)a.cores[m0] + i * (int64_t)r0 * r1;
+#pragma unroll
+      for (int c = 0; c < kMaxRank; ++c) v[c] = c < r1 ? Z[ar + r0 * c] : real(0);
+    }
+    for (int s = 2; s < N; ++s) {  // times Z_m(i_m), m = k+2, ..., k-1
+      const int m = (k + s) % N;
+      const int r0 = a.ranks[m], r1 = a.ranks[(m + 1) % N];
+      const int64_t i = (off / a.strides[m]) % a.dims[m];
+      const real* Z = (const real*)a.cores[m] + i * (int64_t)r0 * r1;
+#pragma unroll
+      for (int c = 0; c < kMaxRank; ++c) {
+        real acc = real(0);
+#pragma unroll
+        for (int b = 0; b < kMaxRank; ++b)
+          if (b < r0 && c < r1) acc = fma(v[b], Z[b + r0 * c], acc);
+        w[c] = acc;
+      }
+#pragma unroll
+      for (int c = 0; c < kMaxRank; ++c) v[c] = w[c];
+    }
+    real* o = (real*)a.out + n * a.out_stride;
+#pragma unroll
+    for (int c = 0; c < kMaxRank; ++c)
+      if (c < rk) o[ar * rk + c] = v[c];
+    if (ar == rs - 1)
+      for (int64_t e = (int64_t)rs * rk; e < a.out_stride; ++e) o[e] = real(0);
+  }
+}
+
+hipError_t launch_chain_cols(int dtype, const void* const* cores, int N, int k, const int32_t* ranks,
+                             const int64_t* dims, const int64_t* strides, const int64_t* off,
+                             int64_t J, void* out, int64_t out_stride, hipStream_t st) {
+  if (J <= 0) return hipSuccess;
+  ChainArgs a;
+  for (int j = 0; j < kMaxN; ++j) {
+    a.cores[j] = j < N ? cores[j] : nullptr;
+    a.ranks[j] = j < N ? ranks[j] : 1;
+    a.dims[j] = j < N ? dims[j] : 1;
+    a.strides[j] = j < N ? strides[j] : 1;
+  }
+  a.N = N;
+  a.k = k;
+  a.off = off;
+  a.J = J;
+  a.out = out;
+  a.out_stride = out_stride;
+  const int64_t total = J * ranks[(k + 1) % N];
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65535);
+  if (dtype != 0)  // FP64
+    hipLaunchKernelGGL(k_chain_cols<double>, dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_chain_cols<float>, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* out,
                        int64_t out_stride, int transpose_out, hipStream_t st, bool bf16_out,
                        void* out_lo) {

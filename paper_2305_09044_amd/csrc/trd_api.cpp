@@ -59,6 +59,7 @@ struct trd_ctx {
   int prec = TRD_PREC_NATIVE;     // precision of the entry passes
   int direction = TRD_DIR_SCALED;  // step direction and Gram of later updates
   int gram = TRD_GRAM_GLOBAL;
+  int sampling = TRD_SAMPLE_RSTS;  // how a sketch picks its rows
   uint16_t* Tb = nullptr; uint16_t* THb = nullptr; uint16_t* Vb = nullptr;
   uint16_t* Tb_lo = nullptr; uint16_t* Vb_lo = nullptr;  // split (BF16X3) remainders
   // Vb (and Vb_lo) in operand-fragment order, and Vb transposed in fragment order
@@ -258,10 +259,11 @@ ModeSet cols_set(trd_ctx* ctx, const Split& sp, const int64_t* counts, const int
 }
 
 // count -> slices -> scan (-> fill when vals/cols are in place)
+// cols_given: L.coloff already holds the column offsets (a uniform row sample)
 int build_layout_head(trd_ctx* ctx, const Split& sp, const int64_t* counts,
-                      const int32_t* const* lists, Layout& L, hipStream_t st) {
+                      const int32_t* const* lists, Layout& L, hipStream_t st, bool cols_given = false) {
   CK(launch_offsets(rows_set(ctx, sp, counts, lists), L.nrows, L.rowoff, st));
-  CK(launch_offsets(cols_set(ctx, sp, counts, lists), L.ncols, L.coloff, st));
+  if (!cols_given) CK(launch_offsets(cols_set(ctx, sp, counts, lists), L.ncols, L.coloff, st));
   CK(launch_zero(L.nobs_dev, sizeof(int64_t), st));
   CK(launch_count(L, ctx->mask, st));
   CK(launch_slices(L, st));
@@ -353,12 +355,17 @@ struct Update {
   TLayout* TL = nullptr;                  // non-null: matrix-core (BF16) passes
   const int64_t* counts = nullptr;        // per-mode counts of this update
   const int32_t* const* lists = nullptr;  // per-mode device lists (nullptr = full)
+  bool rows = false;                      // uniform row sample: columns = sampled fibres
   int64_t cnt[kMaxN];
   const int32_t* lst[kMaxN];
 };
 
+int sketch_layout(trd_ctx* ctx, int k, int64_t nrows, int64_t ncols, int ct_w, int n_ct);
+int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st);
+
 // sample the sketch of update (t, k) and build its layout into the sketch workspace
 int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
+  if (ctx->sampling == TRD_SAMPLE_ROWS) return prepare_rows(ctx, k, sk, up, st);
   const int N = ctx->N;
   SketchWS& W = ctx->sk;
   for (int j = 0; j < N; ++j) {
@@ -386,6 +393,19 @@ int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStr
   int64_t nrows, ncols;
   int ct_w, n_ct;
   TRY(plan_split(ctx, k, up.cnt, up.sp, nrows, ncols, ct_w, n_ct));
+  TRY(sketch_layout(ctx, k, nrows, ncols, ct_w, n_ct));
+  Layout& L = W.L;
+  up.counts = up.cnt;
+  up.lists = up.lst;
+  up.L = &L;
+  TRY(build_layout_head(ctx, up.sp, up.cnt, up.lst, L, st));
+  CK(launch_fill(L, ctx->mask, ctx->X, ctx->dtype, st));
+  return TRD_OK;
+}
+
+// the sketch workspace's layout, sized for an nrows x ncols update (grown, never shrunk)
+int sketch_layout(trd_ctx* ctx, int k, int64_t nrows, int64_t ncols, int ct_w, int n_ct) {
+  SketchWS& W = ctx->sk;
   Layout& L = W.L;
   layout_dims(L, nrows, ncols, ct_w, n_ct);
   const int64_t need_counts = (int64_t)n_ct * L.n_rg * kRowsPerWG;
@@ -410,10 +430,44 @@ int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStr
   L.slots_cap = W.cap_slots;
   L.slots = need_slots;  // upper bound; the device holds the exact value
   L.k = k;
+  return TRD_OK;
+}
+
+// uniform row sampling (the ablation of Sec. 6.1 that replaces RStS): as many rows of the
+// subchain unfolding as the sketch of these sizes holds, drawn independently and uniformly
+// with replacement; the update's matrix has the I_k rows of core k and one column per sample
+int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
+  const int N = ctx->N;
+  if (sk->idx) return fail(ctx, TRD_EINVAL, "caller index lists are RStS sets: not with uniform row sampling");
+  int64_t J = 1;
+  for (int j = 0; j < N; ++j) {
+    up.cnt[j] = ctx->dims[j];
+    up.lst[j] = nullptr;
+    if (j != k) J *= std::min<int64_t>(std::max(1, sk->sizes[j]), ctx->dims[j]);
+  }
+  if (J > (int64_t)1 << 31) return fail(ctx, TRD_EUNSUPPORTED, "uniform row sample above 2^31 rows");
+  Split& sp = up.sp;
+  sp.k = k;
+  sp.p = 0;
+  sp.q = N - 1;
+  for (int t = 1; t <= N - 1; ++t) sp.C[t - 1] = (k + t) % N;
+  sp.r_k = ctx->ranks[k];
+  sp.r_k1 = ctx->ranks[(k + 1) % N];
+  sp.r_s = sp.r_k1;
+  sp.RR = sp.r_k * sp.r_s;
+  sp.RRP = pass_rrp(sp.RR);
+  if (sp.RRP < 0) return fail(ctx, TRD_EUNSUPPORTED, "r_k * r_{k+1} above the pass width");
+  const int64_t wmax = pass_ct_w(ctx->dtype, 0, sp.RRP);
+  const int n_ct = (int)((J + wmax - 1) / wmax);
+  const int ct_w = (int)((J + n_ct - 1) / n_ct);
+  TRY(sketch_layout(ctx, k, ctx->dims[k], J, ct_w, n_ct));
+  Layout& L = ctx->sk.L;
   up.counts = up.cnt;
   up.lists = up.lst;
+  up.rows = true;
   up.L = &L;
-  TRY(build_layout_head(ctx, up.sp, up.cnt, up.lst, L, st));
+  CK(launch_sample_rows(sk->seed, sk->sweep, k, N, ctx->dims, J, L.coloff, nullptr, st));
+  TRY(build_layout_head(ctx, sp, up.cnt, nullptr, L, st, true));
   CK(launch_fill(L, ctx->mask, ctx->X, ctx->dtype, st));
   return TRD_OK;
 }
@@ -591,6 +645,11 @@ int fragment_coltable(trd_ctx* ctx, const Update& up, hipStream_t st) {
 int build_coltable(trd_ctx* ctx, const Update& up, const void* const* cores, hipStream_t st) {
   const Split& sp = up.sp;
   const int N = ctx->N;
+  if (up.rows) {  // one chain per sampled fibre (ELL passes only)
+    CK(launch_chain_cols(ctx->dtype, cores, N, sp.k, ctx->ranks, ctx->dims, ctx->strides, up.L->coloff,
+                         up.L->ncols, ctx->V, sp.RRP, st));
+    return TRD_OK;
+  }
   const int m0 = sp.C[0];
   ItemRef L = core_ref(ctx, cores[m0], m0, up.lists);
   int64_t nL = up.counts[m0];
@@ -893,6 +952,8 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
   // from the global one only under a sketch
   const bool scaled = ctx->direction == TRD_DIR_SCALED;
   const bool local = scaled && ctx->gram == TRD_GRAM_LOCAL && sk;
+  if (local && up.rows)
+    return fail(ctx, TRD_EUNSUPPORTED, "the local Gram matrix needs RStS index sets, not a row sample");
   if (scaled) {
     // G (eq. 13) and (G + lambda I)^{-1} need only the factors of the other cores: on the
     // side stream, after everything queued so far, while the gradient runs here
@@ -1551,6 +1612,23 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
   return TRD_OK;
 }
 
+int trd_sample_rows(uint64_t seed, int t, int k, int N, const int64_t* dims, int64_t J, int64_t* rows_out,
+                    void* stream) {
+  trd_ctx* ctx = nullptr;
+  if (N < 2 || N > kMaxN) return fail(nullptr, TRD_EINVAL, "N must be in [2, 8]");
+  if (!dims || (!rows_out && J > 0)) return fail(nullptr, TRD_EINVAL, "NULL argument");
+  if (k < 0 || k >= N) return fail(nullptr, TRD_EINVAL, "k out of range");
+  if (J < 0) return fail(nullptr, TRD_EINVAL, "J must be >= 0");
+  double M = 1.0;
+  for (int j = 0; j < N; ++j) {
+    if (dims[j] < 1 || dims[j] > 0x7FFFFFFF) return fail(nullptr, TRD_EINVAL, "bad dims");
+    if (j != k) M *= (double)dims[j];
+  }
+  if (M >= 4.6e18) return fail(nullptr, TRD_EUNSUPPORTED, "row count must be < 2^62");
+  CK(launch_sample_rows(seed, t, k, N, dims, J, nullptr, rows_out, (hipStream_t)stream));
+  return TRD_OK;
+}
+
 int trd_sample_mask(uint64_t seed, int N, const int64_t* dims, double rho, int block,
                     double outlier_frac, uint8_t* mask_out, uint8_t* outlier_out, double* u_out,
                     void* stream) {
@@ -1582,13 +1660,17 @@ int trd_set_precision(trd_ctx* ctx, int precision) {
   return TRD_OK;
 }
 
-int trd_set_variant(trd_ctx* ctx, int direction, int gram) {
+int trd_set_variant(trd_ctx* ctx, int direction, int gram, int sampling) {
   if (!ctx) return fail(nullptr, TRD_EINVAL, "null context");
   if (direction != TRD_DIR_SCALED && direction != TRD_DIR_GRADIENT)
     return fail(ctx, TRD_EINVAL, "unknown direction");
   if (gram != TRD_GRAM_GLOBAL && gram != TRD_GRAM_LOCAL) return fail(ctx, TRD_EINVAL, "unknown gram");
+  if (sampling != TRD_SAMPLE_RSTS && sampling != TRD_SAMPLE_ROWS) return fail(ctx, TRD_EINVAL, "unknown sampling");
+  if (gram == TRD_GRAM_LOCAL && sampling == TRD_SAMPLE_ROWS && direction == TRD_DIR_SCALED)
+    return fail(ctx, TRD_EUNSUPPORTED, "the local Gram matrix needs RStS index sets, not a row sample");
   ctx->direction = direction;
   ctx->gram = gram;
+  ctx->sampling = sampling;
   return TRD_OK;
 }
 

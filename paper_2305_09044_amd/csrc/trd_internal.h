@@ -121,6 +121,11 @@ hipError_t launch_fill(const Layout& L, const uint8_t* mask, const void* X, int 
                        hipStream_t st);
 hipError_t launch_sample(uint64_t seed, int t, int k, int N, const int64_t* dims,
                          const int32_t* sizes, int32_t* const* out, hipStream_t st);
+// uniform row sample of core k (J rows of the subchain unfolding, with replacement):
+// column-major tensor offsets of the sampled fibres (i_k = 0) and/or row indices (either
+// may be nullptr)
+hipError_t launch_sample_rows(uint64_t seed, int t, int k, int N, const int64_t* dims, int64_t J,
+                              int64_t* off, int64_t* row, hipStream_t st);
 // mask (Bernoulli rho per entry, or per block x block tile of modes 0-1 at each index of
 // modes 3.., shared by mode 2), outlier selection (observed and Bernoulli frac) and per-entry
 // uniforms; sel and u may be nullptr
@@ -138,6 +143,12 @@ hipError_t launch_accum_i64(int64_t* dst, const int64_t* src, hipStream_t st);
 hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRef R, int64_t nR,
                         int rC, void* out, int64_t out_stride, int transpose_out, hipStream_t st,
                         bool bf16_out = false, void* out_lo = nullptr);
+// column table of sampled fibres: for each column n (tensor offset off[n], i_k = 0) the
+// product Z_{k+1}(i_{k+1}) ... Z_{k-1}(i_{k-1}) (r_{k+1} x r_k), stored transposed
+// (element (a, c) at a * r_k + c) and zero-padded to out_stride
+hipError_t launch_chain_cols(int dtype, const void* const* cores, int N, int k, const int32_t* ranks,
+                             const int64_t* dims, const int64_t* strides, const int64_t* off,
+                             int64_t J, void* out, int64_t out_stride, hipStream_t st);
 hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* out,
                        int64_t out_stride, int transpose_out, hipStream_t st,
                        bool bf16_out = false, void* out_lo = nullptr);

@@ -108,7 +108,7 @@ def test_context_calls_reject_null_context():
     assert lib.trd_fit(None, None, None, None, None) == _lib.TRD_EINVAL
     assert lib.trd_profile(None, 1) == _lib.TRD_EINVAL
     assert lib.trd_set_precision(None, 0) == _lib.TRD_EINVAL
-    assert lib.trd_set_variant(None, 0, 0) == _lib.TRD_EINVAL
+    assert lib.trd_set_variant(None, 0, 0, 0) == _lib.TRD_EINVAL
     lib.trd_destroy(None)  # ignored
 
 

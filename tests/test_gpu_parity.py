@@ -197,8 +197,8 @@ def test_local_gram_without_sketch_is_the_method():
         prob.step(b, k, 0.9)
         assert torch.equal(a[k], b[k])
     lib = trd._lib.load()
-    assert lib.trd_set_variant(prob._ctx, 2, 0) == -1   # TRD_EINVAL
-    assert lib.trd_set_variant(prob._ctx, 0, 2) == -1
+    assert lib.trd_set_variant(prob._ctx, 2, 0, 0) == -1   # TRD_EINVAL
+    assert lib.trd_set_variant(prob._ctx, 0, 2, 0) == -1
 
 
 @pytest.mark.parametrize("direction,gram", [("gradient", "global"), ("scaled", "local")])

@@ -1,0 +1,111 @@
+"""The uniform-row-sampling ablation of Sec. 6.1 on the GPU against the oracle.
+
+Under TRD_SAMPLE_ROWS a sketch of sizes s_j draws J = prod_{j != k} min(s_j, I_j) rows of
+the subchain unfolding uniformly with replacement; the update works on the mode-k fibres
+at those rows.  The drawn rows are compared bit for bit with the oracle's generator; the
+step, gradient and fit with the oracle's row-sampled update on the same rows.  Bars as for
+the RStS path: FP32 1e-5 per step (relative Frobenius), FP64 1e-10, FP32 fits 1e-4."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import awrtrd as aw  # noqa: E402
+from oracle import rng as orng  # noqa: E402
+from oracle import tr  # noqa: E402
+import paper_2305_09044_amd as trd  # noqa: E402
+from _helpers import device_cores, device_problem, host_cores, host_problem, rel, unflatten_d  # noqa: E402
+
+F32, F64 = np.float32, np.float64
+TOL = {F32: 1e-5, F64: 1e-10}
+
+
+def _J(dims, sizes, k):
+    J = 1
+    for j, (I, s) in enumerate(zip(dims, sizes)):
+        if j != k:
+            J *= min(max(1, s), I)
+    return J
+
+
+@pytest.mark.parametrize("seed,t,dims,J", [(0, 0, (60, 50, 40, 30), 1000), (42, 3, (9, 10, 11, 8, 7), 625),
+                                           (7, 1, (300, 257), 77), (3, 2, (60,) * 5, 20000),
+                                           (5, 0, (2, 3, 1, 4), 1)])
+def test_sample_rows_bit_exact(seed, t, dims, J):
+    for k in range(len(dims)):
+        got = trd.trd_sample_rows(seed, t, k, dims, J).cpu().numpy()
+        np.testing.assert_array_equal(got, orng.uniform_rows(seed, t, k, dims, J))
+    assert trd.trd_sample_rows(seed, t, 0, dims, 0).numel() == 0
+
+
+SHAPES = [((60, 50, 40, 30), (3, 4, 3, 2), (12, 9, 17, 8)),
+          ((70, 60, 50), (5, 5, 5), (60, 55, 45)),          # 2475+ columns: several column tiles
+          ((300, 257), (4, 3), (100, 120)),
+          ((9, 10, 11, 8, 7), (2, 2, 3, 2, 2), (5, 5, 5, 5, 5))]
+
+
+@pytest.mark.parametrize("dims,ranks,sizes", SHAPES)
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_rows_step_and_grad_match_oracle(dims, ranks, sizes, dtype):
+    X, P, Z0, _, _ = host_problem(dims, ranks, 0.4, 0, dtype, reconstruct=tr.reconstruct)
+    prob = device_problem(X, P, dims, ranks, dtype)
+    prob.set_variant("scaled", "global", "rows")
+    sigma, seed, t = 0.9, 11, 2
+    for k in range(len(dims)):
+        rows = orng.uniform_rows(seed, t, k, dims, _J(dims, sizes, k))
+        ref, info = aw.core_update(X, P, Z0, k, sigma, 1e-9, rows=rows)
+        sk, _ = trd.make_sketch(sizes, seed, t)
+        d, stats = prob.grad(device_cores(Z0, dtype), k, sigma, sketch=sk)
+        got_d = unflatten_d(d.cpu().numpy(), ranks[k], dims[k], ranks[(k + 1) % len(dims)])
+        assert rel(got_d, info.d) <= 3 * TOL[dtype], (k, rel(got_d, info.d))
+        assert stats[2].item() == info.n_obs
+        cores = device_cores(Z0, dtype)
+        eta, flags = prob.step(cores, k, sigma, 1e-9, sketch=sk)
+        got = host_cores(cores, dims, ranks)
+        assert int(flags) == 0
+        assert rel(got[k], ref) <= TOL[dtype], (k, rel(got[k], ref))
+        assert float(eta) == pytest.approx(info.eta, rel=1e-4 if dtype == F32 else 1e-9)
+
+
+@pytest.mark.parametrize("dtype,mode", [(F64, "quantile"), (F32, "given")])
+def test_rows_fit_matches_oracle(dtype, mode):
+    dims, ranks = (40, 36, 30, 24), (3, 3, 2, 2)
+    X, P, Z0, _, _ = host_problem(dims, ranks, 0.5, 1, dtype, reconstruct=tr.reconstruct)
+    prob = device_problem(X, P, dims, ranks, dtype)
+    prob.set_variant("scaled", "global", "rows")
+    sizes, seed, sig = (10, 8, 9, 7), 7, [2.0, 1.2, 0.9]
+    kw = dict(sigma_mode="given", sigma_given=sig) if mode == "given" else {}
+    cores = device_cores(Z0, dtype)
+    rep = prob.fit(cores, max_sweeps=3, tol=0.0, sketch_sizes=sizes, seed=seed, **kw)
+    ref, hist = aw.fit(X, P, Z0, aw.FitOptions(max_sweeps=3, tol=0.0, sketch_sizes=sizes, seed=seed,
+                                               sampling="rows", **kw))
+    got = host_cores(cores, dims, ranks)
+    err = max(rel(g, r) for g, r in zip(got, ref))
+    # the library selects the quantile on the FP32 bit patterns of |e| (FP64 problems too),
+    # so a quantile width differs from the oracle's by up to 2^-24 relative, and the cores
+    # by what that does to the weights over three sweeps
+    print(f"{mode} fit, {np.dtype(dtype).name}: core error {err:.2e}, widths {rep['sigma']} vs {hist['sigma']}")
+    assert err <= (1e-5 if mode == "quantile" else 1e-4), err
+    for a, b in zip(rep["sigma"], hist["sigma"]):
+        assert a == pytest.approx(b, rel=1e-6)
+    assert rep["flags"] == 0
+
+
+def test_rows_variant_rejections():
+    dims, ranks = (20, 18, 16), (2, 2, 2)
+    X, P, Z0, _, _ = host_problem(dims, ranks, 0.5, 2, F32, reconstruct=tr.reconstruct)
+    prob = device_problem(X, P, dims, ranks, F32)
+    with pytest.raises(trd.TrdError):     # the local Gram needs RStS index sets
+        prob.set_variant("scaled", "local", "rows")
+    prob.set_variant("gradient", "local", "rows")   # the gradient direction forms no Gram
+    prob.set_variant("scaled", "global", "rows")
+    idx = [None if j == 0 else torch.arange(4, dtype=torch.int32, device="cuda") for j in range(3)]
+    sk, keep = trd.make_sketch((4, 4, 4), 0, 0, idx)
+    with pytest.raises(trd.TrdError):     # caller lists are RStS sets
+        prob.step(device_cores(Z0, F32), 0, 1.0, sketch=sk)
+    lib = trd._lib.load()
+    assert lib.trd_set_variant(prob._ctx, 0, 0, 2) == -1   # TRD_EINVAL
