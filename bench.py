@@ -234,15 +234,18 @@ def equal_accuracy_seeds(wname, seeds, sweeps):
     return summary
 
 
-ABLATION_VARIANTS = (("method", "scaled", "global"), ("gradient descent", "gradient", "global"),
-                     ("local scaled term", "scaled", "local"))
+ABLATION_VARIANTS = (("method", "scaled", "global", "rsts"), ("gradient descent", "gradient", "global", "rsts"),
+                     ("local scaled term", "scaled", "local", "rsts"),
+                     ("uniform row sampling", "scaled", "global", "rows"))
 
 
 def ablation(prob, Z0_flat, xstar_d, dims, sizes, sweeps, seed=0, n_sample=1 << 20):
-    """The ablations of Sec. 6.1 on the RStS path: the method, the plain gradient direction
-    and the local scaled term, each fitted for `sweeps` sweeps from the same start with the
-    same sketches, for several per-mode sample sizes s (J = s^(N-1) sampled columns per
-    update); recovery error over a fixed uniform sample of entries, and the fit's time."""
+    """The ablations of Sec. 6.1 on the sketched path: the method, the plain gradient
+    direction, the local scaled term (each with the same RStS sketches) and uniform row
+    sampling (as many rows of the subchain unfolding, drawn i.i.d.), each fitted for
+    `sweeps` sweeps from the same start, for several per-mode sample sizes s (J = s^(N-1)
+    sampled rows per update); recovery error over a fixed uniform sample of entries, and
+    the fit's time."""
     import torch
     g = torch.Generator(device="cpu").manual_seed(seed)
     n = xstar_d.numel()
@@ -250,8 +253,8 @@ def ablation(prob, Z0_flat, xstar_d, dims, sizes, sweeps, seed=0, n_sample=1 << 
     rows = []
     for s in sizes:
         sk = [min(s, d) for d in dims]
-        for name, direction, gram in ABLATION_VARIANTS:
-            prob.set_variant(direction, gram)
+        for name, direction, gram, sampling in ABLATION_VARIANTS:
+            prob.set_variant(direction, gram, sampling)
             prob.fit([z.clone() for z in Z0_flat], max_sweeps=1, tol=0.0, sketch_sizes=sk, seed=seed)
             cores = [z.clone() for z in Z0_flat]
             torch.cuda.synchronize()
@@ -262,7 +265,7 @@ def ablation(prob, Z0_flat, xstar_d, dims, sizes, sweeps, seed=0, n_sample=1 << 
             rows.append({"variant": name, "s": s, "J": math.prod(sk[1:]), "ms": round(dt * 1e3, 3),
                          "rel_error": recovery_error(prob, cores, xstar_d, idx)})
             log(f"ablation {name} s={s}: {dt * 1e3:.1f} ms, rel. error {rows[-1]['rel_error']:.4g}")
-    prob.set_variant("scaled", "global")
+    prob.set_variant("scaled", "global", "rsts")
     return {"sweeps": sweeps, "rows": rows}
 
 

@@ -303,12 +303,14 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 __device__ __forceinline__ uint64_t counter_u64(uint64_t key, uint64_t c) {
   return mix64(key + (c + 1ull) * 0x9E3779B97F4A7C15ull);
 }
+// n in [1, 2^31): the rejection threshold (2^32 - n) mod n in 32-bit arithmetic
 __device__ uint64_t bounded(uint64_t key, uint64_t* ctr, uint64_t n) {
-  const uint64_t threshold = ((1ull << 32) - n) % n;
+  const uint32_t n32 = (uint32_t)n;
+  const uint32_t threshold = (0u - n32) % n32;
   for (;;) {
-    uint64_t x = counter_u64(key, (*ctr)++) >> 32;
-    uint64_t m = x * n;
-    if ((m & 0xFFFFFFFFull) >= threshold) return m >> 32;
+    const uint32_t x = (uint32_t)(counter_u64(key, (*ctr)++) >> 32);
+    const uint64_t m = (uint64_t)x * n32;
+    if ((uint32_t)m >= threshold) return m >> 32;
   }
 }
 
@@ -320,7 +322,16 @@ struct SampleArgs {
   int32_t* out[kMaxN];
 };
 
+// Floyd's subset for mode j of one update per block.  For I_j up to kSampleBits the chosen
+// set is a bitmap in LDS (membership in O(1), set by thread 0 in Floyd's order), and the
+// sorted list is written by the whole block from the bitmap: word counts, a block scan,
+// then each thread's bits in order.  Larger modes keep the sorted list in global memory.
+constexpr int kSampleWords = 8192;                 // 32 KiB of LDS
+constexpr int64_t kSampleBits = 32 * (int64_t)kSampleWords;
+
 __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
+  __shared__ uint32_t bits[kSampleWords];
+  __shared__ int32_t part[4];  // per-wave totals of the 256-thread block
   const int j = blockIdx.x;
   const int64_t n = a.dims[j];
   int32_t* o = a.out[j];
@@ -328,11 +339,51 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) o[i] = (int32_t)i;
     return;
   }
-  if (threadIdx.x != 0) return;
   const int64_t s = a.sizes[j];
   uint64_t key = counter_u64(a.seed ^ 0x5253545300000000ull, (uint64_t)a.t);
   key = counter_u64(key, (uint64_t)a.k);
   key = counter_u64(key, (uint64_t)j);
+  if (n <= kSampleBits) {
+    const int nw = (int)((n + 31) / 32);
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) bits[w] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t ctr = 0;
+      for (int64_t jj = n - s; jj < n; ++jj) {
+        const int64_t tv = (int64_t)bounded(key, &ctr, (uint64_t)(jj + 1));
+        const bool taken = (bits[tv >> 5] >> (tv & 31)) & 1u;
+        const int64_t v = taken ? jj : tv;  // jj itself is never taken yet
+        bits[v >> 5] |= 1u << (v & 31);
+      }
+    }
+    __syncthreads();
+    // each thread owns a contiguous run of words: count, exclusive scan, write in order
+    const int per = (nw + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int w0 = min(nw, (int)threadIdx.x * per), w1 = min(nw, w0 + per);
+    int cnt = 0;
+    for (int w = w0; w < w1; ++w) cnt += __popc(bits[w]);
+    // exclusive block scan: inclusive within each wave by shuffles, then the wave totals
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int inc = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(inc, o);
+      if (lane >= o) inc += v;
+    }
+    if (lane == 63) part[wv] = inc;
+    __syncthreads();
+    int pos = inc - cnt;
+    for (int i = 0; i < wv; ++i) pos += part[i];
+    for (int w = w0; w < w1; ++w) {
+      uint32_t b = bits[w];
+      while (b) {
+        const int q = __ffs(b) - 1;
+        o[pos++] = w * 32 + q;
+        b &= b - 1u;
+      }
+    }
+    return;
+  }
+  if (threadIdx.x != 0) return;
   uint64_t ctr = 0;
   int64_t m = 0;  // current size of the sorted set in o[0..m)
   for (int64_t jj = n - s; jj < n; ++jj) {

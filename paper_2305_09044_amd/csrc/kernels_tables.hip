@@ -445,7 +445,13 @@ hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* o
 }
 
 // S[0][t] = sum over the column-group partials c of S[c][t], fixed order, in place; four
-// elements per thread (n is a multiple of 4: rows of RRP, RRP a multiple of 4)
+// elements per thread (n is a multiple of 4: rows of RRP, RRP a multiple of 4).
+// Many partials of a short S (small, sketched updates): the partials are split over the
+// kSumLanes threads of an element group, each summing c = lane, lane + kSumLanes, ... in
+// order, then combined by a fixed tree in LDS; the threads of a group read different
+// partials, so the loads of one element are in flight together.
+constexpr int kSumLanes = 16;
+
 template <typename real>
 __global__ __launch_bounds__(256) void k_sum_partials(real* __restrict__ S, int n_ct, int64_t n) {
   using V4 = typename std::conditional<sizeof(real) == 4, float4, double4>::type;
@@ -462,10 +468,48 @@ __global__ __launch_bounds__(256) void k_sum_partials(real* __restrict__ S, int 
   }
 }
 
+template <typename real>
+__global__ __launch_bounds__(256) void k_sum_partials_split(real* __restrict__ S, int n_ct, int64_t n) {
+  using V4 = typename std::conditional<sizeof(real) == 4, float4, double4>::type;
+  __shared__ V4 red[256];
+  const int64_t n4 = n / 4;
+  const int lane = threadIdx.x % kSumLanes;
+  const int64_t t = blockIdx.x * (int64_t)(256 / kSumLanes) + threadIdx.x / kSumLanes;
+  V4 acc;
+  acc.x = acc.y = acc.z = acc.w = real(0);
+  if (t < n4)
+    for (int c = lane; c < n_ct; c += kSumLanes) {
+      const V4 v = reinterpret_cast<const V4*>(S + (int64_t)c * n)[t];
+      acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+    }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = kSumLanes / 2; o > 0; o >>= 1) {
+    if (lane < o) {
+      V4 a = red[threadIdx.x];
+      const V4 b = red[threadIdx.x + o];
+      a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
+      red[threadIdx.x] = a;
+    }
+    __syncthreads();
+  }
+  if (lane == 0 && t < n4) reinterpret_cast<V4*>(S)[t] = red[threadIdx.x];
+}
+
 hipError_t launch_sum_partials(int dtype, void* S, int n_ct, int64_t n, hipStream_t st) {
   if (n_ct <= 1 || n <= 0) return hipSuccess;
   if (n % 4 != 0) return hipErrorInvalidValue;
-  dim3 g(grid_for(n / 4, 256, 8192)), b(256);
+  dim3 b(256);
+  // too few float4 elements to fill the device one per thread: split the partials
+  if (n / 4 < 64 * 1024 && n_ct >= 2 * kSumLanes) {
+    dim3 g((unsigned)((n / 4 + (256 / kSumLanes) - 1) / (256 / kSumLanes)));
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_sum_partials_split<float>, g, b, 0, st, (float*)S, n_ct, n);
+    else
+      hipLaunchKernelGGL(k_sum_partials_split<double>, g, b, 0, st, (double*)S, n_ct, n);
+    return hipGetLastError();
+  }
+  dim3 g(grid_for(n / 4, 256, 8192));
   if (dtype == 0)
     hipLaunchKernelGGL(k_sum_partials<float>, g, b, 0, st, (float*)S, n_ct, n);
   else

@@ -168,11 +168,28 @@ size_t esz(int dtype) { return dtype == 0 ? 4 : 8; }
 // ---------------------------------------------------------------- planning
 
 // counts[j]: indices of mode j taking part (I_j on the full path, s_j in a sketch).
+// Column tiles of an nr x nc update: as wide as the LDS allows, or, for a small update
+// (fill_rho >= 0, the observed density), narrower (down to 64 columns) until the row
+// groups times the tiles reach the work-group target, so the whole device takes part.
+int64_t plan_tiles(int64_t nr, int64_t nc, int64_t wmax, double fill_rho) {
+  int64_t nct = (nc + wmax - 1) / wmax;
+  if (fill_rho >= 0) {
+    const int64_t nrg = (nr + kRowsPerWG - 1) / kRowsPerWG;
+    const int64_t want = std::min((wg_target() + nrg - 1) / nrg, (nc + 63) / 64);
+    nct = std::max(nct, want);
+  }
+  return std::max<int64_t>(1, nct);
+}
+
+// fill_rho >= 0: a small (sketched) update of that observed density, whose passes are
+// bound by the longest work-group rather than by HBM: the split is chosen on the larger of
+// its byte time and its per-work-group entry time, with tiles narrowed by plan_tiles
 int plan_split(trd_ctx* ctx, int k, const int64_t* counts, Split& sp, int64_t& nrows,
-               int64_t& ncols, int& ct_w, int& n_ct) {
+               int64_t& ncols, int& ct_w, int& n_ct, double fill_rho = -1.0) {
   const int N = ctx->N;
   double best = -1;
   int bestp = -1;
+  int64_t best_nct = 1;
   for (int p = 0; p <= N - 2; ++p) {
     const int s = (k + p + 1) % N;
     const int RR = ctx->ranks[k] * ctx->ranks[s];
@@ -182,7 +199,7 @@ int plan_split(trd_ctx* ctx, int k, const int64_t* counts, Split& sp, int64_t& n
     for (int t = 1; t <= p; ++t) nr *= counts[(k + t) % N];
     for (int t = p + 1; t <= N - 1; ++t) nc *= counts[(k + t) % N];
     const int64_t wmax = pass_ct_w(ctx->dtype, 0, RRP);
-    const int64_t nct = (nc + wmax - 1) / wmax;
+    const int64_t nct = plan_tiles(nr, nc, wmax, fill_rho);
     const int64_t nrg = (nr + kRowsPerWG - 1) / kRowsPerWG;
     int ncg, cpg;
     column_groups(nrg, (int)std::min<int64_t>(nct, 1 << 30), ncg, cpg);
@@ -192,11 +209,17 @@ int plan_split(trd_ctx* ctx, int k, const int64_t* counts, Split& sp, int64_t& n
     const double esb = (double)esz(ctx->dtype);
     const double vbytes = (double)nc * RRP * esb;
     const double vw = vbytes <= 2.0 * (1 << 20) ? 0.25 : 1.0;
-    const double cost = 2.0 * (double)(nr + nc) * RRP * esb + 2.0 * (double)ncg * nr * RRP * esb +
-                        vw * (double)nrg * vbytes;
+    double cost = 2.0 * (double)(nr + nc) * RRP * esb + 2.0 * (double)ncg * nr * RRP * esb +
+                  vw * (double)nrg * vbytes;
+    if (fill_rho >= 0) {
+      // seconds: bytes at ~4 TB/s against ~1 ns per observed entry of the busiest group
+      const double per_wg = fill_rho * (double)nr * (double)nc / ((double)nrg * ncg) * RRP / 32.0;
+      cost = std::max(cost / 4e12, per_wg * 1e-9);
+    }
     if (bestp < 0 || cost < best) {
       best = cost;
       bestp = p;
+      best_nct = nct;
     }
   }
   if (bestp < 0)
@@ -216,8 +239,7 @@ int plan_split(trd_ctx* ctx, int k, const int64_t* counts, Split& sp, int64_t& n
   for (int t = 0; t < sp.p; ++t) nrows *= counts[sp.B[t]];
   ncols = 1;
   for (int t = 0; t < sp.q; ++t) ncols *= counts[sp.C[t]];
-  const int64_t wmax = pass_ct_w(ctx->dtype, 0, sp.RRP);
-  n_ct = (int)((ncols + wmax - 1) / wmax);
+  n_ct = (int)best_nct;
   ct_w = (int)((ncols + n_ct - 1) / n_ct);
   return TRD_OK;
 }
@@ -361,6 +383,12 @@ struct Update {
 };
 
 int sketch_layout(trd_ctx* ctx, int k, int64_t nrows, int64_t ncols, int ct_w, int n_ct);
+// observed density of the bound problem (what a sketch of it holds on average)
+double sketch_density(const trd_ctx* ctx) {
+  double total = 1.0;
+  for (int j = 0; j < ctx->N; ++j) total *= (double)ctx->dims[j];
+  return total > 0 ? (double)ctx->nobs / total : 0.0;
+}
 int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st);
 
 // sample the sketch of update (t, k) and build its layout into the sketch workspace
@@ -392,7 +420,7 @@ int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStr
   }
   int64_t nrows, ncols;
   int ct_w, n_ct;
-  TRY(plan_split(ctx, k, up.cnt, up.sp, nrows, ncols, ct_w, n_ct));
+  TRY(plan_split(ctx, k, up.cnt, up.sp, nrows, ncols, ct_w, n_ct, sketch_density(ctx)));
   TRY(sketch_layout(ctx, k, nrows, ncols, ct_w, n_ct));
   Layout& L = W.L;
   up.counts = up.cnt;
@@ -409,7 +437,8 @@ int sketch_layout(trd_ctx* ctx, int k, int64_t nrows, int64_t ncols, int ct_w, i
   Layout& L = W.L;
   layout_dims(L, nrows, ncols, ct_w, n_ct);
   const int64_t need_counts = (int64_t)n_ct * L.n_rg * kRowsPerWG;
-  const int64_t need_slots = need_counts * (int64_t)ct_w;  // dense bound
+  // dense bound: every slice as long as its tile is wide, rounded up to whole groups
+  const int64_t need_slots = need_counts * (((int64_t)ct_w + kGroup - 1) / kGroup * kGroup);
   if (nrows > W.cap_rows) { TRY(alloc_n(ctx, &L.rowoff, nrows)); W.cap_rows = nrows; }
   if (ncols > W.cap_cols) { TRY(alloc_n(ctx, &L.coloff, ncols)); W.cap_cols = ncols; }
   if (need_counts > W.cap_counts) { TRY(alloc_n(ctx, &L.counts, need_counts)); W.cap_counts = need_counts; }
@@ -457,8 +486,7 @@ int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStrea
   sp.RR = sp.r_k * sp.r_s;
   sp.RRP = pass_rrp(sp.RR);
   if (sp.RRP < 0) return fail(ctx, TRD_EUNSUPPORTED, "r_k * r_{k+1} above the pass width");
-  const int64_t wmax = pass_ct_w(ctx->dtype, 0, sp.RRP);
-  const int n_ct = (int)((J + wmax - 1) / wmax);
+  const int n_ct = (int)plan_tiles(ctx->dims[k], J, pass_ct_w(ctx->dtype, 0, sp.RRP), sketch_density(ctx));
   const int ct_w = (int)((J + n_ct - 1) / n_ct);
   TRY(sketch_layout(ctx, k, ctx->dims[k], J, ct_w, n_ct));
   Layout& L = ctx->sk.L;

@@ -81,6 +81,17 @@ def test_sample_sketch_bit_exact(seed, t, k):
         assert got[j].cpu().numpy().tolist() == ref[j], j
 
 
+@pytest.mark.parametrize("dims,sizes", [((262144, 300000, 5), (900, 300, 4)),    # LDS bitmap / global list
+                                        ((70000, 33, 2), (69999, 32, 1)),        # nearly every index
+                                        ((1, 64, 65), (1, 63, 1))])
+def test_sample_sketch_bit_exact_large_and_edge_sizes(dims, sizes):
+    for k in range(3):
+        got = trd.trd_sample_sketch(5, 2, k, dims, sizes)
+        ref = orng.sketch_indices(5, 2, k, dims, sizes)
+        for j in range(3):
+            assert got[j].cpu().numpy().tolist() == ref[j], (k, j)
+
+
 @pytest.mark.parametrize("dims,ranks", SHAPES)
 def test_fgmc_gram(dims, ranks):
     X, P, Z0, prob = _setup(dims, ranks)
