@@ -26,6 +26,10 @@ with its justification in the design notes):
     independently and uniformly with replacement, J = the row count of the RStS sketch
     of the same sizes; no rescaling of the sampled rows (a common factor on them leaves
     the step eta h unchanged); the Gram matrix stays the global one.
+  * leverage-score sampling (ablation of Sec. 6.1, TRALS-S's sampler): the same J, each
+    mode's index drawn from that core's leverage distribution (leverage of the rows of
+    its mode-2 unfolding, with the ridge of eq. 10), the row weighted by 1 / (J p) in the
+    gradient, the line search and the loss; the quantile residuals stay unweighted.
   * sigma schedule: 'fixed', 'given' (one value per sweep) or 'quantile'.  The paper
     defers to an external adaptive rule that is not reproduced in its text; the
     quantile rule is this project's own choice: PARITY UNPINNED beyond the
@@ -128,17 +132,63 @@ def _sampled_rows(X, P, cores, k, rows):
     return unfold_cyclic(X, k)[:, rows], unfold_cyclic(P, k)[:, rows], A
 
 
+def core_leverage(Z: np.ndarray, lambda_rel: float = 1e-9) -> np.ndarray:
+    """Leverage scores of the rows of the classical mode-2 unfolding Z_(2) (I x r r'): row i
+    scores z_i^T (C + lambda I)^{-1} z_i with C = Z_(2)^T Z_(2) and lambda = lambda_rel tr(C) / R
+    (the ridge of eq. 10, which keeps a core with fewer slices than r r' well defined)."""
+    Z2 = unfold_core(Z)
+    C = Z2.T @ Z2
+    R = C.shape[0]
+    lam = lambda_rel * np.trace(C) / R
+    Y = np.linalg.solve(C + lam * np.eye(R), Z2.T)      # (C + lam I)^{-1} z_i, column i
+    return np.einsum("ip,pi->i", Z2, Y)
+
+
+def leverage_rows(cores: Sequence[np.ndarray], k: int, J: int, seed: int, t: int,
+                  lambda_rel: float = 1e-9):
+    """TRALS-S's leverage-score row sampling of Z^{!=k}_{[2]} (the ablation of Sec. 6.1):
+    every sample draws the index of each mode j != k independently, with probability
+    q_j(i) = l_j(i) / sum_i l_j(i) from the leverage scores of core j, by inverse CDF of the
+    running sums in slice order; its row has probability p = prod_j q_j(i_j) and importance
+    weight 1 / (J p).  Returns (rows (J,), weights (J,), per-mode indices (J, N))."""
+    N = len(cores)
+    dims = [Z.shape[1] for Z in cores]
+    idx = np.zeros((J, N), dtype=np.int64)
+    p = np.ones(J)
+    for j in range(N):
+        if j == k:
+            continue
+        lev = core_leverage(cores[j], lambda_rel)
+        cdf = np.cumsum(lev)
+        total = cdf[-1]
+        u = _rng.uniform01(_rng.lev_key(seed, t, k, j), np.arange(J))
+        ij = np.minimum(np.searchsorted(cdf, u * total, side="right"), dims[j] - 1)
+        idx[:, j] = ij
+        p *= lev[ij] / total
+    rows = np.zeros(J, dtype=np.int64)
+    stride = 1
+    for s_ in range(1, N):
+        j = (k + s_) % N
+        rows += idx[:, j] * stride
+        stride *= dims[j]
+    return rows, 1.0 / (J * p), idx
+
+
 def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, sigma: float,
                 lambda_rel: float = 1e-9, sketch: Optional[Sequence[Sequence[int]]] = None,
-                gram: str = "fgmc", direction: str = "scaled", rows: Optional[np.ndarray] = None):
+                gram: str = "fgmc", direction: str = "scaled", rows: Optional[np.ndarray] = None,
+                row_weights: Optional[np.ndarray] = None):
     """One update of core k (Alg. 1 body).  Returns (new core k, StepInfo).
 
     sketch: None for the full path (AWRTRD), else index lists I_1..I_N (RStS,
     eqs. 14-18): the gradient and the line search use the subtensor, the Gram matrix
     always uses the full cores.
-    rows: the uniform-row-sampling ablation of Sec. 6.1 instead of a sketch: indices of
-    rows of A = Z^{!=k}_{[2]} (with repeats); the gradient and the line search use those
-    rows of A and the same columns of X_[k], P_[k], the Gram matrix the full cores.
+    rows: the row-sampling ablations of Sec. 6.1 instead of a sketch: indices of rows of
+    A = Z^{!=k}_{[2]} (with repeats); the gradient and the line search use those rows of A
+    and the same columns of X_[k], P_[k], the Gram matrix the full cores.
+    row_weights: importance weight of each sampled row (leverage sampling): every entry of
+    sampled row n counts with weight omega_n in the gradient, the line-search denominator
+    and the reported loss.
     gram: 'fgmc' (eq. 13) or 'explicit' (A^T A), both of the full cores; or 'local',
     the ablation of Sec. 6.1 that scales with the Gram matrix of the sampled cores only,
     A_I^T A_I of the sketched subchain unfolding (the full one without a sketch).
@@ -166,7 +216,8 @@ def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, s
     Zk2 = unfold_core(cores[k])
     E = np.where(Pk, Xk - Zk2 @ A.T, 0.0)               # residual on observed entries
     W = np.where(Pk, weights(E, sigma), 0.0)            # eq. (7)
-    d = (W * E) @ A                                      # eq. (9) / (15)
+    Om = np.ones(Pk.shape[1]) if row_weights is None else np.asarray(row_weights, dtype=np.float64)
+    d = (W * E * Om) @ A                                 # eq. (9) / (15)
     if gram == "local":
         G = A.T @ A
     elif gram == "fgmc":
@@ -182,12 +233,12 @@ def core_update(X: np.ndarray, P: np.ndarray, cores: List[np.ndarray], k: int, s
         h = d.copy()
     num = float(np.sum(d * h))
     Q = h @ A.T
-    den = float(np.sum(W * Q * Q))                        # eq. (12) / (18) denominator
+    den = float(np.sum(W * Q * Q * Om))                   # eq. (12) / (18) denominator
     eta = num / den if den > 0.0 else 0.0
     new = fold_core(Zk2 + eta * h, rk, rk1)              # eq. (11) / (17), sign '+'
-    loss = float(np.sum(np.where(Pk, welsch(E, sigma), 0.0)))
+    loss = float(np.sum(np.where(Pk, welsch(E, sigma), 0.0) * Om))
     info = StepInfo(d=d, h=h, G=G, eta=eta, num=num, den=den, loss=loss,
-                    wls=float(np.sum(W * E * E)), n_obs=int(Pk.sum()), W=W, E=E)
+                    wls=float(np.sum(W * E * E * Om)), n_obs=int(Pk.sum()), W=W, E=E)
     return new, info
 
 
@@ -274,7 +325,7 @@ class FitOptions:
     seed: int = 0
     gram: str = "fgmc"
     direction: str = "scaled"
-    sampling: str = "rsts"          # with sketch_sizes: 'rsts' or 'rows' (Sec. 6.1 ablation)
+    sampling: str = "rsts"          # with sketch_sizes: 'rsts', 'rows' or 'leverage' (Sec. 6.1)
 
 
 def sketch_for(opts: FitOptions, t: int, k: int, dims):
@@ -283,16 +334,32 @@ def sketch_for(opts: FitOptions, t: int, k: int, dims):
     return _rng.sketch_indices(opts.seed, t, k, dims, opts.sketch_sizes)
 
 
-def rows_for(opts: FitOptions, t: int, k: int, dims):
-    """Uniform row sample of update (t, k): as many rows as the RStS sketch of the same
-    sizes holds (the product of the other modes' clamped sizes)."""
-    if opts.sketch_sizes is None or opts.sampling != "rows":
-        return None
+def _rows_J(opts: FitOptions, k: int, dims) -> int:
     J = 1
     for j, (I, s) in enumerate(zip(dims, opts.sketch_sizes)):
         if j != k:
             J *= min(max(1, int(s)), int(I))
-    return _rng.uniform_rows(opts.seed, t, k, dims, J)
+    return J
+
+
+def rows_for(opts: FitOptions, t: int, k: int, dims, cores=None):
+    """Row sample of update (t, k), as many rows as the RStS sketch of the same sizes holds
+    (the product of the other modes' clamped sizes): uniform ('rows'), or by leverage
+    ('leverage', from the cores as they stand), then with its importance weights."""
+    if opts.sketch_sizes is None or opts.sampling not in ("rows", "leverage"):
+        return None
+    J = _rows_J(opts, k, dims)
+    if opts.sampling == "rows":
+        return _rng.uniform_rows(opts.seed, t, k, dims, J)
+    rows, w, _ = leverage_rows(cores, k, J, opts.seed, t, opts.lambda_rel)
+    return rows, w
+
+
+def _rows_and_weights(opts, t, k, dims, cores):
+    r = rows_for(opts, t, k, dims, cores)
+    if isinstance(r, tuple):
+        return r
+    return r, None
 
 
 def sweep_sigma(X, P, cores, opts: FitOptions, t: int, sigma_min: float,
@@ -306,7 +373,7 @@ def sweep_sigma(X, P, cores, opts: FitOptions, t: int, sigma_min: float,
     if opts.sigma_mode == "given":
         return float(opts.sigma_given[t])
     dims = [Z.shape[1] for Z in cores]
-    e = residual_abs(X, P, cores, sketch_for(opts, t, 0, dims), rows_for(opts, t, 0, dims))
+    e = residual_abs(X, P, cores, sketch_for(opts, t, 0, dims), _rows_and_weights(opts, t, 0, dims, cores)[0])
     s = quantile_sigma(e, opts.q, opts.c, sigma_min)
     if math.isfinite(sigma_prev):
         s = max(s, opts.shrink * sigma_prev)
@@ -319,9 +386,10 @@ def sweep(X, P, cores: List[np.ndarray], sigma: float, opts: FitOptions, t: int 
     infos = []
     cores = list(cores)
     for k in range(len(cores)):
+        rows, rw = _rows_and_weights(opts, t, k, dims, cores)
         new, info = core_update(X, P, cores, k, sigma, opts.lambda_rel,
                                 sketch_for(opts, t, k, dims), opts.gram, opts.direction,
-                                rows_for(opts, t, k, dims))
+                                rows, rw)
         cores[k] = new
         infos.append(info)
     return cores, infos

@@ -136,6 +136,28 @@ def uniform_rows(seed: int, t: int, k: int, dims: Sequence[int], J: int) -> np.n
     return m
 
 
+# ----------------------------------------------------------------------------------
+# leverage-score row sampling (the ablation of Sec. 6.1 that applies TRALS-S's sampler)
+#
+# Sample n of update (t, k) draws, for every mode j != k, the uniform
+# u = (u64 >> 11) 2^-53 of counter_u64(lev_key(seed, t, k, j), n); the index is then taken
+# by inverse CDF from that mode's leverage distribution (computed by the caller).
+
+DOMAIN_LEV = 0x4C45564500000000  # "LEVE"
+
+
+def lev_key(seed: int, t: int, k: int, j: int) -> int:
+    """Stream key for sweep t, core update k, mode j of the leverage sampler."""
+    a = counter_u64((seed ^ DOMAIN_LEV) & M64, t)
+    b = counter_u64(a, k)
+    return counter_u64(b, j)
+
+
+def uniform01(key: int, n) -> np.ndarray:
+    """(counter_u64(key, c) >> 11) * 2^-53 for the counters c (exact doubles in [0, 1))."""
+    return (counter_u64_np(key, np.asarray(n, dtype=np.uint64)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
 def sizes_from_J(J: int, dims: Sequence[int]) -> List[int]:
     """Per-mode sample size from the sample parameter J.
 

@@ -15,6 +15,10 @@ from oracle import tr
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def rel_err(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
 def rand_cores(dims, ranks, seed, std=1.0):
     g = np.random.default_rng(seed)
     N = len(dims)
@@ -682,3 +686,116 @@ def test_row_sampled_fit_and_quantile_use_the_update_rows():
     np.testing.assert_allclose(np.sort(e), np.sort(np.abs(Xk - Xh)[Pk]), rtol=1e-12, atol=1e-14)
     cores, hist = aw.fit(X, P, Z, opts)
     assert len(hist["sigma"]) == 2 and all(np.isfinite(cores[0]).ravel())
+
+
+# ---------------------------------------------------------------- leverage-score sampling (Sec. 6.1)
+
+def _orthonormal_core(r, I, r2, seed):
+    # a core whose mode-2 unfolding (I x r r2) has orthonormal columns
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((I, r * r2)))
+    return tr.fold_core(Q, r, r2)
+
+
+def test_core_leverage_closed_forms():
+    # orthonormal columns: the leverage of row i is its squared norm, and they sum to r r'
+    Z = _orthonormal_core(2, 11, 3, 1)
+    lev = aw.core_leverage(Z, 1e-12)
+    np.testing.assert_allclose(lev, np.sum(tr.unfold_core(Z) ** 2, axis=1), rtol=1e-9, atol=1e-12)
+    assert lev.sum() == pytest.approx(6.0, rel=1e-9)
+    # fewer slices than r r' (full row rank): every row has leverage 1 (up to the ridge)
+    Z = np.random.default_rng(2).standard_normal((3, 4, 2))
+    np.testing.assert_allclose(aw.core_leverage(Z, 1e-12), np.ones(4), rtol=1e-6)
+    # invariant to a rescaling of the core and to an invertible change of basis of Z_(2)
+    Z = np.random.default_rng(3).standard_normal((2, 9, 2))
+    B = np.random.default_rng(4).standard_normal((4, 4)) + 3 * np.eye(4)
+    Zb = tr.fold_core(tr.unfold_core(Z) @ B, 2, 2)
+    np.testing.assert_allclose(aw.core_leverage(7.0 * Z, 1e-12), aw.core_leverage(Z, 1e-12), rtol=1e-8)
+    np.testing.assert_allclose(aw.core_leverage(Zb, 1e-12), aw.core_leverage(Z, 1e-12), rtol=1e-7)
+
+
+def test_leverage_draws_follow_the_leverage_distribution():
+    dims, ranks = (3, 12, 4), (2, 2, 3)
+    Z = rand_cores(dims, ranks, 70)
+    rows, w, idx = aw.leverage_rows(Z, 0, 12000, 5, 0)
+    lev = aw.core_leverage(Z[1])
+    q = lev / lev.sum()
+    cnt = np.bincount(idx[:, 1], minlength=12)
+    chi2 = np.sum((cnt - 12000 * q) ** 2 / (12000 * q))
+    assert chi2 < 32.9       # 11 dof; p ~ 1e-3 threshold
+    # the weight is 1 / (J p) with p the product of the per-mode probabilities
+    q2 = aw.core_leverage(Z[2]) / aw.core_leverage(Z[2]).sum()
+    np.testing.assert_allclose(w, 1.0 / (12000 * q[idx[:, 1]] * q2[idx[:, 2]]), rtol=1e-12)
+    np.testing.assert_array_equal(rows, idx[:, 1] + 12 * idx[:, 2])
+
+
+def test_leverage_weighted_gradient_is_unbiased():
+    # E[sum_n omega_n (W P E)_n A_n] over the draws is the full gradient of eq. (9)
+    dims, ranks = (3, 4, 5), (2, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 71, rho=1.0)
+    _, full = aw.core_update(X, P, Z, 0, 0.9)
+    acc = np.zeros_like(full.d)
+    trials = 300
+    for t in range(trials):
+        rows, w, _ = aw.leverage_rows(Z, 0, 20, 9, t)
+        _, info = aw.core_update(X, P, Z, 0, 0.9, rows=rows, row_weights=w)
+        acc += info.d
+    assert rel_err(acc / trials, full.d) < 0.08
+
+
+def test_uniform_leverage_gives_constant_weights_and_the_unweighted_step():
+    # cores whose unfoldings are square orthogonal: every leverage is 1, p is uniform, the
+    # weights are all M / J, and a common weight leaves the step unchanged
+    dims, ranks = (4, 6, 6), (2, 2, 3)
+    Z = [_orthonormal_core(2, 4, 2, 11), _orthonormal_core(2, 6, 3, 12), _orthonormal_core(3, 6, 2, 13)]
+    g = np.random.default_rng(14)
+    P = (g.random(dims) < 0.7).astype(np.uint8)
+    X = tr.reconstruct(rand_cores(dims, ranks, 15)) + 0.1 * g.standard_normal(dims)
+    rows, w, _ = aw.leverage_rows(Z, 0, 30, 3, 1, lambda_rel=1e-13)
+    np.testing.assert_allclose(w, np.full(30, 36 / 30), rtol=1e-9)
+    a, ia = aw.core_update(X, P, Z, 0, 1.2, rows=rows, row_weights=w)
+    b, ib = aw.core_update(X, P, Z, 0, 1.2, rows=rows)
+    np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(ia.d, ib.d * 36 / 30, rtol=1e-9, atol=1e-12)
+
+
+def test_leverage_weighted_gradient_by_brute_force():
+    dims, ranks = (3, 2, 4, 3), (2, 3, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 72)
+    N, k, sigma = 4, 1, 0.7
+    rows, w, idx = aw.leverage_rows(Z, k, 25, 4, 2)
+    _, info = aw.core_update(X, P, Z, k, sigma, rows=rows, row_weights=w)
+    rk, rk1 = ranks[k], ranks[(k + 1) % N]
+    d = np.zeros((dims[k], rk * rk1))
+    for n in range(25):
+        Am = np.eye(rk1)
+        for s in range(1, N):
+            j = (k + s) % N
+            Am = Am @ Z[j][:, idx[n, j], :]
+        for i in range(dims[k]):
+            full = [int(v) for v in idx[n]]
+            full[k] = i
+            if not P[tuple(full)]:
+                continue
+            e = X[tuple(full)] - tr.reconstruct_entry(Z, full)
+            y = w[n] * np.exp(-e * e / (2 * sigma * sigma)) * e
+            for a in range(rk):
+                for b in range(rk1):
+                    d[i, a + b * rk] += y * Am[b, a]
+    np.testing.assert_allclose(info.d, d, rtol=1e-12, atol=1e-12)
+
+
+def test_leverage_fit_draws_from_the_current_cores():
+    dims, ranks = (5, 4, 6), (2, 2, 2)
+    Z, P, X = _masked_problem(dims, ranks, 73)
+    opts = aw.FitOptions(max_sweeps=2, tol=0, sketch_sizes=(3, 2, 4), sampling="leverage", seed=9,
+                         sigma_mode="fixed", sigma=1.0)
+    cores, hist = aw.fit(X, P, Z, opts)
+    # sweep 0, update 1 draws from the cores after update 0
+    c1 = list(Z)
+    c1[0], _ = aw.core_update(X, P, Z, 0, 1.0, rows=aw.rows_for(opts, 0, 0, dims, Z)[0],
+                              row_weights=aw.rows_for(opts, 0, 0, dims, Z)[1])
+    r_fit = aw.rows_for(opts, 0, 1, dims, c1)
+    r_old = aw.rows_for(opts, 0, 1, dims, Z)
+    assert r_fit[0].size == 3 * 4
+    assert not np.allclose(r_fit[1], r_old[1])        # weights follow the updated core 0
+    assert len(hist["sigma"]) == 2 and np.isfinite(cores[1]).all()
