@@ -236,13 +236,15 @@ def equal_accuracy_seeds(wname, seeds, sweeps):
 
 ABLATION_VARIANTS = (("method", "scaled", "global", "rsts"), ("gradient descent", "gradient", "global", "rsts"),
                      ("local scaled term", "scaled", "local", "rsts"),
-                     ("uniform row sampling", "scaled", "global", "rows"))
+                     ("uniform row sampling", "scaled", "global", "rows"),
+                     ("leverage score sampling", "scaled", "global", "leverage"))
 
 
 def ablation(prob, Z0_flat, xstar_d, dims, sizes, sweeps, seed=0, n_sample=1 << 20):
     """The ablations of Sec. 6.1 on the sketched path: the method, the plain gradient
-    direction, the local scaled term (each with the same RStS sketches) and uniform row
-    sampling (as many rows of the subchain unfolding, drawn i.i.d.), each fitted for
+    direction, the local scaled term (each with the same RStS sketches), uniform row
+    sampling and leverage-score sampling (as many rows of the subchain unfolding, drawn
+    i.i.d. uniformly or from the cores' leverage distributions), each fitted for
     `sweeps` sweeps from the same start, for several per-mode sample sizes s (J = s^(N-1)
     sampled rows per update); recovery error over a fixed uniform sample of entries, and
     the fit's time."""

@@ -270,6 +270,21 @@ int trd_sample_rows(uint64_t seed, int t, int k, int N, const int64_t* dims, int
                     void* stream);
 
 /*
+ * Draw the leverage-score row sample of update k in sweep t on the device (the ablation of
+ * Sec. 6.1 that applies TRALS-S's sampler, used under TRD_SAMPLE_LEVERAGE).  For every mode
+ * j != k the leverage of the rows of core j's mode-2 unfolding Z_j(2) (I_j x r_j r_{j+1}) is
+ * l(i) = z_i^T (C + lambda I)^{-1} z_i with C = Z_j(2)^T Z_j(2) and the ridge of eq. (10),
+ * lambda = lambda_rel tr(C) / (r_j r_{j+1}); sample n takes the uniform
+ * u = (u(key_j, n) >> 11) 2^-53 with key_j = u(u(u(seed ^ 0x4C45564500000000, t), k), j) (u as
+ * at trd_sample_sketch) and the first slice i whose running sum l(0) + ... + l(i) in FP64
+ * exceeds u times the total.  Its row has probability p = prod_j l(i_j) / total_j.
+ * rows_out (device, J int64): row indices as at trd_sample_rows; weights_out (device, J FP64):
+ * the importance weights 1 / (J p).  ctx needs a shape; cores: N device pointers.
+ */
+int trd_sample_leverage(trd_ctx* ctx, const void* const* cores, int k, uint64_t seed, int t, int64_t J,
+                        double lambda_rel, int64_t* rows_out, double* weights_out, void* stream);
+
+/*
  * Seeded synthetic observation pattern on the device, bit-exact for a given seed:
  * mask_out[l] = 1 for an observed entry (column-major l), drawn with probability rho per
  * entry (block == 0) or per tile (block > 0: block x block tiles of modes 0 and 1, one draw
@@ -319,6 +334,11 @@ int trd_set_precision(trd_ctx* ctx, int precision);
  *     tensor at those rows (a row drawn twice counts twice), the Gram matrix stays global.
  *     Caller index lists (trd_sketch.idx) are rejected; with TRD_GRAM_LOCAL and the scaled
  *     direction it is TRD_EUNSUPPORTED.
+ *   sampling TRD_SAMPLE_LEVERAGE: as TRD_SAMPLE_ROWS, with the J rows drawn by TRALS-S's
+ *     leverage-score sampler from the cores as they stand (trd_sample_leverage, same seed,
+ *     sweep and ridge: the step's lambda_rel, 1e-9 in trd_grad); each sampled entry counts
+ *     with its row's importance weight 1 / (J p) in the gradient, the line search and the
+ *     reported loss; the kernel-width residuals stay unweighted.
  * Returns TRD_EINVAL for other values (the context keeps its previous variant).
  */
 #define TRD_DIR_SCALED   0
@@ -327,6 +347,7 @@ int trd_set_precision(trd_ctx* ctx, int precision);
 #define TRD_GRAM_LOCAL   1
 #define TRD_SAMPLE_RSTS  0
 #define TRD_SAMPLE_ROWS  1
+#define TRD_SAMPLE_LEVERAGE 2
 int trd_set_variant(trd_ctx* ctx, int direction, int gram, int sampling);
 
 /*

@@ -30,8 +30,8 @@ TRD_DIR_SCALED, TRD_DIR_GRADIENT = 0, 1
 TRD_GRAM_GLOBAL, TRD_GRAM_LOCAL = 0, 1
 DIRECTIONS = {"scaled": TRD_DIR_SCALED, "gradient": TRD_DIR_GRADIENT}
 GRAMS = {"global": TRD_GRAM_GLOBAL, "local": TRD_GRAM_LOCAL}
-TRD_SAMPLE_RSTS, TRD_SAMPLE_ROWS = 0, 1
-SAMPLINGS = {"rsts": TRD_SAMPLE_RSTS, "rows": TRD_SAMPLE_ROWS}
+TRD_SAMPLE_RSTS, TRD_SAMPLE_ROWS, TRD_SAMPLE_LEVERAGE = 0, 1, 2
+SAMPLINGS = {"rsts": TRD_SAMPLE_RSTS, "rows": TRD_SAMPLE_ROWS, "leverage": TRD_SAMPLE_LEVERAGE}
 TRD_FLAG_EMPTY, TRD_FLAG_ZERO_DEN, TRD_FLAG_NOTSPD = 1, 2, 4
 TRD_SIGMA_FIXED, TRD_SIGMA_GIVEN, TRD_SIGMA_QUANTILE = 0, 1, 2
 
@@ -94,6 +94,7 @@ def load() -> C.CDLL:
         "trd_loss_bwd": (i32, [vp, P(vp), dbl, dbl, P(vp), vp]),
         "trd_sample_sketch": (i32, [C.c_uint64, i32, i32, i32, P(i64), P(C.c_int32), P(vp), vp]),
         "trd_sample_rows": (i32, [C.c_uint64, i32, i32, i32, P(i64), i64, vp, vp]),
+        "trd_sample_leverage": (i32, [vp, P(vp), i32, C.c_uint64, i32, i64, dbl, vp, vp, vp]),
         "trd_workspace_bytes": (i32, [i32, i32, P(i64), P(C.c_int32), i32, i32, i64, P(C.c_size_t),
                                       P(C.c_size_t)]),
         "trd_sample_mask": (i32, [C.c_uint64, i32, P(i64), dbl, i32, dbl, vp, vp, vp, vp]),
@@ -389,9 +390,20 @@ class Problem:
     def set_variant(self, direction: str = "scaled", gram: str = "global", sampling: str = "rsts"):
         """Update variants of the Sec. 6.1 ablations: direction 'scaled' | 'gradient',
         gram 'global' | 'local' (the sampled cores' Gram under a sketch), sampling 'rsts' |
-        'rows' (a sketch draws uniform rows of the subchain unfolding instead)."""
+        'rows' | 'leverage' (a sketch draws rows of the subchain unfolding instead: uniform, or
+        by leverage with importance weights)."""
         _check(load().trd_set_variant(self._ctx, DIRECTIONS[direction], GRAMS[gram], SAMPLINGS[sampling]),
                self._ctx)
+
+    def sample_leverage(self, cores, k: int, seed: int, t: int, J: int, lambda_rel: float = 1e-9):
+        """The leverage-score row sample of update k in sweep t: (rows int64, weights FP64)."""
+        dev = cores[0].device
+        rows = torch.empty(int(J), dtype=torch.int64, device=dev)
+        w = torch.empty(int(J), dtype=torch.float64, device=dev)
+        _check(load().trd_sample_leverage(self._ctx, _ptr_array(cores), int(k), int(seed), int(t), int(J),
+                                          float(lambda_rel), C.c_void_p(rows.data_ptr()),
+                                          C.c_void_p(w.data_ptr()), C.c_void_p(_stream())), self._ctx)
+        return rows, w
 
     def profile(self, enable: bool):
         _check(load().trd_profile(self._ctx, 1 if enable else 0), self._ctx)

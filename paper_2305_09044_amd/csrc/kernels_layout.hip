@@ -439,6 +439,146 @@ __global__ __launch_bounds__(256) void k_sample_rows(RowSampleArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- leverage-score row sampling
+// TRALS-S's sampler for the ablation of Sec. 6.1.  Per mode j != k: C = Z_(2)^T Z_(2) of the
+// core's mode-2 unfolding (slice i is the contiguous r_j r_{j+1} vector z_i), its ridge
+// inverse (the scaled-direction inverse kernel), the leverage l(i) = z_i^T C^{-1} z_i and
+// the running sums of l in slice order.  Sample n then draws, per mode, the uniform
+// u = (u64 >> 11) 2^-53 of u(key_j, n), key_j = u(u(u(seed ^ "LEVE", t), k), j), and takes the
+// first slice whose running sum exceeds u * total; its probability p multiplies over the
+// modes and the sample's weight is 1 / (J p).
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_core_gram(const real* __restrict__ Z, int64_t I, int R,
+                                                   double* __restrict__ C) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= R * R) return;
+  const int p = t / R, q = t % R;
+  double acc = 0.0;
+  for (int64_t i = 0; i < I; ++i) acc = fma((double)Z[i * R + p], (double)Z[i * R + q], acc);
+  C[t] = acc;
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_leverage(const real* __restrict__ Z, int64_t I, int R,
+                                                  const double* __restrict__ Ci, double* __restrict__ lev) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= I) return;
+  const real* z = Z + i * R;
+  double acc = 0.0;
+  for (int p = 0; p < R; ++p) {
+    double y = 0.0;
+    for (int q = 0; q < R; ++q) y = fma(Ci[p * R + q], (double)z[q], y);
+    acc = fma((double)z[p], y, acc);
+  }
+  lev[i] = acc;
+}
+
+// running sums of lev in slice order, one work-group: each thread sums a contiguous run
+// sequentially, then adds the totals of the runs before it
+__global__ __launch_bounds__(256) void k_lev_scan(const double* __restrict__ lev, int64_t I,
+                                                  double* __restrict__ cdf) {
+  __shared__ double tot[256];
+  const int64_t per = (I + 255) / 256;
+  const int64_t b = threadIdx.x * per, e = min(I, b + per);
+  double run = 0.0;
+  for (int64_t i = b; i < e; ++i) run += lev[i];
+  tot[threadIdx.x] = run;
+  __syncthreads();
+  double off = 0.0;
+  for (int t = 0; t < (int)threadIdx.x; ++t) off += tot[t];
+  run = off;
+  for (int64_t i = b; i < e; ++i) {
+    run += lev[i];
+    cdf[i] = run;
+  }
+}
+
+struct LevArgs {
+  uint64_t seed;
+  int t, k, N;
+  int64_t dims[kMaxN];
+  int64_t strides[kMaxN];
+  const double* lev[kMaxN];
+  const double* cdf[kMaxN];
+  int64_t J;
+  int64_t* off;
+  int64_t* row;
+  double* weight;
+};
+
+__global__ __launch_bounds__(256) void k_sample_leverage(LevArgs a) {
+  const uint64_t base = counter_u64(counter_u64(a.seed ^ 0x4C45564500000000ull, (uint64_t)a.t), (uint64_t)a.k);
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < a.J;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    int64_t off = 0, row = 0, rs = 1;
+    double p = 1.0;
+    for (int s = 1; s < a.N; ++s) {
+      const int j = (a.k + s) % a.N;
+      const int64_t I = a.dims[j];
+      const double* cdf = a.cdf[j];
+      const double total = cdf[I - 1];
+      const double u = (double)(counter_u64(counter_u64(base, (uint64_t)j), (uint64_t)n) >> 11) * 0x1p-53;
+      const double target = u * total;
+      int64_t lo = 0, hi = I;  // first slice whose running sum exceeds the target
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+      }
+      const int64_t i = lo < I ? lo : I - 1;
+      p *= a.lev[j][i] / total;
+      off += i * a.strides[j];
+      row += i * rs;
+      rs *= I;
+    }
+    if (a.off) a.off[n] = off;
+    if (a.row) a.row[n] = row;
+    a.weight[n] = 1.0 / ((double)a.J * p);
+  }
+}
+
+hipError_t launch_leverage_mode(int dtype, const void* Z, int64_t I, int R, double* C, double* Ci,
+                                double lambda_rel, double* lev, double* cdf, uint32_t* flags,
+                                hipStream_t st) {
+  const unsigned gb = (unsigned)((R * R + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_core_gram<float>, dim3(gb), dim3(256), 0, st, (const float*)Z, I, R, C);
+  else
+    hipLaunchKernelGGL(k_core_gram<double>, dim3(gb), dim3(256), 0, st, (const double*)Z, I, R, C);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_inverse(C, Ci, R, lambda_rel, flags, st);
+  if (e != hipSuccess) return e;
+  const unsigned lb = (unsigned)((I + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_leverage<float>, dim3(lb), dim3(256), 0, st, (const float*)Z, I, R, Ci, lev);
+  else
+    hipLaunchKernelGGL(k_leverage<double>, dim3(lb), dim3(256), 0, st, (const double*)Z, I, R, Ci, lev);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lev_scan, dim3(1), dim3(256), 0, st, lev, I, cdf);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_leverage(uint64_t seed, int t, int k, int N, const int64_t* dims,
+                                  const double* const* lev, const double* const* cdf, int64_t J,
+                                  int64_t* off, int64_t* row, double* weight, hipStream_t st) {
+  if (J <= 0) return hipSuccess;
+  LevArgs a;
+  a.seed = seed; a.t = t; a.k = k; a.N = N; a.J = J; a.off = off; a.row = row; a.weight = weight;
+  int64_t stride = 1;
+  for (int j = 0; j < kMaxN; ++j) {
+    a.dims[j] = j < N ? dims[j] : 1;
+    a.strides[j] = stride;
+    if (j < N) stride *= dims[j];
+    a.lev[j] = j < N ? lev[j] : nullptr;
+    a.cdf[j] = j < N ? cdf[j] : nullptr;
+  }
+  const int64_t blocks = std::min<int64_t>((J + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_sample_leverage, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- masks and outliers
 // Per-entry (or per-tile) Bernoulli draws from the same counter generator: an event of
 // probability p happens when the draw is below floor(p 2^64) (integer compare; p >= 1:

@@ -148,8 +148,13 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
     const real e = x - (xh0 + xh1);
     const real uu = e * e * inv2s2;
     const real w = ls_limit ? real(1) : fast_exp_neg(uu);
+    // importance weight of the entry's column (leverage-sampled rows only)
+    real cw = real(1);
+    if constexpr (kGrad || MODE == kModeLS) {
+      if (a.colw) cw = (real)a.colw[col0 + c];
+    }
     if constexpr (kGrad) {
-      const real y = w * e;
+      const real y = w * e * cw;
       if constexpr (kHoldV) {
 #pragma unroll
         for (int j = 0; j < RC; ++j) u[j] = fma(y, vr[j], u[j]);
@@ -165,13 +170,13 @@ __global__ __launch_bounds__(kPassThreads, 2) void k_pass(PassArgs a) {
       }
       if constexpr (MODE == kModeGrad) {
         const real l = ls_limit ? real(0.5) * e * e : sig2 * one_minus_exp_neg(uu, w);
-        s0 += (double)l;
-        s1 += (double)(w * e * e);
+        s0 += (double)(l * cw);
+        s1 += (double)(w * e * e * cw);
         s2 += 1.0;
       }
     } else if constexpr (MODE == kModeLS) {
       const real q = q0 + q1;
-      f0 = fma(w * q, q, f0);
+      f0 = fma(w * q * cw, q, f0);
     } else if constexpr (MODE == kModeResid) {
       a.resid[slot] = (float)fabs(e);
     } else {

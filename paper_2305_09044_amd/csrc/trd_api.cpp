@@ -32,6 +32,16 @@ struct SketchWS {
   Layout L;                 // layout storage at capacity
   int64_t cap_rows = 0, cap_cols = 0, cap_slices = 0, cap_counts = 0, cap_slots = 0;
   bool ready = false;
+  // leverage sampling: C and its inverse (one mode at a time), per-mode leverage and
+  // running sums, per-sample importance weights
+  double* levC = nullptr;
+  double* levCi = nullptr;
+  int64_t cap_levC = 0;
+  double* lev[kMaxN] = {nullptr};
+  double* cdf[kMaxN] = {nullptr};
+  int64_t cap_lev[kMaxN] = {0};
+  double* colw = nullptr;
+  int64_t cap_colw = 0;
 };
 
 }  // namespace
@@ -60,6 +70,7 @@ struct trd_ctx {
   int direction = TRD_DIR_SCALED;  // step direction and Gram of later updates
   int gram = TRD_GRAM_GLOBAL;
   int sampling = TRD_SAMPLE_RSTS;  // how a sketch picks its rows
+  double lev_lambda = 1e-9;        // ridge of the leverage scores (the step's lambda_rel)
   uint16_t* Tb = nullptr; uint16_t* THb = nullptr; uint16_t* Vb = nullptr;
   uint16_t* Tb_lo = nullptr; uint16_t* Vb_lo = nullptr;  // split (BF16X3) remainders
   // Vb (and Vb_lo) in operand-fragment order, and Vb transposed in fragment order
@@ -377,7 +388,8 @@ struct Update {
   TLayout* TL = nullptr;                  // non-null: matrix-core (BF16) passes
   const int64_t* counts = nullptr;        // per-mode counts of this update
   const int32_t* const* lists = nullptr;  // per-mode device lists (nullptr = full)
-  bool rows = false;                      // uniform row sample: columns = sampled fibres
+  bool rows = false;                      // row sample: columns = sampled fibres
+  const double* colw = nullptr;           // importance weight per column (leverage sample)
   int64_t cnt[kMaxN];
   const int32_t* lst[kMaxN];
 };
@@ -389,11 +401,13 @@ double sketch_density(const trd_ctx* ctx) {
   for (int j = 0; j < ctx->N; ++j) total *= (double)ctx->dims[j];
   return total > 0 ? (double)ctx->nobs / total : 0.0;
 }
-int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st);
+int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st,
+                 const void* const* cores);
 
 // sample the sketch of update (t, k) and build its layout into the sketch workspace
-int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
-  if (ctx->sampling == TRD_SAMPLE_ROWS) return prepare_rows(ctx, k, sk, up, st);
+int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st,
+                   const void* const* cores) {
+  if (ctx->sampling != TRD_SAMPLE_RSTS) return prepare_rows(ctx, k, sk, up, st, cores);
   const int N = ctx->N;
   SketchWS& W = ctx->sk;
   for (int j = 0; j < N; ++j) {
@@ -462,12 +476,46 @@ int sketch_layout(trd_ctx* ctx, int k, int64_t nrows, int64_t ncols, int ct_w, i
   return TRD_OK;
 }
 
-// uniform row sampling (the ablation of Sec. 6.1 that replaces RStS): as many rows of the
-// subchain unfolding as the sketch of these sizes holds, drawn independently and uniformly
-// with replacement; the update's matrix has the I_k rows of core k and one column per sample
-int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
+// leverage distributions of every mode but k from the cores as they stand, and J draws
+// from their product with importance weights (TRALS-S's sampler)
+int sample_leverage(trd_ctx* ctx, const void* const* cores, int k, uint64_t seed, int t, int64_t J,
+                    double lambda_rel, int64_t* off, int64_t* row, double* weight, hipStream_t st) {
   const int N = ctx->N;
-  if (sk->idx) return fail(ctx, TRD_EINVAL, "caller index lists are RStS sets: not with uniform row sampling");
+  SketchWS& W = ctx->sk;
+  int64_t maxR2 = 1;
+  for (int j = 0; j < N; ++j)
+    if (j != k) maxR2 = std::max<int64_t>(maxR2, (int64_t)ctx->ranks[j] * ctx->ranks[(j + 1) % N] *
+                                                     ctx->ranks[j] * ctx->ranks[(j + 1) % N]);
+  if (maxR2 > W.cap_levC) {
+    TRY(alloc_n(ctx, &W.levC, maxR2));
+    TRY(alloc_n(ctx, &W.levCi, maxR2));
+    W.cap_levC = maxR2;
+  }
+  for (int j = 0; j < N; ++j) {
+    if (j == k) continue;
+    if (ctx->dims[j] > W.cap_lev[j]) {
+      TRY(alloc_n(ctx, &W.lev[j], ctx->dims[j]));
+      TRY(alloc_n(ctx, &W.cdf[j], ctx->dims[j]));
+      W.cap_lev[j] = ctx->dims[j];
+    }
+    const int R = ctx->ranks[j] * ctx->ranks[(j + 1) % N];
+    CK(launch_leverage_mode(ctx->dtype, cores[j], ctx->dims[j], R, W.levC, W.levCi, lambda_rel, W.lev[j],
+                            W.cdf[j], ctx->flags + 3, st));
+  }
+  CK(launch_sample_leverage(seed, t, k, N, ctx->dims, W.lev, W.cdf, J, off, row, weight, st));
+  return TRD_OK;
+}
+
+// row sampling (the ablations of Sec. 6.1 that replace RStS): as many rows of the subchain
+// unfolding as the sketch of these sizes holds, drawn independently with replacement,
+// uniformly or by leverage (then with importance weights); the update's matrix has the I_k
+// rows of core k and one column per sample
+int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st,
+                 const void* const* cores) {
+  const int N = ctx->N;
+  const bool lev = ctx->sampling == TRD_SAMPLE_LEVERAGE;
+  if (sk->idx) return fail(ctx, TRD_EINVAL, "caller index lists are RStS sets: not with row sampling");
+  if (lev && !cores) return fail(ctx, TRD_EINVAL, "leverage sampling needs the cores");
   int64_t J = 1;
   for (int j = 0; j < N; ++j) {
     up.cnt[j] = ctx->dims[j];
@@ -494,7 +542,17 @@ int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStrea
   up.lists = up.lst;
   up.rows = true;
   up.L = &L;
-  CK(launch_sample_rows(sk->seed, sk->sweep, k, N, ctx->dims, J, L.coloff, nullptr, st));
+  if (lev) {
+    SketchWS& W = ctx->sk;
+    if (J > W.cap_colw) {
+      TRY(alloc_n(ctx, &W.colw, J));
+      W.cap_colw = J;
+    }
+    TRY(sample_leverage(ctx, cores, k, sk->seed, sk->sweep, J, ctx->lev_lambda, L.coloff, nullptr, W.colw, st));
+    up.colw = W.colw;
+  } else {
+    CK(launch_sample_rows(sk->seed, sk->sweep, k, N, ctx->dims, J, L.coloff, nullptr, st));
+  }
   TRY(build_layout_head(ctx, sp, up.cnt, nullptr, L, st, true));
   CK(launch_fill(L, ctx->mask, ctx->X, ctx->dtype, st));
   return TRD_OK;
@@ -564,8 +622,9 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
 
 bool bf16_form(int prec) { return prec == TRD_PREC_BF16 || prec == TRD_PREC_BF16X3; }
 
-int prepare_update(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st) {
-  if (sk) return prepare_sketch(ctx, k, sk, up, st);  // sketches use the ELL passes
+int prepare_update(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStream_t st,
+                   const void* const* cores = nullptr) {
+  if (sk) return prepare_sketch(ctx, k, sk, up, st, cores);  // sketches use the ELL passes
   if (bf16_form(ctx->prec)) {
     TRY(ensure_tile_layout(ctx, k, st));
     up.TL = &ctx->tlayouts[k];
@@ -731,6 +790,7 @@ PassArgs pass_args(trd_ctx* ctx, const Update& up) {
   a.slice_off = L.slice_off;
   a.slice_len = L.slice_len;
   a.resid = ctx->resid;
+  a.colw = up.colw;
   a.partials = ctx->part_pass;
   a.sigma = ctx->scal + kSigma;
   a.nrows = L.nrows;
@@ -971,7 +1031,8 @@ int ensure_side(trd_ctx* ctx) {
 int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const trd_sketch* sk,
             double* eta_user, uint32_t* flags_user, hipStream_t st) {
   Update up;
-  TRY(prepare_update(ctx, k, sk, up, st));
+  ctx->lev_lambda = lambda_rel;
+  TRY(prepare_update(ctx, k, sk, up, st, cores));
   const Split& sp = up.sp;
   const int64_t Ik = ctx->dims[k];
   const int R = sp.r_k * sp.r_k1;
@@ -1401,7 +1462,8 @@ int trd_grad(trd_ctx* ctx, const void* const* cores, int k, double sigma, const 
   hipStream_t st = (hipStream_t)stream;
   TRY(set_sigma(ctx, sigma, st));
   Update up;
-  TRY(prepare_update(ctx, k, sketch, up, st));
+  ctx->lev_lambda = 1e-9;
+  TRY(prepare_update(ctx, k, sketch, up, st, cores));
   TRY(do_grad(ctx, up, cores, d_out, 1.0, stats_dev, st, nullptr, nullptr));
   return TRD_OK;
 }
@@ -1499,7 +1561,8 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
       TRY(set_sigma(ctx, o->sigma_given[t], st));
     } else {
       Update up;
-      TRY(prepare_update(ctx, 0, sk, up, st));
+      ctx->lev_lambda = o->lambda_rel;
+      TRY(prepare_update(ctx, 0, sk, up, st, (const void* const*)cores));
       const Layout& L = *up.L;
       // residual slots: ELL slots (padding holds +inf) or exactly the observed entries
       const int64_t nkeys = up.TL ? up.TL->nobs : L.slots_cap;
@@ -1640,6 +1703,19 @@ int trd_sample_sketch(uint64_t seed, int t, int k, int N, const int64_t* dims, c
   return TRD_OK;
 }
 
+int trd_sample_leverage(trd_ctx* ctx, const void* const* cores, int k, uint64_t seed, int t, int64_t J,
+                        double lambda_rel, int64_t* rows_out, double* weights_out, void* stream) {
+  TRY(check_ctx(ctx, false));
+  TRY(check_cores(ctx, cores));
+  if (k < 0 || k >= ctx->N) return fail(ctx, TRD_EINVAL, "k out of range");
+  if (J < 0) return fail(ctx, TRD_EINVAL, "J must be >= 0");
+  if (J > 0 && (!rows_out || !weights_out)) return fail(ctx, TRD_EINVAL, "NULL output");
+  if (!(lambda_rel >= 0.0)) return fail(ctx, TRD_EINVAL, "lambda_rel must be >= 0");
+  if (J == 0) return TRD_OK;
+  return sample_leverage(ctx, cores, k, seed, t, J, lambda_rel, nullptr, rows_out, weights_out,
+                         (hipStream_t)stream);
+}
+
 int trd_sample_rows(uint64_t seed, int t, int k, int N, const int64_t* dims, int64_t J, int64_t* rows_out,
                     void* stream) {
   trd_ctx* ctx = nullptr;
@@ -1693,8 +1769,9 @@ int trd_set_variant(trd_ctx* ctx, int direction, int gram, int sampling) {
   if (direction != TRD_DIR_SCALED && direction != TRD_DIR_GRADIENT)
     return fail(ctx, TRD_EINVAL, "unknown direction");
   if (gram != TRD_GRAM_GLOBAL && gram != TRD_GRAM_LOCAL) return fail(ctx, TRD_EINVAL, "unknown gram");
-  if (sampling != TRD_SAMPLE_RSTS && sampling != TRD_SAMPLE_ROWS) return fail(ctx, TRD_EINVAL, "unknown sampling");
-  if (gram == TRD_GRAM_LOCAL && sampling == TRD_SAMPLE_ROWS && direction == TRD_DIR_SCALED)
+  if (sampling != TRD_SAMPLE_RSTS && sampling != TRD_SAMPLE_ROWS && sampling != TRD_SAMPLE_LEVERAGE)
+    return fail(ctx, TRD_EINVAL, "unknown sampling");
+  if (gram == TRD_GRAM_LOCAL && sampling != TRD_SAMPLE_RSTS && direction == TRD_DIR_SCALED)
     return fail(ctx, TRD_EUNSUPPORTED, "the local Gram matrix needs RStS index sets, not a row sample");
   ctx->direction = direction;
   ctx->gram = gram;

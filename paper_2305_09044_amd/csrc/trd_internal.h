@@ -126,6 +126,16 @@ hipError_t launch_sample(uint64_t seed, int t, int k, int N, const int64_t* dims
 // may be nullptr)
 hipError_t launch_sample_rows(uint64_t seed, int t, int k, int N, const int64_t* dims, int64_t J,
                               int64_t* off, int64_t* row, hipStream_t st);
+// leverage distribution of one core (mode-2 unfolding, I slices of R = r r' values): C and
+// its ridge inverse (R x R FP64 scratch), leverage and running sums (I FP64 each)
+hipError_t launch_leverage_mode(int dtype, const void* Z, int64_t I, int R, double* C, double* Ci,
+                                double lambda_rel, double* lev, double* cdf, uint32_t* flags,
+                                hipStream_t st);
+// J leverage-sampled rows of the subchain unfolding of core k (lev/cdf of every mode j != k):
+// tensor offsets and/or row indices (either may be nullptr) and importance weights 1 / (J p)
+hipError_t launch_sample_leverage(uint64_t seed, int t, int k, int N, const int64_t* dims,
+                                  const double* const* lev, const double* const* cdf, int64_t J,
+                                  int64_t* off, int64_t* row, double* weight, hipStream_t st);
 // mask (Bernoulli rho per entry, or per block x block tile of modes 0-1 at each index of
 // modes 3.., shared by mode 2), outlier selection (observed and Bernoulli frac) and per-entry
 // uniforms; sel and u may be nullptr
@@ -175,6 +185,7 @@ struct PassArgs {
   const int64_t* slice_off;
   const int32_t* slice_len;
   float* resid;         // kModeResid output, one per slot
+  const double* colw;   // per-column weights (leverage-sampled rows) or nullptr
   double* partials;     // [n_wg][3]
   const double* sigma;  // device scalar
   int64_t nrows, ncols, n_rg;

@@ -109,6 +109,7 @@ def test_context_calls_reject_null_context():
     assert lib.trd_profile(None, 1) == _lib.TRD_EINVAL
     assert lib.trd_set_precision(None, 0) == _lib.TRD_EINVAL
     assert lib.trd_set_variant(None, 0, 0, 0) == _lib.TRD_EINVAL
+    assert lib.trd_sample_leverage(None, None, 0, 0, 0, 1, 1e-9, None, None, None) == _lib.TRD_EINVAL
     lib.trd_destroy(None)  # ignored
 
 

@@ -108,4 +108,75 @@ def test_rows_variant_rejections():
     with pytest.raises(trd.TrdError):     # caller lists are RStS sets
         prob.step(device_cores(Z0, F32), 0, 1.0, sketch=sk)
     lib = trd._lib.load()
-    assert lib.trd_set_variant(prob._ctx, 0, 0, 2) == -1   # TRD_EINVAL
+    assert lib.trd_set_variant(prob._ctx, 0, 0, 3) == -1   # TRD_EINVAL
+    with pytest.raises(trd.TrdError):     # nor with leverage rows
+        prob.set_variant("scaled", "local", "leverage")
+
+
+# ---------------------------------------------------------------- leverage-score sampling
+
+@pytest.mark.parametrize("dims,ranks,wtol", [((60, 50, 40, 30), (3, 4, 3, 2), 1e-10),
+                                             ((9, 10, 11, 8, 7), (2, 2, 3, 2, 2), 1e-10),
+                                             ((300, 257), (4, 3), 1e-10),
+                                             ((5, 70, 3), (4, 4, 4), 1e-6)])
+def test_sample_leverage_matches_oracle(dims, ranks, wtol):
+    # indices bit for bit (both sides take the inverse-CDF decision on FP64 leverages of the
+    # same FP32 cores); weights to FP64 rounding, amplified by the condition number of
+    # C + lambda I where a core has fewer slices than r r' (5 and 3 < 16 here: the ridge,
+    # 1e-9 of the trace, sets the small eigenvalues, measured 2.5e-8 relative)
+    X, P, Z0, _, _ = host_problem(dims, ranks, 0.4, 3, F32, reconstruct=tr.reconstruct)
+    prob = device_problem(X, P, dims, ranks, F32)
+    cores = device_cores(Z0, F32)
+    for k in range(len(dims)):
+        for seed, t, J in ((1, 0, 777), (9, 4, 64)):
+            rows, w = prob.sample_leverage(cores, k, seed, t, J)
+            r_ref, w_ref, _ = aw.leverage_rows(Z0, k, J, seed, t)
+            np.testing.assert_array_equal(rows.cpu().numpy(), r_ref)
+            np.testing.assert_allclose(w.cpu().numpy(), w_ref, rtol=wtol)
+
+
+@pytest.mark.parametrize("dims,ranks,sizes", SHAPES)
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_leverage_step_and_grad_match_oracle(dims, ranks, sizes, dtype):
+    X, P, Z0, _, _ = host_problem(dims, ranks, 0.4, 0, dtype, reconstruct=tr.reconstruct)
+    prob = device_problem(X, P, dims, ranks, dtype)
+    prob.set_variant("scaled", "global", "leverage")
+    sigma, seed, t = 0.9, 11, 2
+    for k in range(len(dims)):
+        J = _J(dims, sizes, k)
+        sk, _ = trd.make_sketch(sizes, seed, t)
+        # trd_grad draws with the ridge 1e-9, trd_step with its lambda_rel (here 1e-9 too)
+        rows, w, _ = aw.leverage_rows(Z0, k, J, seed, t, 1e-9)
+        ref, info = aw.core_update(X, P, Z0, k, sigma, 1e-9, rows=rows, row_weights=w)
+        d, stats = prob.grad(device_cores(Z0, dtype), k, sigma, sketch=sk)
+        got_d = unflatten_d(d.cpu().numpy(), ranks[k], dims[k], ranks[(k + 1) % len(dims)])
+        assert rel(got_d, info.d) <= 3 * TOL[dtype], (k, rel(got_d, info.d))
+        assert stats[2].item() == info.n_obs
+        assert stats[0].item() == pytest.approx(info.loss, rel=1e-5 if dtype == F32 else 1e-10)
+        cores = device_cores(Z0, dtype)
+        eta, flags = prob.step(cores, k, sigma, 1e-9, sketch=sk)
+        got = host_cores(cores, dims, ranks)
+        assert int(flags) == 0
+        assert rel(got[k], ref) <= TOL[dtype], (k, rel(got[k], ref))
+        assert float(eta) == pytest.approx(info.eta, rel=1e-4 if dtype == F32 else 1e-9)
+
+
+@pytest.mark.parametrize("mode", ["given", "quantile"])
+def test_leverage_fit_matches_oracle(mode):
+    # FP64: the leverages of updated cores agree to rounding, so every draw agrees
+    dims, ranks = (40, 36, 30, 24), (3, 3, 2, 2)
+    X, P, Z0, _, _ = host_problem(dims, ranks, 0.5, 1, F64, reconstruct=tr.reconstruct)
+    prob = device_problem(X, P, dims, ranks, F64)
+    prob.set_variant("scaled", "global", "leverage")
+    sizes, seed, sig = (10, 8, 9, 7), 7, [2.0, 1.2, 0.9]
+    kw = dict(sigma_mode="given", sigma_given=sig) if mode == "given" else {}
+    cores = device_cores(Z0, F64)
+    rep = prob.fit(cores, max_sweeps=3, tol=0.0, sketch_sizes=sizes, seed=seed, **kw)
+    ref, hist = aw.fit(X, P, Z0, aw.FitOptions(max_sweeps=3, tol=0.0, sketch_sizes=sizes, seed=seed,
+                                               sampling="leverage", **kw))
+    got = host_cores(cores, dims, ranks)
+    err = max(rel(g, r) for g, r in zip(got, ref))
+    print(f"leverage {mode} fit: core error {err:.2e}")
+    assert err <= (1e-9 if mode == "given" else 1e-5), err
+    for a, b in zip(rep["sigma"], hist["sigma"]):
+        assert a == pytest.approx(b, rel=1e-6)
