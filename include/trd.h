@@ -214,6 +214,10 @@ int trd_fgmc_gram_noalloc(int N, const int64_t* dims, const int32_t* ranks, int 
  * Z_k <- Z_k + eta * fold(h) (sign reading: d is the negative gradient, eta the
  * minimiser along +h).  cores[k] is updated in place.  eta_dev (optional device
  * double) receives eta; flags_dev (optional device uint32) is OR-ed with TRD_FLAG_*.
+ * TR-ALS as a special case: on a fully observed tensor (P = 1) with sigma = +inf and
+ * lambda_rel = 0 the step lands on the least-squares core X_[k] A (A^T A)^{-1} of one ALS
+ * update (eta = 1), so trd_fit with TRD_SIGMA_FIXED, sigma = +inf and lambda_rel = 0 runs
+ * TR-ALS sweeps.
  */
 int trd_step(trd_ctx* ctx, void* const* cores, int k, double sigma, double lambda_rel,
              const trd_sketch* sketch, double* eta_dev, uint32_t* flags_dev, void* stream);
