@@ -411,24 +411,22 @@ def test_sample_mask_bit_exact(seed, dims, rho, block, frac):
 
 
 @pytest.mark.parametrize("dims,ranks", [((20, 18, 16), (3, 3, 3)), ((9, 10, 11, 8), (2, 3, 2, 2))])
-def test_full_ls_step_is_tr_als(dims, ranks):
-    # P = 1, sigma = inf, lambda = 0: the step lands on the ALS core X_[k] A (A^T A)^{-1},
-    # solved here by least squares on the explicit unfoldings (Thm. 1), with eta = 1
+def test_fit_with_the_als_options_runs_tr_als_sweeps(dims, ranks):
+    # trd_fit with P = 1, sigma = inf, lambda = 0 runs TR-ALS: two sweeps equal two sweeps of
+    # per-core least-squares solves on the explicit unfoldings (Thm. 1), every eta = 1
     g = np.random.default_rng(5)
     X = g.standard_normal(dims)
     P = np.ones(dims, dtype=np.uint8)
     Z0 = synth.init_cores(dims, ranks, 5)
     prob = device_problem(X, P, dims, ranks, F64)
-    for k in range(len(dims)):
-        cores = device_cores(Z0, F64)
-        eta, flags = prob.step(cores, k, math.inf, 0.0)
-        A = tr.subchain_unfolding(Z0, k)
-        sol, *_ = np.linalg.lstsq(A, tr.unfold_cyclic(X, k).T, rcond=None)
-        als = tr.fold_core(sol.T, ranks[k], ranks[(k + 1) % len(dims)])
-        assert int(flags) == 0
-        assert float(eta) == pytest.approx(1.0, rel=1e-9)
-        assert rel(host_cores(cores, dims, ranks)[k], als) <= 1e-9, k
-    # and trd_fit with these options runs ALS sweeps: every update has eta = 1
-    rep = prob.fit(device_cores(Z0, F64), max_sweeps=5, tol=0.0, sigma_mode="fixed", sigma=math.inf,
-                   lambda_rel=0.0)
+    cores = device_cores(Z0, F64)
+    rep = prob.fit(cores, max_sweeps=2, tol=0.0, sigma_mode="fixed", sigma=math.inf, lambda_rel=0.0)
+    Z = [z.copy() for z in Z0]
+    for _ in range(2):
+        for k in range(len(dims)):
+            A = tr.subchain_unfolding(Z, k)
+            sol, *_ = np.linalg.lstsq(A, tr.unfold_cyclic(X, k).T, rcond=None)
+            Z[k] = tr.fold_core(sol.T, ranks[k], ranks[(k + 1) % len(dims)])
+    got = host_cores(cores, dims, ranks)
+    assert max(rel(a, b) for a, b in zip(got, Z)) <= 1e-8
     assert all(abs(e - 1.0) < 1e-9 for sweep in rep["eta"] for e in sweep)
