@@ -459,19 +459,23 @@ __global__ __launch_bounds__(256) void k_core_gram(const real* __restrict__ Z, i
   C[t] = acc;
 }
 
+// one wave per slice: lane p forms (C^{-1} z)_p for p = lane, lane + 64, ...; the wave sums
+// z_p (C^{-1} z)_p
 template <typename real>
 __global__ __launch_bounds__(256) void k_leverage(const real* __restrict__ Z, int64_t I, int R,
                                                   const double* __restrict__ Ci, double* __restrict__ lev) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= I) return;
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= I) return;  // whole waves (no barrier below)
   const real* z = Z + i * R;
   double acc = 0.0;
-  for (int p = 0; p < R; ++p) {
+  for (int p = lane; p < R; p += 64) {
     double y = 0.0;
     for (int q = 0; q < R; ++q) y = fma(Ci[p * R + q], (double)z[q], y);
     acc = fma((double)z[p], y, acc);
   }
-  lev[i] = acc;
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) lev[i] = acc;
 }
 
 // running sums of lev in slice order, one work-group: each thread sums a contiguous run
@@ -549,7 +553,7 @@ hipError_t launch_leverage_mode(int dtype, const void* Z, int64_t I, int R, doub
   if (e != hipSuccess) return e;
   e = launch_inverse(C, Ci, R, lambda_rel, flags, st);
   if (e != hipSuccess) return e;
-  const unsigned lb = (unsigned)((I + 255) / 256);
+  const unsigned lb = (unsigned)((I + 3) / 4);
   if (dtype == 0)
     hipLaunchKernelGGL(k_leverage<float>, dim3(lb), dim3(256), 0, st, (const float*)Z, I, R, Ci, lev);
   else

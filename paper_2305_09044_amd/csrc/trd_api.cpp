@@ -42,6 +42,10 @@ struct SketchWS {
   int64_t cap_lev[kMaxN] = {0};
   double* colw = nullptr;
   int64_t cap_colw = 0;
+  // inside trd_fit: lev[j] / cdf[j] hold core j's distribution as it stands (a core's
+  // leverage changes only with the core, once per sweep)
+  bool lev_cache = false;
+  bool lev_valid[kMaxN] = {false};
 };
 
 }  // namespace
@@ -498,9 +502,11 @@ int sample_leverage(trd_ctx* ctx, const void* const* cores, int k, uint64_t seed
       TRY(alloc_n(ctx, &W.cdf[j], ctx->dims[j]));
       W.cap_lev[j] = ctx->dims[j];
     }
+    if (W.lev_cache && W.lev_valid[j]) continue;
     const int R = ctx->ranks[j] * ctx->ranks[(j + 1) % N];
     CK(launch_leverage_mode(ctx->dtype, cores[j], ctx->dims[j], R, W.levC, W.levCi, lambda_rel, W.lev[j],
                             W.cdf[j], ctx->flags + 3, st));
+    W.lev_valid[j] = W.lev_cache;
   }
   CK(launch_sample_leverage(seed, t, k, N, ctx->dims, W.lev, W.cdf, J, off, row, weight, st));
   return TRD_OK;
@@ -1545,9 +1551,12 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
   // fit (a later step or backward on core 0 must form its own)
   struct FitGuard {
     trd_ctx* c; int saved;
-    ~FitGuard() { c->prec = saved; c->resid_core = -1; }
+    ~FitGuard() { c->prec = saved; c->resid_core = -1; c->sk.lev_cache = false; }
   } guard{ctx, ctx->prec};
   ctx->prec = o->precision;
+  // leverage distributions are kept between updates of this fit (every core starts stale)
+  ctx->sk.lev_cache = true;
+  for (int j = 0; j < kMaxN; ++j) ctx->sk.lev_valid[j] = false;
   int cur = 0;
   struct HostRead { double sigma; double conv[2]; uint32_t flags; uint32_t pad; } hr;
   std::vector<double> etas(N);
@@ -1603,6 +1612,7 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
     }
     for (int k = 0; k < N; ++k) {
       TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st));
+      ctx->sk.lev_valid[k] = false;  // core k changed
       TRY(refresh_K(ctx, (const void* const*)cores, k, st));
     }
     // convergence matrix with G^{!=N} of the full cores (it does not involve core N): the
