@@ -64,11 +64,16 @@ def src_hash(precision: str = "fp32") -> str:
     return h.hexdigest()[:16]
 
 
+def noise_seed(seed: int, stream: int) -> int:
+    """Seed of the uniform stream `stream` (1, 2) of a workload's additive noise."""
+    return (int(seed) ^ (0x4E4F495345000000 + stream)) & ((1 << 64) - 1)
+
+
 def build_inputs(wname: str, seed: int, dims=None):
     """Seeded workload on the device: the clean tensor X* from the library's reconstruction
     of seeded Gaussian cores (synth), additive noise, then the mask, the outlier selection
-    and the outlier values from trd_sample_mask.  Returns (workload, dims, X, mask, X*,
-    true cores (host))."""
+    and the outlier values, every random number from the counter generator of
+    trd_sample_mask.  Returns (workload, dims, X, mask, X*, true cores (host))."""
     import numpy as np
     import torch
     import synth
@@ -96,8 +101,15 @@ def build_inputs(wname: str, seed: int, dims=None):
                                      uniforms=want_out)
     X = xs.clone()
     if w.noise_var > 0:
-        g = torch.Generator(device="cuda").manual_seed(int(seed) + 4)
-        X += torch.randn(X.shape, generator=g, device="cuda", dtype=X.dtype) * math.sqrt(w.noise_var)
+        # N(0, noise_var) by Box-Muller from two per-entry uniform streams of the same counter
+        # generator (noise seeds derived from the workload seed), so that any entry's value
+        # can be recomputed from the seed alone
+        _, _, u1 = trd.trd_sample_mask(noise_seed(seed, 1), dims, 1.0, 0, 0.0, uniforms=True)
+        _, _, u2 = trd.trd_sample_mask(noise_seed(seed, 2), dims, 1.0, 0, 0.0, uniforms=True)
+        z = torch.sqrt(-2.0 * torch.log1p(-u1)) * torch.cos((2.0 * math.pi) * u2)
+        del u1, u2
+        X += (z * math.sqrt(w.noise_var)).to(X.dtype)
+        del z
     if want_out:
         selb = sel.bool()
         del sel

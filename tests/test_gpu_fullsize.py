@@ -1,7 +1,10 @@
 """Parity at the workloads' full sizes, in the configurations bench.py times.
 
-The oracle cannot unfold these tensors, so it computes sampled outputs one at a time from
-the same seeded inputs (built exactly as bench.py builds them):
+The oracle cannot unfold these tensors, so it computes sampled outputs one at a time.  The
+device problem is built exactly as bench.py builds it; the oracle's inputs are recomputed
+on the host from the seed alone (tests/_inputs.py: its own reconstruction and its own
+counter generator), never read back from the device, and the two are checked against each
+other at sampled entries (mask bit for bit, values to FP32 rounding).  Outputs compared:
   * reconstructed entries (Def. 1) at a uniform sample of positions;
   * whole gradient rows of eq. (9) from the observed entries of a slice (gradient_row);
   * the FGMC Gram matrix (eq. 13, cheap at any size) against the explicit sum of
@@ -26,6 +29,7 @@ from oracle import awrtrd as aw  # noqa: E402
 from oracle import rng as orng  # noqa: E402
 from oracle import tr  # noqa: E402
 from _helpers import rel  # noqa: E402
+from _inputs import OracleInputs  # noqa: E402
 
 import paper_2305_09044_amd as trd  # noqa: E402
 
@@ -38,10 +42,11 @@ class Full:
         self.w, self.dims, self.seed = w, tuple(dims), seed
         self.prob = trd.Problem(Xd, Pd, dims, w.ranks)
         self.Xd, self.Pd, self.xs = Xd, Pd, xs
-        self.X = Xd.cpu().numpy()               # column-major flat, FP32
-        self.mask = Pd.cpu().numpy().reshape(dims, order="F")   # host, shaped
+        self.n = int(np.prod(dims))
+        self.oin = OracleInputs(name, seed)
         # the start of a fit, or (the differentiation form) the true cores perturbed
-        Z = synth.perturbed_cores(cores_t, seed, rel=0.1) if perturbed else synth.init_cores(dims, w.ranks, seed)
+        Z = (synth.perturbed_cores(self.oin.cores, seed, rel=0.1) if perturbed
+             else synth.init_cores(dims, w.ranks, seed))
         self.Z = [z.astype(np.float32).astype(np.float64) for z in Z]
         self.cores = [torch.from_numpy(f).cuda() for f in synth.cores_to_flat(self.Z, np.float32)]
         self.strides = np.cumprod((1,) + self.dims[:-1])
@@ -55,22 +60,35 @@ class Full:
         return self._rows[key]
 
     def slice_entries(self, k, i):
-        """Indices (n, N) and values of the observed entries with i_k = i."""
-        sub = np.take(self.mask, i, axis=k)
-        rest = np.argwhere(sub != 0)
-        idx = np.insert(rest, k, i, axis=1).astype(np.int64)
-        lin = idx @ self.strides
-        return idx, self.X[lin].astype(np.float64)
+        """Indices (n, N) and values of the observed entries with i_k = i (host recipe)."""
+        idx = self.oin.mask_of_slice(k, i)
+        _, vals = self.oin.entries(idx)
+        return idx, vals
+
+    def check_inputs(self, n=1 << 16, seed=3):
+        """device mask == host mask bit for bit, device X == host X to FP32 rounding, at a
+        uniform sample of entries"""
+        lin = np.random.default_rng(seed).integers(0, self.n, n)
+        idx = np.stack(np.unravel_index(lin, self.dims, order="F"), axis=1)
+        obs, vals = self.oin.entries(idx)
+        li = torch.from_numpy(lin).cuda()
+        np.testing.assert_array_equal(self.Pd[li].cpu().numpy(), obs)
+        got = self.Xd[li].cpu().numpy().astype(np.float64)
+        scale = float(np.max(np.abs(vals)))
+        err = float(np.max(np.abs(got - vals))) / scale
+        assert err <= 1e-6, err
+        return obs, vals
 
     def close(self):
         self.prob.close()
-        del self.prob, self.Xd, self.Pd, self.xs, self.cores
+        del self.prob, self.Xd, self.Pd, self.xs, self.cores, self.oin
         torch.cuda.empty_cache()
 
 
 @pytest.fixture(scope="module")
 def cfg_prec():
     f = Full("tr5_60_r8")
+    f.check_inputs()
     yield f
     f.close()
 
@@ -159,6 +177,7 @@ def test_sketch_workloads_full_size(name):
     # RStS at the workloads' sketch sizes: index sets bit-exact, sketched gradient complete
     f = Full(name)
     try:
+        f.check_inputs()
         sizes = list(f.w.sketch)
         sigma = 0.5
         for t, k in ((0, 0), (3, len(f.dims) - 1)):
@@ -168,14 +187,13 @@ def test_sketch_workloads_full_size(name):
                 assert got[j].cpu().numpy().tolist() == ref[j]
             sk, _ = trd.make_sketch(sizes, 11, t)
             d, stats = f.prob.grad(f.cores, k, sigma, sketch=sk)
-            ix = np.ix_(*[np.asarray(s, dtype=np.int64) for s in ref])
-            lin = np.zeros([len(s) for s in ref], dtype=np.int64)
-            for j, s in enumerate(ref):
-                shape = [1] * len(f.dims)
-                shape[j] = len(s)
-                lin = lin + (np.asarray(s, dtype=np.int64) * f.strides[j]).reshape(shape)
-            Xs = f.X[lin].astype(np.float64)
-            Ps = f.mask[ix]
+            # the sketched subtensor from the host recipe (column-major over the sketch)
+            grid = np.meshgrid(*[np.asarray(s, dtype=np.int64) for s in ref], indexing="ij")
+            idx = np.stack([g.ravel(order="F") for g in grid], axis=1)
+            obs, vals = f.oin.entries(idx)
+            shape = [len(s) for s in ref]
+            Xs = vals.reshape(shape, order="F")
+            Ps = obs.reshape(shape, order="F")
             cs = [z[:, np.asarray(s), :] for z, s in zip(f.Z, ref)]
             _, info = aw.core_update(Xs, Ps, cs, k, sigma)
             r, r2 = f.w.ranks[k], f.w.ranks[(k + 1) % len(f.dims)]
@@ -189,6 +207,7 @@ def test_sketch_workloads_full_size(name):
 @pytest.fixture(scope="module")
 def cfg_diff():
     f = Full("tr4_200_r10", perturbed=True)
+    f.check_inputs()
     yield f
     f.close()
 
@@ -199,14 +218,14 @@ def test_differentiation_workload_pattern_bit_exact(cfg_diff):
     f = cfg_diff
     w = f.w
     g = np.random.default_rng(3)
-    lin = g.integers(0, f.X.size, 1 << 16)
+    lin = g.integers(0, f.n, 1 << 16)
     m, sel, u = orng.sample_mask_at(f.seed, f.dims, w.rho, 0, w.outlier_frac, lin)
-    np.testing.assert_array_equal(f.mask.ravel(order="F")[lin], m)
-    xs = f.xs.cpu().numpy()
+    li = torch.from_numpy(lin).cuda()
+    np.testing.assert_array_equal(f.Pd[li].cpu().numpy(), m)
     # where an observed entry was not selected as an outlier it keeps its clean value
     keep = (m == 1) & (sel == 0)
-    np.testing.assert_array_equal(f.X[lin][keep], xs[lin][keep])
-    assert abs(f.prob.info()["n_obs"] / f.X.size - w.rho) < 1e-4
+    np.testing.assert_array_equal(f.Xd[li].cpu().numpy()[keep], f.xs[li].cpu().numpy()[keep])
+    assert abs(f.prob.info()["n_obs"] / f.n - w.rho) < 1e-4
 
 
 @pytest.mark.parametrize("prec,bar", [("native", 1e-4), ("bf16", 2e-2)])
