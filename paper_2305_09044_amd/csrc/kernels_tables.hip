@@ -337,6 +337,82 @@ __global__ void k_pack(const real* __restrict__ in, int64_t is, const int32_t* _
   }
 }
 
+// ---------------------------------------------------------------- whole-tensor product
+// The full reconstruction as one product of the two subchain tables of core 0: with rows
+// (i_0, B modes) and columns (C modes) in little-endian order, entry (row, col) of
+// T V^T is x at linear index row + nrows * col, so the column-major tensor is the
+// column-major nrows x ncols product.  64 x 64 output tiles, the shared dimension staged
+// through LDS 32 at a time; each thread holds a 4 x 4 block (4 consecutive rows of 4
+// columns) and stores its rows as one contiguous run.
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_table_product(const real* __restrict__ T, const real* __restrict__ V,
+                                                       int64_t nrows, int64_t ncols, int RRP, int64_t nbr,
+                                                       real* __restrict__ out) {
+  constexpr int TM = 64, KC = 32;
+  __shared__ real Ts[KC][TM + 1];
+  __shared__ real Vs[KC][TM + 1];
+  const int64_t br = blockIdx.x % nbr, bc = blockIdx.x / nbr;
+  const int64_t r0 = br * TM, c0 = bc * TM;
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  real acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = real(0);
+  for (int k0 = 0; k0 < RRP; k0 += KC) {
+    // 64 items x 32 values of each table, 8 per thread, consecutive threads along k
+    for (int e = threadIdx.x; e < TM * KC; e += 256) {
+      const int it = e / KC, kk = e % KC;
+      const int k = k0 + kk;
+      const int64_t r = r0 + it, c = c0 + it;
+      Ts[kk][it] = (r < nrows && k < RRP) ? T[r * RRP + k] : real(0);
+      Vs[kk][it] = (c < ncols && k < RRP) ? V[c * RRP + k] : real(0);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < KC; ++kk) {
+      real a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = Ts[kk][4 * tr + i];
+        b[i] = Vs[kk][4 * tc + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t c = c0 + 4 * tc + j;
+    if (c >= ncols) continue;
+    real* o = out + c * nrows;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + 4 * tr + i;
+      if (r < nrows) o[r] = acc[i][j];
+    }
+  }
+}
+
+hipError_t launch_table_product(int dtype, const void* T, const void* V, int64_t nrows, int64_t ncols,
+                                int RRP, void* out, hipStream_t st) {
+  if (nrows <= 0 || ncols <= 0) return hipSuccess;
+  const int64_t nbr = (nrows + 63) / 64, nbc = (ncols + 63) / 64;
+  if (nbr * nbc >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const dim3 g((unsigned)(nbr * nbc)), b(256);
+  if (dtype != 0)  // FP64
+    hipLaunchKernelGGL(k_table_product<double>, g, b, 0, st, (const double*)T, (const double*)V, nrows, ncols,
+                       RRP, nbr, (double*)out);
+  else
+    hipLaunchKernelGGL(k_table_product<float>, g, b, 0, st, (const float*)T, (const float*)V, nrows, ncols,
+                       RRP, nbr, (float*)out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- sampled-fibre chains
 // Column table of a uniform row sample: every sampled column n carries its own multi-index,
 // so the product of the N - 1 slices is formed per column (no shared partial products).

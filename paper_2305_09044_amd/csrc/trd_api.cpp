@@ -1437,13 +1437,36 @@ int trd_reconstruct(trd_ctx* ctx, const void* const* cores, const int64_t* lin_i
   TRY(check_cores(ctx, cores));
   if (!out && n > 0) return fail(ctx, TRD_EINVAL, "out is NULL");
   if (n < 0) return fail(ctx, TRD_EINVAL, "n < 0");
+  hipStream_t st = (hipStream_t)stream;
   if (!lin_idx) {
     int64_t tot = 1;
     for (int j = 0; j < ctx->N; ++j) tot *= ctx->dims[j];
     if (n != tot) return fail(ctx, TRD_EINVAL, "n must equal prod(dims) when lin_idx is NULL");
+    // the whole tensor: one product of core 0's two subchain tables (Def. 2 halves)
+    Update up;
+    int64_t nrows, ncols;
+    int ct_w, n_ct;
+    if (plan_split(ctx, 0, ctx->dims, up.sp, nrows, ncols, ct_w, n_ct) == TRD_OK) {
+      for (int j = 0; j < ctx->N; ++j) {
+        up.cnt[j] = ctx->dims[j];
+        up.lst[j] = nullptr;
+      }
+      up.counts = up.cnt;
+      up.lists = nullptr;
+      int64_t needT, needV, needU, needC;
+      table_needs(ctx, up.sp, up.cnt, nrows, ncols, needT, needV, needU, needC);
+      TRY(ensure_tables(ctx, needT, needV, needU, needC));
+      ItemRef Uref;
+      int64_t nB;
+      TRY(build_U(ctx, up, cores, Uref, nB, st));
+      TRY(build_rowtable(ctx, up, cores[0], Uref, nB, ctx->T, st));
+      TRY(build_coltable(ctx, up, cores, st));
+      CK(launch_table_product(ctx->dtype, ctx->T, ctx->V, nrows, ncols, up.sp.RRP, out, st));
+      return TRD_OK;
+    }
+    ctx->err.clear();  // no split with r_0 r_s <= 128: one chain per entry below
   }
-  CK(launch_reconstruct(ctx->dtype, ctx->N, ctx->dims, ctx->ranks, cores, lin_idx, n, out,
-                        (hipStream_t)stream));
+  CK(launch_reconstruct(ctx->dtype, ctx->N, ctx->dims, ctx->ranks, cores, lin_idx, n, out, st));
   return TRD_OK;
 }
 

@@ -159,6 +159,10 @@ hipError_t launch_merge(int dtype, ItemRef L, int64_t nL, int rA, int rB, ItemRe
 hipError_t launch_chain_cols(int dtype, const void* const* cores, int N, int k, const int32_t* ranks,
                              const int64_t* dims, const int64_t* strides, const int64_t* off,
                              int64_t J, void* out, int64_t out_stride, hipStream_t st);
+// out (column-major nrows x ncols, the whole tensor) = T V^T of the two subchain tables of
+// core 0 (rows of RRP values each)
+hipError_t launch_table_product(int dtype, const void* T, const void* V, int64_t nrows, int64_t ncols,
+                                int RRP, void* out, hipStream_t st);
 hipError_t launch_pack(int dtype, ItemRef in, int64_t n, int rA, int rB, void* out,
                        int64_t out_stride, int transpose_out, hipStream_t st,
                        bool bf16_out = false, void* out_lo = nullptr);
