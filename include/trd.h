@@ -58,6 +58,8 @@ extern "C" {
 #define TRD_FLAG_EMPTY     1u /* the update touched no observed entry: eta = 0 */
 #define TRD_FLAG_ZERO_DEN  2u /* line-search denominator <= 0 or not finite: eta = 0 */
 #define TRD_FLAG_NOTSPD    4u /* G + lambda I not positive definite: h = 0, eta = 0 */
+#define TRD_FLAG_CLAMPED   8u /* a caller's sketch index list (trd_sketch.idx) held indices
+                                 outside [0, I_j): they were clamped into range */
 
 /* kernel-width schedule modes for trd_fit */
 #define TRD_SIGMA_FIXED    0

@@ -32,7 +32,7 @@ DIRECTIONS = {"scaled": TRD_DIR_SCALED, "gradient": TRD_DIR_GRADIENT}
 GRAMS = {"global": TRD_GRAM_GLOBAL, "local": TRD_GRAM_LOCAL}
 TRD_SAMPLE_RSTS, TRD_SAMPLE_ROWS, TRD_SAMPLE_LEVERAGE = 0, 1, 2
 SAMPLINGS = {"rsts": TRD_SAMPLE_RSTS, "rows": TRD_SAMPLE_ROWS, "leverage": TRD_SAMPLE_LEVERAGE}
-TRD_FLAG_EMPTY, TRD_FLAG_ZERO_DEN, TRD_FLAG_NOTSPD = 1, 2, 4
+TRD_FLAG_EMPTY, TRD_FLAG_ZERO_DEN, TRD_FLAG_NOTSPD, TRD_FLAG_CLAMPED = 1, 2, 4, 8
 TRD_SIGMA_FIXED, TRD_SIGMA_GIVEN, TRD_SIGMA_QUANTILE = 0, 1, 2
 
 _NAMES = {0: "TRD_OK", -1: "TRD_EINVAL", -2: "TRD_ENOMEM", -3: "TRD_EDEVICE", -4: "TRD_ENOTSPD",

@@ -34,14 +34,14 @@ hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-// out[i] = in[i] clamped into [0, dim); any clamped entry raises *bad
+// out[i] = in[i] clamped into [0, dim); any clamped entry sets TRD_FLAG_CLAMPED in *bad
 __global__ void k_copy_clamp(const int32_t* __restrict__ in, int64_t n, int64_t dim,
                              int32_t* __restrict__ out, uint32_t* bad) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     int64_t v = in[i];
     if (v < 0 || v >= dim) {
-      atomicOr(bad, 1u);
+      atomicOr(bad, TRD_FLAG_CLAMPED_BIT);
       v = v < 0 ? 0 : dim - 1;
     }
     out[i] = (int32_t)v;

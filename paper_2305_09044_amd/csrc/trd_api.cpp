@@ -428,7 +428,7 @@ int prepare_sketch(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStr
   if (sk->idx) {
     // copy the caller's lists into the workspace, clamped into range (never read out of bounds)
     for (int j = 0; j < N; ++j)
-      if (j != k) CK(launch_copy_clamp(sk->idx[j], up.cnt[j], ctx->dims[j], W.idx[j], ctx->flags + 2, st));
+      if (j != k) CK(launch_copy_clamp(sk->idx[j], up.cnt[j], ctx->dims[j], W.idx[j], ctx->flags, st));
     for (int j = 0; j < N; ++j) up.lst[j] = j == k ? nullptr : W.idx[j];
   } else {
     int32_t sizes[kMaxN];
@@ -1038,11 +1038,11 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
             double* eta_user, uint32_t* flags_user, hipStream_t st) {
   Update up;
   ctx->lev_lambda = lambda_rel;
+  CK(launch_zero(ctx->flags, sizeof(uint32_t), st));  // before the sketch (it may flag clamping)
   TRY(prepare_update(ctx, k, sk, up, st, cores));
   const Split& sp = up.sp;
   const int64_t Ik = ctx->dims[k];
   const int R = sp.r_k * sp.r_k1;
-  CK(launch_zero(ctx->flags, sizeof(uint32_t), st));
   // the unscaled direction (h = d) needs no Gram; the local Gram (sampled cores) differs
   // from the global one only under a sketch
   const bool scaled = ctx->direction == TRD_DIR_SCALED;

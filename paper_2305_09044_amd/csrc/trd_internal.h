@@ -27,6 +27,7 @@ __host__ __device__ inline int64_t slot_of(int64_t base, int t, int lane) {
 constexpr uint32_t TRD_FLAG_EMPTY_BIT = 1u;     // mirrors TRD_FLAG_EMPTY
 constexpr uint32_t TRD_FLAG_ZERO_DEN_BIT = 2u;  // mirrors TRD_FLAG_ZERO_DEN
 constexpr uint32_t TRD_FLAG_NOTSPD_BIT = 4u;    // mirrors TRD_FLAG_NOTSPD
+constexpr uint32_t TRD_FLAG_CLAMPED_BIT = 8u;   // mirrors TRD_FLAG_CLAMPED
 
 // largest dynamic LDS a work-group may request, and the compute-unit count (both set from
 // the device at context creation)

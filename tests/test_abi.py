@@ -119,6 +119,7 @@ def test_header_constants_match_the_binding():
                   for m in re.finditer(r"#define\s+(TRD_\w+)\s+(-?\d+)", txt))
     for name in ("TRD_OK", "TRD_EINVAL", "TRD_PREC_NATIVE", "TRD_PREC_BF16", "TRD_PREC_BF16X3",
                  "TRD_SIGMA_FIXED", "TRD_SIGMA_GIVEN", "TRD_SIGMA_QUANTILE", "TRD_DIR_SCALED",
+                 "TRD_FLAG_CLAMPED", "TRD_SAMPLE_RSTS", "TRD_SAMPLE_ROWS", "TRD_SAMPLE_LEVERAGE",
                  "TRD_DIR_GRADIENT", "TRD_GRAM_GLOBAL", "TRD_GRAM_LOCAL"):
         assert getattr(_lib, name) == consts[name], name
 

@@ -157,6 +157,26 @@ def test_step_sketch(explicit):
         assert float(eta) == pytest.approx(info.eta, rel=1e-4)
 
 
+def test_step_sketch_clamps_out_of_range_caller_lists_and_flags_them():
+    # a caller's list with indices outside [0, I_j): the step runs on the clamped lists and
+    # raises TRD_FLAG_CLAMPED (the same lists in range give the same core, without the flag)
+    dims, ranks = (30, 25, 20), (2, 3, 2)
+    X, P, Z0, prob = _setup(dims, ranks, rho=0.5)
+    bad = [None, torch.tensor([-3, 4, 7, 40], dtype=torch.int32, device="cuda"),
+           torch.tensor([0, 5, 19, 25], dtype=torch.int32, device="cuda")]
+    good = [None, torch.tensor([0, 4, 7, 24], dtype=torch.int32, device="cuda"),
+            torch.tensor([0, 5, 19, 19], dtype=torch.int32, device="cuda")]
+    a, b = device_cores(Z0, F32), device_cores(Z0, F32)
+    sk, keep = trd.make_sketch((30, 4, 4), 3, 0, bad)
+    _, fa = prob.step(a, 0, 0.9, sketch=sk)
+    sk2, keep2 = trd.make_sketch((30, 4, 4), 3, 0, good)
+    _, fb = prob.step(b, 0, 0.9, sketch=sk2)
+    assert int(fa) & trd.TRD_FLAG_CLAMPED and not int(fb) & trd.TRD_FLAG_CLAMPED
+    assert torch.equal(a[0], b[0])
+    _, fc = prob.step(device_cores(Z0, F32), 0, 0.9)   # the next step starts clean
+    assert not int(fc) & trd.TRD_FLAG_CLAMPED
+
+
 ORACLE_GRAM = {"global": "fgmc", "local": "local"}
 
 
