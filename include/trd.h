@@ -283,7 +283,8 @@ int trd_sample_rows(uint64_t seed, int t, int k, int N, const int64_t* dims, int
  * lambda = lambda_rel tr(C) / (r_j r_{j+1}); sample n takes the uniform
  * u = (u(key_j, n) >> 11) 2^-53 with key_j = u(u(u(seed ^ 0x4C45564500000000, t), k), j) (u as
  * at trd_sample_sketch) and the first slice i whose running sum l(0) + ... + l(i) in FP64
- * exceeds u times the total.  Its row has probability p = prod_j l(i_j) / total_j.
+ * exceeds u times the total (a core whose leverages are all zero: the slice floor(u I_j)).
+ * Its row has probability p = prod_j l(i_j) / total_j (1 / I_j for such a core).
  * rows_out (device, J int64): row indices as at trd_sample_rows; weights_out (device, J FP64):
  * the importance weights 1 / (J p).  ctx needs a shape; cores: N device pointers.
  */

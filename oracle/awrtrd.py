@@ -139,6 +139,8 @@ def core_leverage(Z: np.ndarray, lambda_rel: float = 1e-9) -> np.ndarray:
     Z2 = unfold_core(Z)
     C = Z2.T @ Z2
     R = C.shape[0]
+    if not np.trace(C) > 0.0:                            # a zero core: no leverage
+        return np.zeros(Z2.shape[0])
     lam = lambda_rel * np.trace(C) / R
     Y = np.linalg.solve(C + lam * np.eye(R), Z2.T)      # (C + lam I)^{-1} z_i, column i
     return np.einsum("ip,pi->i", Z2, Y)
@@ -150,7 +152,8 @@ def leverage_rows(cores: Sequence[np.ndarray], k: int, J: int, seed: int, t: int
     every sample draws the index of each mode j != k independently, with probability
     q_j(i) = l_j(i) / sum_i l_j(i) from the leverage scores of core j, by inverse CDF of the
     running sums in slice order; its row has probability p = prod_j q_j(i_j) and importance
-    weight 1 / (J p).  Returns (rows (J,), weights (J,), per-mode indices (J, N))."""
+    weight 1 / (J p).  A core whose leverages are all zero (a zero core) is sampled
+    uniformly instead.  Returns (rows (J,), weights (J,), per-mode indices (J, N))."""
     N = len(cores)
     dims = [Z.shape[1] for Z in cores]
     idx = np.zeros((J, N), dtype=np.int64)
@@ -162,9 +165,13 @@ def leverage_rows(cores: Sequence[np.ndarray], k: int, J: int, seed: int, t: int
         cdf = np.cumsum(lev)
         total = cdf[-1]
         u = _rng.uniform01(_rng.lev_key(seed, t, k, j), np.arange(J))
-        ij = np.minimum(np.searchsorted(cdf, u * total, side="right"), dims[j] - 1)
+        if total > 0.0:
+            ij = np.minimum(np.searchsorted(cdf, u * total, side="right"), dims[j] - 1)
+            p *= lev[ij] / total
+        else:  # a zero core has no leverage: draw its index uniformly
+            ij = np.minimum(np.floor(u * dims[j]).astype(np.int64), dims[j] - 1)
+            p *= 1.0 / dims[j]
         idx[:, j] = ij
-        p *= lev[ij] / total
     rows = np.zeros(J, dtype=np.int64)
     stride = 1
     for s_ in range(1, N):

@@ -446,7 +446,8 @@ __global__ __launch_bounds__(256) void k_sample_rows(RowSampleArgs a) {
 // the running sums of l in slice order.  Sample n then draws, per mode, the uniform
 // u = (u64 >> 11) 2^-53 of u(key_j, n), key_j = u(u(u(seed ^ "LEVE", t), k), j), and takes the
 // first slice whose running sum exceeds u * total; its probability p multiplies over the
-// modes and the sample's weight is 1 / (J p).
+// modes and the sample's weight is 1 / (J p).  A zero core (its Gram is not positive
+// definite, the inverse comes back zero, every leverage is 0) is sampled uniformly.
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_core_gram(const real* __restrict__ Z, int64_t I, int R,
@@ -523,14 +524,21 @@ __global__ __launch_bounds__(256) void k_sample_leverage(LevArgs a) {
       const double* cdf = a.cdf[j];
       const double total = cdf[I - 1];
       const double u = (double)(counter_u64(counter_u64(base, (uint64_t)j), (uint64_t)n) >> 11) * 0x1p-53;
-      const double target = u * total;
-      int64_t lo = 0, hi = I;  // first slice whose running sum exceeds the target
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+      int64_t i;
+      if (total > 0.0) {
+        const double target = u * total;
+        int64_t lo = 0, hi = I;  // first slice whose running sum exceeds the target
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        i = lo < I ? lo : I - 1;
+        p *= a.lev[j][i] / total;
+      } else {  // a zero core has no leverage: its index is drawn uniformly
+        i = (int64_t)floor(u * (double)I);
+        i = i < I ? i : I - 1;
+        p *= 1.0 / (double)I;
       }
-      const int64_t i = lo < I ? lo : I - 1;
-      p *= a.lev[j][i] / total;
       off += i * a.strides[j];
       row += i * rs;
       rs *= I;

@@ -180,3 +180,16 @@ def test_leverage_fit_matches_oracle(mode):
     assert err <= (1e-9 if mode == "given" else 1e-5), err
     for a, b in zip(rep["sigma"], hist["sigma"]):
         assert a == pytest.approx(b, rel=1e-6)
+
+
+def test_sample_leverage_of_a_zero_core_is_uniform():
+    dims, ranks = (20, 18, 16), (2, 3, 2)
+    X, P, Z0, _, _ = host_problem(dims, ranks, 0.5, 4, F32, reconstruct=tr.reconstruct)
+    prob = device_problem(X, P, dims, ranks, F32)
+    Z = [z.copy() for z in Z0]
+    Z[1] = np.zeros_like(Z[1])
+    cores = device_cores(Z, F32)
+    rows, w = prob.sample_leverage(cores, 0, 6, 1, 999)
+    r_ref, w_ref, _ = aw.leverage_rows(Z, 0, 999, 6, 1)
+    np.testing.assert_array_equal(rows.cpu().numpy(), r_ref)
+    np.testing.assert_allclose(w.cpu().numpy(), w_ref, rtol=1e-10)

@@ -799,3 +799,15 @@ def test_leverage_fit_draws_from_the_current_cores():
     assert r_fit[0].size == 3 * 4
     assert not np.allclose(r_fit[1], r_old[1])        # weights follow the updated core 0
     assert len(hist["sigma"]) == 2 and np.isfinite(cores[1]).all()
+
+
+def test_leverage_of_a_zero_core_falls_back_to_uniform_draws():
+    dims, ranks = (4, 6, 5), (2, 2, 2)
+    Z = rand_cores(dims, ranks, 74)
+    Z[1] = np.zeros_like(Z[1])
+    rows, w, idx = aw.leverage_rows(Z, 0, 3000, 2, 0)
+    u = orng.uniform01(orng.lev_key(2, 0, 0, 1), np.arange(3000))
+    np.testing.assert_array_equal(idx[:, 1], np.floor(u * 6).astype(np.int64))
+    q2 = aw.core_leverage(Z[2]) / aw.core_leverage(Z[2]).sum()
+    np.testing.assert_allclose(w, 1.0 / (3000 * (1.0 / 6) * q2[idx[:, 2]]), rtol=1e-12)
+    assert np.isfinite(w).all()
