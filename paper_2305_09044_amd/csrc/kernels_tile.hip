@@ -54,13 +54,23 @@ struct TileArgs {
   float* vals;
   uint16_t* pos;
   int64_t nrows, ncols, n_chunks, n_blocks;
+  int64_t nB, Ik;  // B-major rows (bmaj): tile row b + nB i_k is layout row i_k + Ik b
+  int bmaj;
 };
+
+// layout row (the row tables' and the row offsets' order) of a tile row
+__device__ __forceinline__ int64_t layout_row(int64_t t, int bmaj, int64_t nB, int64_t Ik) {
+  if (!bmaj) return t;
+  const int64_t ik = t / nB;
+  return ik + Ik * (t - ik * nB);
+}
 
 static TileArgs targs(const TLayout& L) {
   TileArgs a;
   a.rowoff = L.rowoff; a.coloff = L.coloff; a.bcnt = L.bcnt; a.boff = L.boff;
   a.vals = L.vals; a.pos = L.pos;
   a.nrows = L.nrows; a.ncols = L.ncols; a.n_chunks = L.n_chunks; a.n_blocks = L.n_blocks;
+  a.nB = L.nB; a.Ik = L.Ik; a.bmaj = L.bmaj ? 1 : 0;
   return a;
 }
 
@@ -86,7 +96,7 @@ __global__ __launch_bounds__(256) void k_tblock(TileArgs a, const uint8_t* __res
     bool obs = false;
     int64_t off = 0;
     if (col_ok && row < a.nrows) {
-      off = a.rowoff[row] + co;
+      off = a.rowoff[layout_row(row, a.bmaj, a.nB, a.Ik)] + co;
       obs = mask[off] != 0;
     }
     const uint64_t bal = __ballot(obs);
@@ -178,7 +188,9 @@ size_t tpass_lds(int mode, int K, int CW) {
   (void)K;
   (void)CW;
   if (mode == kModeGrad || mode == kModeGradFast) return (size_t)kXBytes + kYBytes;
-  if (mode == kModeGradE) return (size_t)kYBytes;  // the y tiles only
+  // the y tiles, then the tiles of the row-factor reduction at the end of the walk (its own:
+  // the waves of a work-group finish their walks at different times)
+  if (mode == kModeGradE) return (size_t)kYBytes + kXBytes;
   if (mode == kModeLS) return (size_t)kXBytes;  // the q tile only
   if (mode == kModeResid) return (size_t)kXBytes + kQHistBytes;
   return (size_t)kXBytes;
@@ -203,7 +215,9 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(
   // block row, block offsets, loop bounds) in scalar registers
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l = threadIdx.x & 63, h = l >> 5, li = l & 31;
-  float* Xs = reinterpret_cast<float*>(smem_raw) + w * kXTile;
+  // (the pass that reads stored residuals keeps this tile after its y tiles, for the
+  // reduction at the end of the walk)
+  float* Xs = reinterpret_cast<float*>(smem_raw + (kGradE ? kYBytes : 0)) + w * kXTile;
   float* Qs = Xs;  // LS: the q tile in place of the xhat tile
   uint16_t* Ys = reinterpret_cast<uint16_t*>(smem_raw + (kRecon ? kXBytes : 0)) + w * kYTile;  // grad
   uint32_t* qh = reinterpret_cast<uint32_t*>(smem_raw + kXBytes);                     // resid
@@ -228,23 +242,24 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(
 #pragma unroll
   for (int n = 0; n < 2; ++n) {
     const int64_t row = rb * 64 + 32 * n + li;
+    const int64_t trow = row < a.nrows ? layout_row(row, a.bmaj, a.nB, a.Ik) : 0;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       bf16x8 z = {};
       if constexpr (kRecon) {
         tb[n][s] = z;
         if (row < a.nrows)
-          tb[n][s] = *reinterpret_cast<const bf16x8*>(a.T + row * K + s * 16 + h * 8);
+          tb[n][s] = *reinterpret_cast<const bf16x8*>(a.T + trow * K + s * 16 + h * 8);
       }
       if constexpr (SPLIT && kRecon) {
         tlo[n][s] = z;
         if (row < a.nrows)
-          tlo[n][s] = *reinterpret_cast<const bf16x8*>(a.T_lo + row * K + s * 16 + h * 8);
+          tlo[n][s] = *reinterpret_cast<const bf16x8*>(a.T_lo + trow * K + s * 16 + h * 8);
       }
       if constexpr (kLS) {
         thb[n][s] = z;
         if (row < a.nrows)
-          thb[n][s] = *reinterpret_cast<const bf16x8*>(a.TH + row * K + s * 16 + h * 8);
+          thb[n][s] = *reinterpret_cast<const bf16x8*>(a.TH + trow * K + s * 16 + h * 8);
       }
     }
   }
@@ -631,15 +646,72 @@ __global__ __launch_bounds__(256, (K >= 96 ? 1 : 2)) void k_tpass(
     else grad_products(1);
   }
 
+  // S^T accumulator: lane l holds row 32 n + li of the block and, in register v,
+  // j = 32 mt + 8 (v/4) + 4h + v%4
+  bool contracted = false;
+  if constexpr (kGrad && K == 64) {
+    if (a.dpart && rb_ok) {  // (uniform over the wave)
+      // B-major rows, r_k = r_s = r_{k+1} = 8: item j = a + 8c of a row factor has a = 4h +
+      // v%4 and c = 4 mt + v/4, so the lane's part of D(i_k)[a + 8 beta] = sum_c S[a + 8c]
+      // U(b)[beta + 8c] is a = 4h .. 4h + 3 for every beta.  The block's rows belong to
+      // slice i0 and, past a slice boundary, i0 + 1: one reduction per slice.
+      contracted = true;
+      const int64_t t0 = rb * 64;
+      const int64_t i0 = t0 / a.nB;
+      const int64_t tl = min(t0 + 63, a.nrows - 1);
+      const int nsl = (int)(tl / a.nB - i0) + 1;
+      float* rtile = Xs;  // this wave's tile: [h][li][kXS]; the walk no longer reads it
+      for (int sl = 0; sl < nsl; ++sl) {
+        float acc[4][8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int be = 0; be < 8; ++be) acc[u][be] = 0.f;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const int64_t t = t0 + 32 * n + li;
+          const int64_t ik = t / a.nB;
+          const bool in = t < a.nrows && ik == i0 + sl;
+          const float* up = a.U + (in ? t - ik * a.nB : 0) * a.Us;
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int c = 4 * mt + q;
+              const float4 u0 = *reinterpret_cast<const float4*>(up + 8 * c);
+              const float4 u1 = *reinterpret_cast<const float4*>(up + 8 * c + 4);
+              const float uv[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const float sv = in ? sacc[mt][n][4 * q + u] : 0.f;
+#pragma unroll
+                for (int be = 0; be < 8; ++be) acc[u][be] = fmaf(sv, uv[be], acc[u][be]);
+              }
+            }
+        }
+        // the 32 lanes of each half h hold the same 32 outputs: add them in lane order
+        wave_sync();
+#pragma unroll
+        for (int be = 0; be < 8; ++be)
+          *reinterpret_cast<float4*>(rtile + (h * 32 + li) * kXS + 4 * be) =
+              float4{acc[0][be], acc[1][be], acc[2][be], acc[3][be]};
+        wave_sync();
+        const int hh = l >> 5, oo = l & 31;  // output a = 4 hh + oo % 4, beta = oo / 4
+        float sum = 0.f;
+        for (int i = 0; i < 32; ++i) sum += rtile[(hh * 32 + i) * kXS + oo];
+        a.dpart[((cg * a.n_rb + rb) * 2 + sl) * 64 + (4 * hh + (oo & 3)) + 8 * (oo >> 2)] = sum;
+      }
+    }
+  }
   if constexpr (kGrad) {
-    // S^T accumulator: lane l holds row 32 n + li of the block and, in register v,
-    // j = 32 mt + 8 (v/4) + 4h + v%4: four consecutive j per group of four registers,
-    // stored as one 16-byte vector (RRP is a multiple of 4, so j0 < RRP covers j0 + 3)
+    // otherwise the row factors themselves: four consecutive j per group of four
+    // registers, stored as one 16-byte vector (RRP is a multiple of 4, so j0 < RRP covers
+    // j0 + 3), at the row's layout position
 #pragma unroll
     for (int n = 0; n < 2; ++n) {
       const int64_t row = rb * 64 + 32 * n + li;
-      if (row >= a.nrows) continue;
-      float* sp = a.S + (cg * a.nrows + row) * a.RRP;
+      if (contracted || row >= a.nrows) continue;
+      float* sp = a.S + (cg * a.nrows + layout_row(row, a.bmaj, a.nB, a.Ik)) * a.RRP;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -788,6 +860,12 @@ hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {
   if (a.Vf == nullptr ||
       ((mode == kModeGrad || mode == kModeGradFast || mode == kModeGradE) && a.VTf == nullptr))
     return hipErrorInvalidValue;
+  // B-major rows: tile rows are the layout rows of nB items per slice, and the epilogue
+  // contraction (rank 8, K = 64) needs at least 64 rows per slice (a block spans <= 2)
+  if (a.bmaj && (a.nB < 1 || a.Ik < 1 || a.nB * a.Ik != a.nrows)) return hipErrorInvalidValue;
+  if (a.dpart && (K != 64 || !a.bmaj || a.nB < 64 || a.U == nullptr || a.Us < 64 ||
+                  a.RR != 64 || a.RRP != 64))
+    return hipErrorInvalidValue;
   switch (K) {
     case 32: return launch_ks<32>(mode, a, st);
     case 64: return launch_ks<64>(mode, a, st);
@@ -795,6 +873,57 @@ hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {
     case 128: return launch_ks<128>(mode, a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// d(i_k)[o] = scale * sum of the epilogue partials of slice i_k, the partial index running
+// over the column groups, then over the 64-row blocks rb that hold rows of the slice (slot
+// i_k - first slice of rb).  One work-group per slice; thread (o, g) adds partials g, g + 16,
+// ... in order (its loads issued eight at a time before the sums), then the 16 group sums
+// are added in a fixed tree.
+__global__ __launch_bounds__(1024) void k_dpart_finish(const float* __restrict__ part, int n_cg,
+                                                       int64_t n_rb, int64_t nB, int64_t Ik,
+                                                       double* __restrict__ d64,
+                                                       float* __restrict__ d_out, double scale) {
+  __shared__ double red[16][64];
+  const int64_t ik = blockIdx.x;
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t rb_lo = ik * nB / 64, rb_hi = ((ik + 1) * nB - 1) / 64;
+  const int64_t nrb = rb_hi - rb_lo + 1, np = (int64_t)n_cg * nrb;
+  auto at = [&](int64_t i) -> float {
+    const int64_t cg = i / nrb, rb = rb_lo + (i - cg * nrb);
+    const int64_t slot = ik - rb * 64 / nB;
+    return part[((cg * n_rb + rb) * 2 + slot) * 64 + o];
+  };
+  double s = 0.0;
+  int64_t i = g;
+  for (; i + 16 * 7 < np; i += 16 * 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = at(i + 16 * u);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (double)v[u];
+  }
+  for (; i < np; i += 16) s += (double)at(i);
+  red[g][o] = s;
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if (g < w) red[g][o] += red[g + w][o];
+    __syncthreads();
+  }
+  if (g == 0) {
+    const double v = red[0][o] * scale;
+    if (d64) d64[ik * 64 + o] = v;
+    if (d_out) d_out[ik * 64 + o] = (float)v;
+  }
+}
+
+hipError_t launch_dpart_finish(const float* part, int n_cg, int64_t n_rb, int64_t nB, int64_t Ik,
+                               double* d64, float* d_out, double scale, hipStream_t st) {
+  if (Ik <= 0) return hipSuccess;
+  if (nB < 64 || n_cg < 1 || (Ik * nB + 63) / 64 > n_rb) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dpart_finish, dim3((unsigned)Ik), dim3(1024), 0, st, part, n_cg, n_rb, nB,
+                     Ik, d64, d_out, scale);
+  return hipGetLastError();
 }
 
 }  // namespace trd

@@ -256,6 +256,7 @@ int plan_split(trd_ctx* ctx, int k, const int64_t* counts, Split& sp, int64_t& n
   for (int t = 0; t < sp.q; ++t) ncols *= counts[sp.C[t]];
   n_ct = (int)best_nct;
   ct_w = (int)((ncols + n_ct - 1) / n_ct);
+  if (ct_w > 0) n_ct = (int)((ncols + ct_w - 1) / ct_w);  // no empty trailing tile
   return TRD_OK;
 }
 
@@ -540,8 +541,9 @@ int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStrea
   sp.RR = sp.r_k * sp.r_s;
   sp.RRP = pass_rrp(sp.RR);
   if (sp.RRP < 0) return fail(ctx, TRD_EUNSUPPORTED, "r_k * r_{k+1} above the pass width");
-  const int n_ct = (int)plan_tiles(ctx->dims[k], J, pass_ct_w(ctx->dtype, 0, sp.RRP), sketch_density(ctx));
+  int n_ct = (int)plan_tiles(ctx->dims[k], J, pass_ct_w(ctx->dtype, 0, sp.RRP), sketch_density(ctx));
   const int ct_w = (int)((J + n_ct - 1) / n_ct);
+  if (ct_w > 0) n_ct = (int)((J + ct_w - 1) / ct_w);  // no empty trailing tile
   TRY(sketch_layout(ctx, k, ctx->dims[k], J, ct_w, n_ct));
   Layout& L = ctx->sk.L;
   up.counts = up.cnt;
@@ -571,9 +573,15 @@ constexpr int kTileWGPerCU = 6;
 
 // shape of the bitmask-tile layout of a core-k matrix (nrows x ncols, split sp): block and
 // column-tile counts and the column groups of the matrix-core passes (no device work)
-void plan_tile(const Split& sp, int64_t nrows, int64_t ncols, TLayout& T) {
+void plan_tile(const Split& sp, int64_t nrows, int64_t ncols, int64_t Ik, TLayout& T) {
   T.nrows = nrows;
   T.ncols = ncols;
+  // B-major rows where the gradient pass can contract its own row factors: TR ranks 8
+  // around the split and at least 64 B items per slice (a 64-row block spans <= 2 slices)
+  T.Ik = Ik;
+  T.nB = Ik > 0 ? nrows / Ik : 1;
+  T.bmaj = sp.p >= 1 && sp.r_k == 8 && sp.r_k1 == 8 && sp.r_s == 8 && T.nB >= 64 &&
+           T.nB * Ik == nrows;
   T.K = tile_k(sp.RRP);  // covers the padded width the row-factor partials are stored with
   T.n_chunks = (T.ncols + 31) / 32;
   const int64_t cwmax = tile_cw(T.K);
@@ -597,7 +605,7 @@ int ensure_tile_layout(trd_ctx* ctx, int k, hipStream_t st) {
   if (T.ready) return TRD_OK;
   const Split& sp = ctx->splits[k];
   const Layout& L = ctx->layouts[k];
-  plan_tile(sp, L.nrows, L.ncols, T);
+  plan_tile(sp, L.nrows, L.ncols, ctx->dims[k], T);
   if ((int64_t)tpass_lds(kModeGradFast, T.K, T.CW) > g_lds_max)
     return fail(ctx, TRD_EUNSUPPORTED, "matrix-core pass does not fit the device LDS");
   T.rowoff = L.rowoff;
@@ -855,7 +863,9 @@ int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStr
 
 // matrix-core pass (its bf16 tables are written by the table builders)
 // keep_w: a gradient pass stores each entry's weight for the line search that follows it
-int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w) {
+// Uc: U(m_B) of a gradient pass that contracts its row factors itself (B-major layout)
+int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w,
+                     const ItemRef* Uc) {
   const TLayout& TL = *up.TL;
   const Split& sp = up.sp;
   TPassArgs a;
@@ -892,7 +902,16 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, b
   // positions): below that, a block rarely needs a fifth round from memory
   a.rounds = TL.n_blocks > 0 && TL.nobs > 224 * TL.n_blocks ? 8 : 4;
   a.nobs = TL.nobs;
-  if (keep_w && (mode == kModeGrad || mode == kModeGradFast || mode == kModeGradE)) a.wout = ctx->wts;
+  a.nB = TL.nB;
+  a.Ik = TL.Ik;
+  a.bmaj = TL.bmaj ? 1 : 0;
+  const bool grad = mode == kModeGrad || mode == kModeGradFast || mode == kModeGradE;
+  if (grad && Uc) {
+    a.dpart = reinterpret_cast<float*>(ctx->part_misc);
+    a.U = static_cast<const float*>(Uc->ptr);
+    a.Us = Uc->stride;
+  }
+  if (keep_w && grad) a.wout = ctx->wts;
   if (mode == kModeGradE) {  // the residual pass's e; no reconstruction, no split tables
     a.vals = ctx->resid;
     a.T_lo = nullptr;
@@ -907,7 +926,8 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, b
   return TRD_OK;
 }
 
-int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w = false) {
+int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w = false,
+             const ItemRef* Uc = nullptr) {
   const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
@@ -916,7 +936,7 @@ int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep
     CK(hipEventRecord(e0, st));
   }
   if (up.TL) {
-    TRY(launch_tile_pass(ctx, up, mode, st, keep_w));
+    TRY(launch_tile_pass(ctx, up, mode, st, keep_w, Uc));
   } else {
     PassArgs a = pass_args(ctx, up);
     CK(launch_pass(ctx->dtype, 0, mode, a, st));
@@ -952,7 +972,11 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   int64_t nB = 1;
   for (int t = 0; t < sp.p; ++t) nB *= up.counts[sp.B[t]];
   const int nchunk = contract_chunks(Ik, nB, sp.r_k);
-  TRY(ensure_part(ctx, up_nwg(up) * 3, std::max<int64_t>((int64_t)nchunk * Ik * sp.r_k * sp.r_k1, 8)));
+  // B-major tile layout: the pass writes 2 x 64 floats of d partials per (column group,
+  // 64-row block) into part_misc instead of its row factors
+  const int64_t ndpart = up.TL && up.TL->bmaj ? (int64_t)up.TL->n_cg * up.TL->n_rb * 64 : 0;
+  TRY(ensure_part(ctx, up_nwg(up) * 3,
+                  std::max<int64_t>(std::max<int64_t>((int64_t)nchunk * Ik * sp.r_k * sp.r_k1, 8), ndpart)));
   const int64_t nd = Ik * sp.r_k * sp.r_k1;
   if (nd > ctx->cap_d) {
     TRY(alloc_n(ctx, &ctx->d64, nd));
@@ -969,10 +993,23 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
     TRY(build_rowtable(ctx, up, cores[sp.k], Uref, nB, ctx->T, st));
     TRY(build_coltable(ctx, up, cores, st));
   }
-  TRY(ensure_S(ctx, (int64_t)up_nct(up) * L.nrows * sp.RRP));
-  TRY(run_pass(ctx, up, stats_dev ? kModeGrad : (reuse_e ? kModeGradE : kModeGradFast), st, keep_w));
+  // the pass contracts its own row factors (FP32 U items, 16-byte aligned, no list)
+  const bool tile_contract = ndpart > 0 && Uref.ptr && !Uref.list && Uref.stride >= 64 &&
+                             Uref.stride % 4 == 0 &&
+                             reinterpret_cast<uintptr_t>(Uref.ptr) % 16 == 0;
+  if (!tile_contract) TRY(ensure_S(ctx, (int64_t)up_nct(up) * L.nrows * sp.RRP));
+  TRY(run_pass(ctx, up, stats_dev ? kModeGrad : (reuse_e ? kModeGradE : kModeGradFast), st, keep_w,
+               tile_contract ? &Uref : nullptr));
   ctx->resid_core = -1;  // the core changes with this update
   if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, stats_dev, st));
+  if (tile_contract) {
+    CK(launch_dpart_finish(reinterpret_cast<const float*>(ctx->part_misc), up.TL->n_cg,
+                           up.TL->n_rb, up.TL->nB, Ik, ctx->d64, static_cast<float*>(d_out), scale,
+                           st));
+    if (Uout) *Uout = Uref;
+    if (nBout) *nBout = nB;
+    return TRD_OK;
+  }
   // a few column-group partials are added by the contraction as it loads S; many are
   // first summed by a streaming kernel
   int ncg = up_nct(up);
@@ -1414,7 +1451,8 @@ int trd_workspace_bytes(int device, int N, const int64_t* dims, const int32_t* r
     int64_t tiles = 0;
     for (int k = 0; k < N; ++k) {
       TLayout T;
-      plan_tile(sps[k], nr[k], nc[k], T);
+      plan_tile(sps[k], nr[k], nc[k], dims[k], T);
+      if (T.bmaj) tiles += al(T.n_cg * T.n_rb * 2 * 64 * 4);  // the epilogue's d partials
       tiles += al(T.n_blocks * 4) + al((T.n_blocks + 1) * 8) + al(8) + al((n_obs + kTileSlack) * 4) +
                al((n_obs + kTileSlack) * 2);
       const int64_t K = T.K, nf = tile_frag_elems(nc[k], K);

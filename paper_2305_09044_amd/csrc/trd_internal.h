@@ -265,6 +265,11 @@ struct TLayout {
   int64_t n_chunks = 0;            // 32-column chunks
   int64_t n_rb = 0, n_rg = 0;      // 64-row blocks, 256-row groups
   int64_t n_blocks = 0;            // n_rb * n_chunks
+  // B-major rows (bmaj): tile row b + nB i_k holds the layout row i_k + I_k b, so that a
+  // 64-row block spans at most two slices i_k and the gradient pass contracts its own row
+  // factors (TPassArgs::dpart); otherwise tile rows are the layout rows
+  int64_t nB = 1, Ik = 0;
+  bool bmaj = false;
   const int64_t* rowoff = nullptr; // shared with the ELL layout of the same split
   const int64_t* coloff = nullptr;
   int32_t* bcnt = nullptr;         // [n_blocks]
@@ -286,7 +291,15 @@ struct TPassArgs {
   const uint16_t* VTf;
   const uint16_t* T_lo;  // split tables (remainders), or nullptr
   const uint16_t* Vf_lo;
-  float* S;              // [n_cg][nrows][RRP] per-column-group partials
+  float* S;              // [n_cg][nrows][RRP] per-column-group partials (layout row order)
+  // B-major rows (gradient modes, K = 64, r_k = r_s = r_{k+1} = 8): instead of S, each
+  // wave writes dpart[cg][rb][s][a + 8 beta] = sum over its rows of slice i0 + s (i0 the
+  // slice of the block's first row) of sum_c S(row)[a + 8c] U(b)[beta + 8c]
+  float* dpart;
+  const float* U;        // U(m_B) items (r_k1 x r_s, index beta + r_k1 c), Us apart
+  int64_t Us;
+  int64_t nB, Ik;        // B items per slice and slices (B-major rows)
+  int bmaj;
   const int64_t* boff;
   const float* vals;
   const uint16_t* pos;
@@ -317,6 +330,9 @@ hipError_t launch_fragments(const uint16_t* V, int64_t ncols, int K, uint16_t* V
 hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* X, int dtype,
                              bool fill, hipStream_t st);
 hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st);
+// d(i_k)[o] = scale * (fixed-order sum of the B-major epilogue partials of slice i_k)
+hipError_t launch_dpart_finish(const float* part, int n_cg, int64_t n_rb, int64_t nB, int64_t Ik,
+                               double* d64, float* d_out, double scale, hipStream_t st);
 
 // sigma quantile by radix select over float bit patterns
 // radix select of the kernel-width quantile over the |e| keys: three digits (11, 11, 10

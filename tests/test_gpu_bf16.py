@@ -31,7 +31,15 @@ SHAPES = [
     ((48, 40, 36), (8, 8, 8)),            # K = 64, full blocks of ~820 entries: eight
                                           # register rounds and the rounds read past them
     ((300, 257), (4, 3)),                 # N = 2
+    # B-major block rows (TR ranks 8, >= 64 B items per slice): the gradient pass contracts
+    # its row factors with U(m_B) itself
+    ((20, 70, 20, 20), (8, 8, 8, 8)),     # core 0: 70 items per slice (blocks straddle two
+                                          # slices), three column groups
+    ((12, 11, 10, 9, 8), (8,) * 5),       # cores 2, 3: U(m_B) from two B modes
 ]
+
+# the cores of the shapes above whose block rows are B-major, by the library's rule
+B_MAJOR = {(20, 70, 20, 20): [0], (12, 11, 10, 9, 8): [2, 3]}
 
 
 PRECS = ["bf16", "bf16x3"]
@@ -62,6 +70,22 @@ def test_bf16_grad(dims, ranks, prec):
         assert s[2] == info.n_obs                      # every observed entry visited once
         assert s[0] == pytest.approx(info.loss, rel=2e-2)
     print(f"{prec} gradient worst relative error {worst:.2e}")
+
+
+@pytest.mark.parametrize("dims", sorted(B_MAJOR))
+def test_b_major_shapes_take_the_b_major_rows(dims):
+    # B-major rows need a split with B modes (split >= 1) whose items number >= 64 at TR
+    # ranks 8; the split is the library's own choice, read back from trd_problem_info
+    ranks = (8,) * len(dims)
+    X, P, Z0, prob = _setup(dims, ranks)
+    split = prob.info()["split"]
+    N = len(dims)
+    for k in range(N):
+        nB = math.prod(dims[(k + t) % N] for t in range(1, split[k] + 1))
+        assert (split[k] >= 1 and nB >= 64) == (k in B_MAJOR[dims]), (k, split[k], nB)
+    # straddling blocks: a slice's rows do not fill whole 64-row blocks
+    k0 = B_MAJOR[dims][0]
+    assert math.prod(dims[(k0 + t) % N] for t in range(1, split[k0] + 1)) % 64 != 0
 
 
 @pytest.mark.parametrize("prec", PRECS)

@@ -98,6 +98,42 @@ def test_stored_residual_gradient_pass_equals_plain_pass(order5, prec):
     assert torch.equal(a[0], b[0])
 
 
+@pytest.fixture(scope="module")
+def b_major():
+    # order 4, rank 8, core 0 on B-major block rows (70 B items per slice): its gradient
+    # pass, which reads the quantile pass's residuals, contracts its own row factors
+    w = synth.Workload("tr4_b_major", (20, 70, 20, 20), (8, 8, 8, 8), 0.3, 0.15, "uniform_std",
+                       20.0)
+    Zt, xstar, P, X = synth.make_workload(w, 2, tr.reconstruct)
+    X = X.astype(F32).astype(np.float64)
+    Z0 = [z.astype(F32).astype(np.float64) for z in synth.perturbed_cores(Zt, 2, rel=0.3)]
+    ref, hist = aw.fit(X, P, Z0, aw.FitOptions(max_sweeps=1, tol=0.0))
+    return w, X, P, Z0, ref, hist
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+def test_fit_on_b_major_rows_matches_oracle(b_major, prec):
+    w, X, P, Z0, ref, hist = b_major
+    prob = device_problem(X, P, w.dims, w.ranks, F32)
+    assert prob.info()["split"][0] == 1  # B = mode 1: 70 items per slice
+    bs, b1, _ = BARS[prec]
+    a = device_cores(Z0, F32)
+    rep = prob.fit(a, max_sweeps=1, tol=0.0, precision=prec)
+    assert rep["sigma"][0] == pytest.approx(hist["sigma"][0], rel=bs)
+    errs = [rel(g, r) for g, r in zip(host_cores(a, w.dims, w.ranks), ref)]
+    print(f"{prec} B-major fit, one sweep: core errors {['%.2e' % e for e in errs]}")
+    assert max(errs) <= b1, errs
+    assert rep["flags"] == 0
+    # the same core-0 update by a step, whose gradient pass forms the residuals itself
+    b = device_cores(Z0, F32)
+    prob.set_precision(prec)
+    eta, flags = prob.step(b, 0, rep["sigma"][0], 1e-9)
+    prob.set_precision("native")
+    assert int(flags) == 0
+    assert float(eta) == pytest.approx(rep["eta"][0][0], rel=1e-12)
+    assert torch.equal(a[0], b[0])
+
+
 def test_plain_fp64_workload_as_configured():
     w = synth.WORKLOADS["tr3_30_r3"]
     Zt, xstar, P, X = synth.make_workload(w, 0, tr.reconstruct)
