@@ -11,7 +11,10 @@
 //      forms e = x - xhat, w = exp(-e^2/2s^2) (eq. 7) and y = w e in FP32, and scatters
 //      y (rounded to bf16) into a cleared 64 x 32 tile in LDS;
 //   3. S^T (K x 64 rows) += V^T-items^T (K x 32 cols) . Y^T (32 cols x 64 rows) on the
-//      matrix cores: the row factor of the gradient of eq. 9.
+//      matrix cores: the row factor of the gradient of eq. 9;
+//   4. at the end of the walk, the row factors go out as they are, or, on B-major block
+//      rows (TR ranks 8, rows ordered with the B-mode index fastest so that a block holds
+//      one or two slices i_k), contracted with U(m_B) into 64-float partials of d.
 // Matrix-core work covers every position of a block; vector work is per observed entry.
 // Split form (SPLIT): the T and V tables also come as bf16 remainders (t = t_hi + t_lo),
 // and Xhat adds the products t_hi v_lo and t_lo v_hi, so the reconstruction (and the

@@ -567,8 +567,9 @@ int prepare_rows(trd_ctx* ctx, int k, const trd_sketch* sk, Update& up, hipStrea
 }
 
 // work-groups per compute unit the matrix-core passes aim for: each column group adds a
-// partial of the gradient row factors (written by the pass, read by the contraction), so
-// fewer, longer walks are preferred to the denser grid of the other passes
+// partial of the gradient (row factors, written by the pass and read by the contraction,
+// or on B-major rows the pass's own 64-float partials of d), so fewer, longer walks are
+// preferred to the denser grid of the other passes
 constexpr int kTileWGPerCU = 6;
 
 // shape of the bitmask-tile layout of a core-k matrix (nrows x ncols, split sp): block and
