@@ -929,4 +929,70 @@ hipError_t launch_dpart_finish(const float* part, int n_cg, int64_t n_rb, int64_
   return hipGetLastError();
 }
 
+
+// The same sums, then the scaled direction of eq. (10) for the slice: h(i_k)[c] =
+// sum_l d(i_k)[l] Cinv[l n + c] in order (Cinv == nullptr: h = d; the not-SPD flag set: h = 0),
+// written as FP64 and FP32, and the slice's share of <d, h> (the line search's numerator)
+// into pdh[i_k].  One work-group per slice; the matrix is 64 x 64 (rank 8).
+__global__ __launch_bounds__(1024) void k_dpart_direction(const float* __restrict__ part, int n_cg,
+                                                          int64_t n_rb, int64_t nB,
+                                                          const double* __restrict__ Cinv,
+                                                          const uint32_t* flags,
+                                                          double* __restrict__ d64,
+                                                          double* __restrict__ h64,
+                                                          float* __restrict__ h_real,
+                                                          double* __restrict__ pdh) {
+  __shared__ double red[16][64];
+  const int64_t ik = blockIdx.x;
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t rb_lo = ik * nB / 64, rb_hi = ((ik + 1) * nB - 1) / 64;
+  const int64_t nrb = rb_hi - rb_lo + 1, np = (int64_t)n_cg * nrb;
+  auto at = [&](int64_t i) -> float {
+    const int64_t cg = i / nrb, rb = rb_lo + (i - cg * nrb);
+    const int64_t slot = ik - rb * 64 / nB;
+    return part[((cg * n_rb + rb) * 2 + slot) * 64 + o];
+  };
+  double s = 0.0;
+  int64_t i = g;
+  for (; i + 16 * 7 < np; i += 16 * 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = at(i + 16 * u);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (double)v[u];
+  }
+  for (; i < np; i += 16) s += (double)at(i);
+  red[g][o] = s;
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if (g < w) red[g][o] += red[g + w][o];
+    __syncthreads();
+  }
+  if (g == 0) {  // one wave: output c = o
+    const double dv = red[0][o];
+    d64[ik * 64 + o] = dv;
+    const bool bad = (*flags & TRD_FLAG_NOTSPD_BIT) != 0;
+    double hv = 0.0;
+    if (!Cinv)
+      hv = dv;
+    else if (!bad)
+      for (int l = 0; l < 64; ++l) hv = fma(red[0][l], Cinv[l * 64 + o], hv);
+    h64[ik * 64 + o] = hv;
+    if (h_real) h_real[ik * 64 + o] = (float)hv;
+    double c = dv * hv;
+    for (int w = 32; w > 0; w >>= 1) c += __shfl_xor(c, w);
+    if (o == 0) pdh[ik] = c;
+  }
+}
+
+hipError_t launch_dpart_direction(const float* part, int n_cg, int64_t n_rb, int64_t nB, int64_t Ik,
+                                  const double* Cinv, const uint32_t* flags, double* d64,
+                                  double* h64, float* h_real, double* pdh, hipStream_t st) {
+  if (Ik <= 0) return hipSuccess;
+  if (nB < 64 || n_cg < 1 || (Ik * nB + 63) / 64 > n_rb) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dpart_direction, dim3((unsigned)Ik), dim3(1024), 0, st, part, n_cg, n_rb,
+                     nB, Cinv, flags, d64, h64, h_real, pdh);
+  return hipGetLastError();
+}
+
 }  // namespace trd

@@ -962,8 +962,11 @@ int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep
 
 // gradient of eq. (9)/(15) for the prepared update: tables, pass, contraction -> d64
 // keep_w: a line search of the same update follows (the matrix-core pass keeps the weights)
+// deferred (optional): on B-major layouts the caller adds the pass's d partials itself
+// (launch_dpart_direction, after the Gram inverse); *deferred tells whether it must
 int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_out, double scale,
-            double* stats_dev, hipStream_t st, ItemRef* Uout, int64_t* nBout, bool keep_w = false) {
+            double* stats_dev, hipStream_t st, ItemRef* Uout, int64_t* nBout, bool keep_w = false,
+            bool* deferred = nullptr) {
   const Split& sp = up.sp;
   const Layout& L = *up.L;
   int64_t needT, needV, needU, needC;
@@ -976,8 +979,10 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
   // B-major tile layout: the pass writes 2 x 64 floats of d partials per (column group,
   // 64-row block) into part_misc instead of its row factors
   const int64_t ndpart = up.TL && up.TL->bmaj ? (int64_t)up.TL->n_cg * up.TL->n_rb * 64 : 0;
+  // (+ Ik: the slices' shares of <d, h> after the partials, when the caller adds them)
   TRY(ensure_part(ctx, up_nwg(up) * 3,
-                  std::max<int64_t>(std::max<int64_t>((int64_t)nchunk * Ik * sp.r_k * sp.r_k1, 8), ndpart)));
+                  std::max<int64_t>(std::max<int64_t>((int64_t)nchunk * Ik * sp.r_k * sp.r_k1, 8),
+                                    ndpart > 0 ? ndpart + Ik : 0)));
   const int64_t nd = Ik * sp.r_k * sp.r_k1;
   if (nd > ctx->cap_d) {
     TRY(alloc_n(ctx, &ctx->d64, nd));
@@ -1003,10 +1008,12 @@ int do_grad(trd_ctx* ctx, const Update& up, const void* const* cores, void* d_ou
                tile_contract ? &Uref : nullptr));
   ctx->resid_core = -1;  // the core changes with this update
   if (stats_dev) CK(launch_reduce_partials(ctx->part_pass, up_nwg(up), 3, stats_dev, st));
+  if (deferred) *deferred = tile_contract && !d_out && scale == 1.0;
   if (tile_contract) {
-    CK(launch_dpart_finish(reinterpret_cast<const float*>(ctx->part_misc), up.TL->n_cg,
-                           up.TL->n_rb, up.TL->nB, Ik, ctx->d64, static_cast<float*>(d_out), scale,
-                           st));
+    if (!(deferred && *deferred))
+      CK(launch_dpart_finish(reinterpret_cast<const float*>(ctx->part_misc), up.TL->n_cg,
+                             up.TL->n_rb, up.TL->nB, Ik, ctx->d64, static_cast<float*>(d_out),
+                             scale, st));
     if (Uout) *Uout = Uref;
     if (nBout) *nBout = nB;
     return TRD_OK;
@@ -1105,15 +1112,29 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
   }
   ItemRef Uref;
   int64_t nB;
-  TRY(do_grad(ctx, up, (const void* const*)cores, nullptr, 1.0, nullptr, st, &Uref, &nB, true));
+  bool deferred = false;
+  TRY(do_grad(ctx, up, (const void* const*)cores, nullptr, 1.0, nullptr, st, &Uref, &nB, true,
+              &deferred));
   if (scaled) CK(hipStreamWaitEvent(st, ctx->ev_join, 0));
-  const int64_t nbl = (Ik * R + 255) / 256;
-  TRY(ensure_part(ctx, 0, nbl));
-  CK(launch_apply_inverse(ctx->d64, scaled ? ctx->Cinv : nullptr, Ik, R, ctx->h64, ctx->h_real,
-                          ctx->dtype, ctx->part_misc, ctx->flags, st));
+  // <d, h> partials: per 256 elements of h, or (B-major layouts, where one kernel adds the
+  // pass's d partials and applies the inverse per slice) per slice, after the d partials
+  int64_t nbl = (Ik * R + 255) / 256;
+  double* pnum = ctx->part_misc;
+  if (deferred) {
+    const TLayout& TL = *up.TL;
+    nbl = Ik;
+    pnum = ctx->part_misc + TL.n_cg * TL.n_rb * 64;
+    CK(launch_dpart_direction(reinterpret_cast<const float*>(ctx->part_misc), TL.n_cg, TL.n_rb,
+                              TL.nB, Ik, scaled ? ctx->Cinv : nullptr, ctx->flags, ctx->d64,
+                              ctx->h64, static_cast<float*>(ctx->h_real), pnum, st));
+  } else {
+    TRY(ensure_part(ctx, 0, nbl));
+    CK(launch_apply_inverse(ctx->d64, scaled ? ctx->Cinv : nullptr, Ik, R, ctx->h64, ctx->h_real,
+                            ctx->dtype, ctx->part_misc, ctx->flags, st));
+  }
   TRY(build_rowtable(ctx, up, ctx->h_real, Uref, nB, ctx->TH, st));
   TRY(run_pass(ctx, up, kModeLS, st));
-  CK(launch_finish_step(ctx->dtype, ctx->part_misc, nbl, ctx->part_pass, up_nwg(up),
+  CK(launch_finish_step(ctx->dtype, pnum, nbl, ctx->part_pass, up_nwg(up),
                         up_nobs_dev(up), ctx->flags, flags_user, ctx->scal + kEta, eta_user, cores[k],
                         ctx->h64, Ik * R, st));
   return TRD_OK;

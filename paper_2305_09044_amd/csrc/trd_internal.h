@@ -333,6 +333,11 @@ hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st);
 // d(i_k)[o] = scale * (fixed-order sum of the B-major epilogue partials of slice i_k)
 hipError_t launch_dpart_finish(const float* part, int n_cg, int64_t n_rb, int64_t nB, int64_t Ik,
                                double* d64, float* d_out, double scale, hipStream_t st);
+// the same sums followed by the scaled direction of the slice (rank 8: 64 x 64 inverse),
+// h in FP64 and FP32 and the slice's share of <d, h> in pdh[i_k]
+hipError_t launch_dpart_direction(const float* part, int n_cg, int64_t n_rb, int64_t nB, int64_t Ik,
+                                  const double* Cinv, const uint32_t* flags, double* d64,
+                                  double* h64, float* h_real, double* pdh, hipStream_t st);
 
 // sigma quantile by radix select over float bit patterns
 // radix select of the kernel-width quantile over the |e| keys: three digits (11, 11, 10
