@@ -238,7 +238,8 @@ hipError_t launch_ring_gram(int N, const int32_t* ranks, int k, const double* co
 template <bool kLDS>
 __global__ __launch_bounds__(1024) void k_inverse(const double* __restrict__ G,
                                                   double* __restrict__ Cinv, int n,
-                                                  double lambda_rel, uint32_t* flags) {
+                                                  double lambda_rel, uint32_t* flags,
+                                                  int assign) {
   extern __shared__ double lds[];
   __shared__ double f[256];
   __shared__ double s_lam, s_thr;
@@ -286,17 +287,21 @@ __global__ __launch_bounds__(1024) void k_inverse(const double* __restrict__ G,
   __syncthreads();
   const bool bad = s_bad != 0;
   for (int t = threadIdx.x; t < nn; t += blockDim.x) Cinv[t] = bad ? 0.0 : A[t];
-  if (bad && threadIdx.x == 0) atomicOr(flags, TRD_FLAG_NOTSPD_BIT);
+  if (threadIdx.x == 0) {
+    if (assign) *flags = bad ? TRD_FLAG_NOTSPD_BIT : 0u;
+    else if (bad) atomicOr(flags, TRD_FLAG_NOTSPD_BIT);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_inverse64(const double* __restrict__ G, int n,
                                                    double lambda_rel, double* __restrict__ Cinv,
-                                                   uint32_t* flags);
+                                                   uint32_t* flags, int assign);
 
 hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
-                          uint32_t* flags, hipStream_t st) {
+                          uint32_t* flags, hipStream_t st, bool assign) {
+  const int as = assign ? 1 : 0;
   if (n > 32 && n <= 64) {  // register form; smaller systems keep one element per thread
-    hipLaunchKernelGGL(k_inverse64, dim3(1), dim3(256), 0, st, G, n, lambda_rel, Cinv, flags);
+    hipLaunchKernelGGL(k_inverse64, dim3(1), dim3(256), 0, st, G, n, lambda_rel, Cinv, flags, as);
     return hipGetLastError();
   }
   // small systems run in one or a few waves: fewer barrier participants per step
@@ -304,10 +309,10 @@ hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_re
   if (threads > 1024) threads = 1024;
   if ((int64_t)n * n * (int64_t)sizeof(double) + 4096 <= g_lds_max) {
     hipLaunchKernelGGL(k_inverse<true>, dim3(1), dim3(threads), (size_t)n * n * sizeof(double), st,
-                       G, Cinv, n, lambda_rel, flags);
+                       G, Cinv, n, lambda_rel, flags, as);
   } else {
     hipLaunchKernelGGL(k_inverse<false>, dim3(1), dim3(1024), 0, st, G, Cinv, n, lambda_rel,
-                       flags);
+                       flags, as);
   }
   return hipGetLastError();
 }
@@ -325,7 +330,7 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 // the same wave, the scaled pivot row from LDS (one barrier per step).
 __global__ __launch_bounds__(256) void k_inverse64(const double* __restrict__ G, int n,
                                                    double lambda_rel, double* __restrict__ Cinv,
-                                                   uint32_t* flags) {
+                                                   uint32_t* flags, int assign) {
   __shared__ double prow[2][64];
   __shared__ double s_lam, s_thr;
   __shared__ int s_bad;
@@ -387,7 +392,10 @@ __global__ __launch_bounds__(256) void k_inverse64(const double* __restrict__ G,
     const int i = w + 4 * q;
     if (i < n && j < n) Cinv[i * n + j] = bad ? 0.0 : A[q];
   }
-  if (bad && threadIdx.x == 0) atomicOr(flags, TRD_FLAG_NOTSPD_BIT);
+  if (threadIdx.x == 0) {
+    if (assign) *flags = bad ? TRD_FLAG_NOTSPD_BIT : 0u;
+    else if (bad) atomicOr(flags, TRD_FLAG_NOTSPD_BIT);
+  }
 }
 
 // h = d Cinv (I_k x n), written in FP64 and in the problem dtype; per-block partial

@@ -1083,7 +1083,11 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
             double* eta_user, uint32_t* flags_user, hipStream_t st) {
   Update up;
   ctx->lev_lambda = lambda_rel;
-  CK(launch_zero(ctx->flags, sizeof(uint32_t), st));  // before the sketch (it may flag clamping)
+  // the step's flags start at zero: on the full path with the scaled direction nothing
+  // writes them before the Gram inverse on the second stream, which sets the whole word;
+  // otherwise cleared here, before the sketch (it may flag clamping)
+  const bool inverse_clears = ctx->direction == TRD_DIR_SCALED && !sk;
+  if (!inverse_clears) CK(launch_zero(ctx->flags, sizeof(uint32_t), st));
   TRY(prepare_update(ctx, k, sk, up, st, cores));
   const Split& sp = up.sp;
   const int64_t Ik = ctx->dims[k];
@@ -1107,7 +1111,7 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
                                 ctx->ranks[(j + 1) % ctx->N], ctx->Kl[j], ctx->side, up.lst[j]));
     }
     TRY(ring_gram(ctx, k, ctx->G, ctx->side, local ? ctx->Kl : nullptr));
-    CK(launch_inverse(ctx->G, ctx->Cinv, R, lambda_rel, ctx->flags, ctx->side));
+    CK(launch_inverse(ctx->G, ctx->Cinv, R, lambda_rel, ctx->flags, ctx->side, inverse_clears));
     CK(hipEventRecord(ctx->ev_join, ctx->side));
   }
   ItemRef Uref;

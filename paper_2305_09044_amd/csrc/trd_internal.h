@@ -229,8 +229,10 @@ hipError_t launch_ring_gram(int N, const int32_t* ranks, int k, const double* co
                             double* P1, double* G, int64_t lds_max, hipStream_t st);
 // message of the last failure of a context-free call (trd_last_error(NULL)); returns code
 int fail_free(int code, const std::string& msg);
+// (G + lambda_rel tr(G)/n I)^-1; not SPD: zero and the NOTSPD bit ORed into *flags, or
+// with assign the whole word set to that bit or 0 (the step's first writer of its flags)
 hipError_t launch_inverse(const double* G, double* Cinv, int n, double lambda_rel,
-                          uint32_t* flags, hipStream_t st);
+                          uint32_t* flags, hipStream_t st, bool assign = false);
 // Cinv == nullptr: h = d
 hipError_t launch_apply_inverse(const double* d64, const double* Cinv, int64_t Ik, int n,
                                 double* h64, void* h_real, int dtype, double* part_num,
