@@ -89,6 +89,22 @@ def test_b_major_shapes_take_the_b_major_rows(dims):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dims", sorted(B_MAJOR))
+def test_bf16_backward_on_b_major_rows(dims, prec):
+    # the differentiation form's all-core backward (eq. 9 at one point, -d per core) through
+    # the B-major passes: their partials of d are added with the caller's scale and output
+    ranks = (8,) * len(dims)
+    X, P, Z0, prob = _setup(dims, ranks, prec=prec)
+    sigma = 1.2
+    cores = device_cores(Z0, F32)
+    grads = prob.loss_bwd(cores, sigma)
+    gref = aw.loss_grads(X, P, Z0, sigma)
+    errs = [rel(g, r) for g, r in zip(host_cores(grads, dims, ranks), gref)]
+    print(f"{prec} backward on {dims}: relative errors {['%.2e' % e for e in errs]}")
+    assert max(errs) <= 2e-2, errs
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("dims,ranks", SHAPES)
 def test_bf16_step(dims, ranks, prec):
     X, P, Z0, prob = _setup(dims, ranks, prec=prec)
