@@ -18,6 +18,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
+import paper_2305_09044_amd as trd  # noqa: E402
 from oracle import awrtrd as aw  # noqa: E402
 from oracle import tr  # noqa: E402
 from _helpers import device_cores, device_problem, host_cores, host_problem, rel, unflatten_d  # noqa: E402
@@ -102,6 +103,36 @@ def test_bf16_backward_on_b_major_rows(dims, prec):
     errs = [rel(g, r) for g, r in zip(host_cores(grads, dims, ranks), gref)]
     print(f"{prec} backward on {dims}: relative errors {['%.2e' % e for e in errs]}")
     assert max(errs) <= 2e-2, errs
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gradient_direction_step_on_b_major_rows(prec):
+    # h = d (no Gram, no inverse): the per-slice kernel takes d itself as the direction
+    dims, ranks = (20, 70, 20, 20), (8, 8, 8, 8)
+    X, P, Z0, prob = _setup(dims, ranks, prec=prec)
+    prob.set_variant("gradient", "global")
+    cores = device_cores(Z0, F32)
+    eta, flags = prob.step(cores, 0, 1.1, 1e-9)
+    ref, info = aw.core_update(X, P, Z0, 0, 1.1, 1e-9, direction="gradient")
+    assert int(flags) == 0
+    assert rel(host_cores(cores, dims, ranks)[0], ref) <= 1e-2
+    assert float(eta) == pytest.approx(info.eta, rel=3e-2)
+
+
+def test_not_spd_gram_on_b_major_rows_leaves_the_core():
+    # the first column of every slice of core 3 is zero, so is the first column of every
+    # subchain product of core 0: G^{!=0} (64 x 64) has rank 56, with lambda = 0 the inverse
+    # fails, the step reports it, takes eta = 0 and leaves core 0 as it was (d is not zero)
+    dims, ranks = (20, 70, 20, 20), (8, 8, 8, 8)
+    X, P, Z0, prob = _setup(dims, ranks, prec="bf16")
+    Z = [z.copy() for z in Z0]
+    Z[3][:, :, 0] = 0.0  # r_3 x I_3 x r_0
+    assert np.linalg.matrix_rank(aw.gram_fgmc(Z, 0)) < 64
+    cores = device_cores(Z, F32)
+    eta, flags = prob.step(cores, 0, math.inf, 0.0)
+    assert int(flags) & trd.TRD_FLAG_NOTSPD
+    assert float(eta) == 0.0
+    np.testing.assert_array_equal(host_cores(cores, dims, ranks)[0], np.asarray(Z[0], np.float32))
 
 
 @pytest.mark.parametrize("prec", PRECS)
