@@ -188,12 +188,12 @@ template <int K, bool SPLIT, bool WIDE> struct TileRounds {
 };
 
 size_t tpass_lds(int mode, int K, int CW) {
-  (void)K;
   (void)CW;
   if (mode == kModeGrad || mode == kModeGradFast) return (size_t)kXBytes + kYBytes;
-  // the y tiles, then the tiles of the row-factor reduction at the end of the walk (its own:
-  // the waves of a work-group finish their walks at different times)
-  if (mode == kModeGradE) return (size_t)kYBytes + kXBytes;
+  // the y tiles, then (K = 64, the B-major contraction) the tiles of the row-factor
+  // reduction at the end of the walk (its own: the waves of a work-group finish their walks
+  // at different times)
+  if (mode == kModeGradE) return (size_t)kYBytes + (K == 64 ? kXBytes : 0);
   if (mode == kModeLS) return (size_t)kXBytes;  // the q tile only
   if (mode == kModeResid) return (size_t)kXBytes + kQHistBytes;
   return (size_t)kXBytes;
