@@ -1078,9 +1078,11 @@ int ensure_side(trd_ctx* ctx) {
   return TRD_OK;
 }
 
-// one full core update (eqs. 9-12 / 15-18); K factors of the other cores must be current
+// one full core update (eqs. 9-12 / 15-18); K factors of the other cores must be current,
+// except that of core `stale` (>= 0), refreshed here first: with the scaled direction on the
+// second stream, just before the Gram that reads it (its core was updated by the step before)
 int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const trd_sketch* sk,
-            double* eta_user, uint32_t* flags_user, hipStream_t st) {
+            double* eta_user, uint32_t* flags_user, hipStream_t st, int stale = -1) {
   Update up;
   ctx->lev_lambda = lambda_rel;
   // the step's flags start at zero: on the full path with the scaled direction nothing
@@ -1098,12 +1100,14 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
   const bool local = scaled && ctx->gram == TRD_GRAM_LOCAL && sk;
   if (local && up.rows)
     return fail(ctx, TRD_EUNSUPPORTED, "the local Gram matrix needs RStS index sets, not a row sample");
+  if (stale >= 0 && !scaled) TRY(refresh_K(ctx, (const void* const*)cores, stale, st));
   if (scaled) {
     // G (eq. 13) and (G + lambda I)^{-1} need only the factors of the other cores: on the
     // side stream, after everything queued so far, while the gradient runs here
     TRY(ensure_side(ctx));
     CK(hipEventRecord(ctx->ev_fork, st));
     CK(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    if (stale >= 0) TRY(refresh_K(ctx, (const void* const*)cores, stale, ctx->side));
     if (local) {  // factors of the sampled slices I_j of every other core (Sec. 6.1)
       for (int j = 0; j < ctx->N; ++j)
         if (j != k)
@@ -1645,6 +1649,7 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
   ctx->sk.lev_cache = true;
   for (int j = 0; j < kMaxN; ++j) ctx->sk.lev_valid[j] = false;
   int cur = 0;
+  int stale = -1;  // core whose K factor the next step refreshes (all are current here)
   struct HostRead { double sigma; double conv[2]; uint32_t flags; uint32_t pad; } hr;
   std::vector<double> etas(N);
   int status = TRD_OK;
@@ -1698,9 +1703,11 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
                                up_nobs_dev(up), ctx->qcand, ctx->qcand_cnt, up.TL != nullptr, st));
     }
     for (int k = 0; k < N; ++k) {
-      TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st));
+      // the factor of the core updated last is refreshed by this step, beside its gradient
+      TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st,
+                  stale));
       ctx->sk.lev_valid[k] = false;  // core k changed
-      TRY(refresh_K(ctx, (const void* const*)cores, k, st));
+      stale = k;
     }
     // convergence matrix with G^{!=N} of the full cores (it does not involve core N): the
     // last update left it in G unless that update formed no Gram (gradient direction) or the
