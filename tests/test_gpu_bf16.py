@@ -105,6 +105,32 @@ def test_bf16_backward_on_b_major_rows(dims, prec):
     assert max(errs) <= 2e-2, errs
 
 
+# B-major edge cases for core 0: slices of exactly one 64-row block (no block straddles two
+# slices), of 65 rows (almost every block straddles), and a single slice (I_0 = 1)
+B_MAJOR_EDGES = [(9, 64, 10, 11), (12, 65, 9, 10), (1, 80, 9, 11)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dims", B_MAJOR_EDGES)
+def test_b_major_edge_shapes(dims, prec):
+    ranks = (8,) * len(dims)
+    X, P, Z0, prob = _setup(dims, ranks, prec=prec)
+    split = prob.info()["split"]
+    assert split[0] >= 1 and math.prod(dims[1:1 + split[0]]) >= 64, split
+    sigma = 1.3
+    d, stats = prob.grad(device_cores(Z0, F32), 0, sigma)
+    _, info = aw.core_update(X, P, Z0, 0, sigma)
+    got = unflatten_d(d.cpu().numpy(), ranks[0], dims[0], ranks[1])
+    assert rel(got, info.d) <= 2e-2, rel(got, info.d)
+    assert stats[2].item() == info.n_obs
+    cores = device_cores(Z0, F32)
+    eta, flags = prob.step(cores, 0, 1.1, 1e-9)
+    ref, info = aw.core_update(X, P, Z0, 0, 1.1, 1e-9)
+    assert int(flags) == 0
+    assert rel(host_cores(cores, dims, ranks)[0], ref) <= 1e-2
+    assert float(eta) == pytest.approx(info.eta, rel=3e-2)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_gradient_direction_step_on_b_major_rows(prec):
     # h = d (no Gram, no inverse): the per-slice kernel takes d itself as the direction
