@@ -228,8 +228,11 @@ int trd_step(trd_ctx* ctx, void* const* cores, int k, double sigma, double lambd
  * Algorithm 1: sweeps k = 0..N-1 (Gauss-Seidel) until max_sweeps or the relative
  * change e = ||D^t - D^{t-1}||_F / ||D^t||_F of D^t = Z_{N(2)} G^{!=N} Z_{N(2)}^T
  * falls below tol (no test after the first sweep).  cores updated in place.
- * Synchronizes `stream` once per sweep.  Returns TRD_ENOTSPD if a step hit a
- * non-positive-definite G + lambda I (the run stops after that sweep).
+ * With tol > 0 it synchronizes `stream` once per sweep (the stop test reads e); with
+ * tol <= 0 (a fixed number of sweeps) it queues the sweeps and synchronizes once per 32
+ * sweeps and at the end.  Returns TRD_ENOTSPD if a step hit a non-positive-definite
+ * G + lambda I: the run stops after that sweep (sweeps already queued after it change
+ * no core), and the report covers the sweeps up to it.
  */
 int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* opts, trd_fit_report* report,
             void* stream);

@@ -519,14 +519,17 @@ hipError_t launch_eta(const double* num, const double* den, const int64_t* nobs,
 
 // One work-group: num = sum of <d,h> partials, den = sum of the line-search pass
 // partials (column 0 of [n_den][3]), eta of eq. (12) with its flags, then the update
-// Z_k <- Z_k + eta h (eq. 11, '+' reading).  Fixed-order reductions.
+// Z_k <- Z_k + eta h (eq. 11, '+' reading).  Fixed-order reductions.  halt (optional):
+// a nonzero word there leaves Z unchanged (eta 0): a fit that stopped at an earlier sweep
+// whose later sweeps were already queued.
 template <typename real>
 __global__ __launch_bounds__(1024) void k_finish_step(const double* __restrict__ pnum, int64_t n_num,
                                                       const double* __restrict__ pden, int64_t n_den,
                                                       const int64_t* nobs, uint32_t* flags,
                                                       uint32_t* flags_user, double* eta_out,
                                                       double* eta_user, real* __restrict__ Z,
-                                                      const double* __restrict__ h, int64_t nz) {
+                                                      const double* __restrict__ h, int64_t nz,
+                                                      const uint32_t* halt) {
   __shared__ double bn[1024], bd[1024];
   __shared__ double s_eta;
   double a = 0.0, b = 0.0;
@@ -550,6 +553,7 @@ __global__ __launch_bounds__(1024) void k_finish_step(const double* __restrict__
     if (!(den > 0.0) || !isfinite(den) || !isfinite(num)) f |= TRD_FLAG_ZERO_DEN_BIT;
     else e = num / den;
     if (f & TRD_FLAG_NOTSPD_BIT) e = 0.0;
+    if (halt && *halt) e = 0.0;
     *eta_out = e;
     *flags = f;
     if (eta_user) *eta_user = e;
@@ -565,13 +569,14 @@ __global__ __launch_bounds__(1024) void k_finish_step(const double* __restrict__
 hipError_t launch_finish_step(int dtype, const double* pnum, int64_t n_num, const double* pden,
                               int64_t n_den, const int64_t* nobs, uint32_t* flags,
                               uint32_t* flags_user, double* eta, double* eta_user, void* Z,
-                              const double* h, int64_t nz, hipStream_t st) {
+                              const double* h, int64_t nz, const uint32_t* halt,
+                              hipStream_t st) {
   if (dtype == 0)
     hipLaunchKernelGGL(k_finish_step<float>, dim3(1), dim3(1024), 0, st, pnum, n_num, pden, n_den,
-                       nobs, flags, flags_user, eta, eta_user, (float*)Z, h, nz);
+                       nobs, flags, flags_user, eta, eta_user, (float*)Z, h, nz, halt);
   else
     hipLaunchKernelGGL(k_finish_step<double>, dim3(1), dim3(1024), 0, st, pnum, n_num, pden, n_den,
-                       nobs, flags, flags_user, eta, eta_user, (double*)Z, h, nz);
+                       nobs, flags, flags_user, eta, eta_user, (double*)Z, h, nz, halt);
   return hipGetLastError();
 }
 
@@ -598,20 +603,25 @@ hipError_t launch_update(int dtype, void* Z, const double* h64, const double* et
 }
 
 // Gather the per-sweep host-visible values into mapped pinned host memory:
-// out = {sigma, conv[0], conv[1], (double)flags, eta[0..N)}
+// out = {sigma, conv[0], conv[1], (double)flags, eta[0..N)}.  halt (optional) is set once
+// flags carry NOTSPD, so that the steps of sweeps queued after this one change no core.
 __global__ void k_pack_report(const double* sigma, const double* conv, const uint32_t* flags,
-                              const double* eta, int N, double* out) {
+                              const double* eta, int N, double* out, uint32_t* halt) {
+  const uint32_t f = *flags;
   out[0] = *sigma;
   out[1] = conv[0];
   out[2] = conv[1];
-  out[3] = (double)*flags;
+  out[3] = (double)f;
   for (int k = 0; k < N; ++k) out[4 + k] = eta[k];
+  if (halt && (f & TRD_FLAG_NOTSPD_BIT)) *halt = 1u;
   __threadfence_system();
 }
 
 hipError_t launch_pack_report(const double* sigma, const double* conv, const uint32_t* flags,
-                              const double* eta, int N, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_report, dim3(1), dim3(1), 0, st, sigma, conv, flags, eta, N, out);
+                              const double* eta, int N, double* out, uint32_t* halt,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_report, dim3(1), dim3(1), 0, st, sigma, conv, flags, eta, N, out,
+                     halt);
   return hipGetLastError();
 }
 

@@ -25,6 +25,11 @@ namespace {
 
 thread_local std::string g_free_err;
 
+// ring of per-sweep fit reports in mapped pinned host memory: slots of
+// {sigma, conv[0], conv[1], flags, eta[0..N)}
+constexpr int kRepSlots = 32;
+constexpr int kRepStride = 4 + kMaxN;
+
 struct SketchWS {
   // index lists per mode (device), capacity per mode
   int32_t* idx[kMaxN] = {nullptr};
@@ -109,7 +114,7 @@ struct trd_ctx {
   float* qcand = nullptr; uint32_t* qcand_cnt = nullptr; int64_t cap_qcand = 0, cap_qcnt = 0;
   double* Dbuf[2] = {nullptr, nullptr}; double* M = nullptr;
   double* eta_hist = nullptr;     // [N] per sweep
-  double* host_rep = nullptr;     // mapped pinned host memory for the per-sweep report
+  double* host_rep = nullptr;     // mapped pinned host memory: a ring of per-sweep reports
   double* host_rep_dev = nullptr; // its device address
   SketchWS sk;
 
@@ -1082,7 +1087,8 @@ int ensure_side(trd_ctx* ctx) {
 // except that of core `stale` (>= 0), refreshed here first: with the scaled direction on the
 // second stream, just before the Gram that reads it (its core was updated by the step before)
 int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const trd_sketch* sk,
-            double* eta_user, uint32_t* flags_user, hipStream_t st, int stale = -1) {
+            double* eta_user, uint32_t* flags_user, hipStream_t st, int stale = -1,
+            const uint32_t* halt = nullptr) {
   Update up;
   ctx->lev_lambda = lambda_rel;
   // the step's flags start at zero: on the full path with the scaled direction nothing
@@ -1144,7 +1150,7 @@ int do_step(trd_ctx* ctx, void* const* cores, int k, double lambda_rel, const tr
   TRY(run_pass(ctx, up, kModeLS, st));
   CK(launch_finish_step(ctx->dtype, pnum, nbl, ctx->part_pass, up_nwg(up),
                         up_nobs_dev(up), ctx->flags, flags_user, ctx->scal + kEta, eta_user, cores[k],
-                        ctx->h64, Ik * R, st));
+                        ctx->h64, Ik * R, halt, st));
   return TRD_OK;
 }
 
@@ -1282,7 +1288,8 @@ int trd_set_problem(trd_ctx* ctx, int N, const int64_t* dims, const int32_t* ran
   TRY(alloc_n(ctx, &ctx->qhist, 2048));
   TRY(alloc_n(ctx, &ctx->qstate, 4));
   TRY(alloc_n(ctx, &ctx->eta_hist, N));
-  CK(hipHostMalloc((void**)&ctx->host_rep, 64 * sizeof(double), hipHostMallocMapped));
+  CK(hipHostMalloc((void**)&ctx->host_rep, kRepSlots * kRepStride * sizeof(double),
+                  hipHostMallocMapped));
   CK(hipHostGetDevicePointer((void**)&ctx->host_rep_dev, ctx->host_rep, 0));
   CK(launch_zero(ctx->flags, 4 * sizeof(uint32_t), st));
 
@@ -1626,7 +1633,9 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
   hipStream_t st = (hipStream_t)stream;
   const int N = ctx->N;
   for (int j = 0; j < N; ++j) TRY(refresh_K(ctx, (const void* const*)cores, j, st));
-  CK(launch_zero(ctx->flags + 1, sizeof(uint32_t), st));
+  // the fit's flags and its halt word (set by the report of a sweep that hit NOTSPD)
+  CK(launch_zero(ctx->flags + 1, 2 * sizeof(uint32_t), st));
+  const uint32_t* halt = ctx->flags + 2;
   if (o->sigma_mode == TRD_SIGMA_QUANTILE) {
     CK(launch_set_scalar(ctx->scal + kSigma, INFINITY, st));
     // sigma_min = sigma_min_rel * max |x| over the observed entries
@@ -1650,10 +1659,16 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
   for (int j = 0; j < kMaxN; ++j) ctx->sk.lev_valid[j] = false;
   int cur = 0;
   int stale = -1;  // core whose K factor the next step refreshes (all are current here)
-  struct HostRead { double sigma; double conv[2]; uint32_t flags; uint32_t pad; } hr;
-  std::vector<double> etas(N);
+  // Without a stop test (tol <= 0) the host queues the sweeps without waiting for their
+  // reports: each sweep's report goes to its slot of a ring in pinned host memory, read
+  // when the ring is full and at the end.  A sweep that hit NOTSPD ends the run; the
+  // halt word its report sets makes the steps of the sweeps queued after it change no
+  // core, so the cores are those of the sweeps the report covers.
+  const bool batched = !(o->tol > 0.0);
+  int next_read = 0;  // first sweep whose report is unread
+  bool stop = false;
   int status = TRD_OK;
-  for (int t = 0; t < o->max_sweeps; ++t) {
+  for (int t = 0; t < o->max_sweeps && !stop; ++t) {
     if (sk) skb.sweep = t;
     // kernel width for this sweep
     if (o->sigma_mode == TRD_SIGMA_FIXED) {
@@ -1705,7 +1720,7 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
     for (int k = 0; k < N; ++k) {
       // the factor of the core updated last is refreshed by this step, beside its gradient
       TRY(do_step(ctx, cores, k, o->lambda_rel, sk, ctx->eta_hist + k, ctx->flags + 1, st,
-                  stale));
+                  stale, halt));
       ctx->sk.lev_valid[k] = false;  // core k changed
       stale = k;
     }
@@ -1722,30 +1737,33 @@ int trd_fit(trd_ctx* ctx, void* const* cores, const trd_fit_opts* o, trd_fit_rep
       CK(launch_reduce_partials(ctx->part_misc, (IN * IN + 255) / 256, 2, ctx->scal + kConv, st));
     }
     CK(launch_pack_report(ctx->scal + kSigma, ctx->scal + kConv, ctx->flags + 1, ctx->eta_hist, N,
-                          ctx->host_rep_dev, st));
-    CK(hipStreamSynchronize(st));
-    hr.sigma = ctx->host_rep[0];
-    hr.conv[0] = ctx->host_rep[1];
-    hr.conv[1] = ctx->host_rep[2];
-    hr.flags = (uint32_t)ctx->host_rep[3];
-    for (int k = 0; k < N; ++k) etas[k] = ctx->host_rep[4 + k];
+                          ctx->host_rep_dev + (t % kRepSlots) * kRepStride, ctx->flags + 2, st));
     cur ^= 1;
-    const double e = t > 0 ? sqrt(hr.conv[0]) / sqrt(hr.conv[1]) : INFINITY;
-    if (rep) {
-      rep->sweeps = t + 1;
-      rep->last_e = e;
-      rep->last_sigma = hr.sigma;
-      rep->flags |= hr.flags;
-      if (rep->e_hist) rep->e_hist[t] = e;
-      if (rep->sigma_hist) rep->sigma_hist[t] = hr.sigma;
-      if (rep->eta_hist)
-        for (int k = 0; k < N; ++k) rep->eta_hist[(int64_t)t * N + k] = etas[k];
+    if (batched && t + 1 < o->max_sweeps && (t + 1) % kRepSlots != 0) continue;
+    CK(hipStreamSynchronize(st));
+    for (int u = next_read; u <= t && !stop; ++u) {
+      const double* hr = ctx->host_rep + (u % kRepSlots) * kRepStride;
+      const double sigma = hr[0];
+      const uint32_t flags = (uint32_t)hr[3];
+      const double e = u > 0 ? sqrt(hr[1]) / sqrt(hr[2]) : INFINITY;
+      if (rep) {
+        rep->sweeps = u + 1;
+        rep->last_e = e;
+        rep->last_sigma = sigma;
+        rep->flags |= flags;
+        if (rep->e_hist) rep->e_hist[u] = e;
+        if (rep->sigma_hist) rep->sigma_hist[u] = sigma;
+        if (rep->eta_hist)
+          for (int k = 0; k < N; ++k) rep->eta_hist[(int64_t)u * N + k] = hr[4 + k];
+      }
+      if (flags & TRD_FLAG_NOTSPD) {
+        status = fail(ctx, TRD_ENOTSPD, "G + lambda I not positive definite (eq. 10)");
+        stop = true;
+      } else if (u > 0 && e < o->tol) {
+        stop = true;
+      }
     }
-    if (hr.flags & TRD_FLAG_NOTSPD) {
-      status = fail(ctx, TRD_ENOTSPD, "G + lambda I not positive definite (eq. 10)");
-      break;
-    }
-    if (t > 0 && e < o->tol) break;
+    next_read = t + 1;
   }
   return status;
 }

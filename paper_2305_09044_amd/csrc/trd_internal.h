@@ -212,7 +212,7 @@ hipError_t launch_gemm64(const double* A, const double* B, double* C, int m, int
 hipError_t launch_finish_step(int dtype, const double* pnum, int64_t n_num, const double* pden,
                               int64_t n_den, const int64_t* nobs, uint32_t* flags,
                               uint32_t* flags_user, double* eta, double* eta_user, void* Z,
-                              const double* h, int64_t nz, hipStream_t st);
+                              const double* h, int64_t nz, const uint32_t* halt, hipStream_t st);
 hipError_t launch_realign(const double* P, double* G, int r_k, int r_k1, hipStream_t st);
 // ring product of eq. 13 in one work-group (factor sides <= 64), realigned into G
 struct RingArgs {
@@ -245,7 +245,8 @@ hipError_t launch_reduce_partials(const double* part, int64_t n, int width, doub
                                   hipStream_t st);
 hipError_t launch_set_scalar(double* p, double v, hipStream_t st);
 hipError_t launch_pack_report(const double* sigma, const double* conv, const uint32_t* flags,
-                              const double* eta, int N, double* out, hipStream_t st);
+                              const double* eta, int N, double* out, uint32_t* halt,
+                              hipStream_t st);
 hipError_t launch_convergence(int dtype, const void* ZN, const double* G, int64_t IN, int n,
                               double* M, double* D, const double* Dprev, int have_prev,
                               double* part, hipStream_t st);
