@@ -817,38 +817,32 @@ int64_t tile_cw(int K) {
 }
 
 template <int K, bool SPLIT, bool WIDE>
-static hipError_t launch_k(int mode, const TPassArgs& a, hipStream_t st) {
+static hipError_t launch_k(int mode, const TPassArgs& a, hipStream_t st, KTiming tm) {
   const int64_t nwg = a.n_rg * a.n_cg;
   const size_t lds = tpass_lds(mode, K, a.CW);
   if ((int64_t)lds > g_lds_max) return hipErrorInvalidConfiguration;
   dim3 g((unsigned)nwg), b(256);
   switch (mode) {
-    case kModeGrad:
-      hipLaunchKernelGGL((k_tpass<K, kModeGrad, SPLIT, WIDE>), g, b, lds, st, a);
-      break;
+    case kModeGrad: TRD_LAUNCH((k_tpass<K, kModeGrad, SPLIT, WIDE>), g, b, lds, st, tm, a); break;
     case kModeGradFast:
-      hipLaunchKernelGGL((k_tpass<K, kModeGradFast, SPLIT, WIDE>), g, b, lds, st, a);
+      TRD_LAUNCH((k_tpass<K, kModeGradFast, SPLIT, WIDE>), g, b, lds, st, tm, a);
       break;
-    case kModeLS: hipLaunchKernelGGL((k_tpass<K, kModeLS, SPLIT, WIDE>), g, b, lds, st, a); break;
-    case kModeResid:
-      hipLaunchKernelGGL((k_tpass<K, kModeResid, SPLIT, WIDE>), g, b, lds, st, a);
-      break;
-    case kModeGradE:
-      hipLaunchKernelGGL((k_tpass<K, kModeGradE, SPLIT, WIDE>), g, b, lds, st, a);
-      break;
-    default: hipLaunchKernelGGL((k_tpass<K, kModeLoss, SPLIT, WIDE>), g, b, lds, st, a); break;
+    case kModeLS: TRD_LAUNCH((k_tpass<K, kModeLS, SPLIT, WIDE>), g, b, lds, st, tm, a); break;
+    case kModeResid: TRD_LAUNCH((k_tpass<K, kModeResid, SPLIT, WIDE>), g, b, lds, st, tm, a); break;
+    case kModeGradE: TRD_LAUNCH((k_tpass<K, kModeGradE, SPLIT, WIDE>), g, b, lds, st, tm, a); break;
+    default: TRD_LAUNCH((k_tpass<K, kModeLoss, SPLIT, WIDE>), g, b, lds, st, tm, a); break;
   }
   return hipGetLastError();
 }
 
 template <int K>
-static hipError_t launch_ks(int mode, const TPassArgs& a, hipStream_t st) {
-  if (a.T_lo && a.Vf_lo) return launch_k<K, true, false>(mode, a, st);
-  if (K == 64 && a.rounds > 4) return launch_k<K, false, true>(mode, a, st);
-  return launch_k<K, false, false>(mode, a, st);
+static hipError_t launch_ks(int mode, const TPassArgs& a, hipStream_t st, KTiming tm) {
+  if (a.T_lo && a.Vf_lo) return launch_k<K, true, false>(mode, a, st, tm);
+  if (K == 64 && a.rounds > 4) return launch_k<K, false, true>(mode, a, st, tm);
+  return launch_k<K, false, false>(mode, a, st, tm);
 }
 
-hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {
+hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st, KTiming tm) {
   if (a.n_rg * a.n_cg <= 0 || a.n_chunks <= 0) return hipSuccess;
   // the grid and chunk walk must cover exactly the layout the pass indexes
   if ((a.T_lo == nullptr) != (a.Vf_lo == nullptr)) return hipErrorInvalidValue;
@@ -870,10 +864,10 @@ hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st) {
                   a.RR != 64 || a.RRP != 64))
     return hipErrorInvalidValue;
   switch (K) {
-    case 32: return launch_ks<32>(mode, a, st);
-    case 64: return launch_ks<64>(mode, a, st);
-    case 96: return launch_ks<96>(mode, a, st);
-    case 128: return launch_ks<128>(mode, a, st);
+    case 32: return launch_ks<32>(mode, a, st, tm);
+    case 64: return launch_ks<64>(mode, a, st, tm);
+    case 96: return launch_ks<96>(mode, a, st, tm);
+    case 128: return launch_ks<128>(mode, a, st, tm);
     default: return hipErrorInvalidValue;
   }
 }

@@ -871,7 +871,7 @@ int ensure_bf16_tables(trd_ctx* ctx, int64_t nrows, int64_t ncols, int K, hipStr
 // keep_w: a gradient pass stores each entry's weight for the line search that follows it
 // Uc: U(m_B) of a gradient pass that contracts its row factors itself (B-major layout)
 int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w,
-                     const ItemRef* Uc) {
+                     const ItemRef* Uc, KTiming tm = {}) {
   const TLayout& TL = *up.TL;
   const Split& sp = up.sp;
   TPassArgs a;
@@ -928,27 +928,36 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, b
     a.T_lo = nullptr;
     a.Vf_lo = nullptr;
   }
-  CK(launch_tpass(mode, TL.K, a, st));
+  CK(launch_tpass(mode, TL.K, a, st, tm));
   return TRD_OK;
 }
 
 int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w = false,
              const ItemRef* Uc = nullptr) {
+  // profiling: the pass's own start and end, set by the launch (no marker packets)
   const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
-    CK(hipEventRecord(e0, st));
   }
+  KTiming tm;
+  tm.start = e0;
+  tm.stop = e1;
+  bool empty;  // a pass with no work-groups launches nothing (its events stay unset)
   if (up.TL) {
-    TRY(launch_tile_pass(ctx, up, mode, st, keep_w, Uc));
+    TRY(launch_tile_pass(ctx, up, mode, st, keep_w, Uc, tm));
+    empty = up.TL->n_rg * up.TL->n_cg <= 0 || up.TL->n_chunks <= 0;
   } else {
     PassArgs a = pass_args(ctx, up);
-    CK(launch_pass(ctx->dtype, 0, mode, a, st));
+    CK(launch_pass(ctx->dtype, 0, mode, a, st, tm));
+    empty = a.n_rg * a.n_cg <= 0;
   }
   if (timed) {
-    CK(hipEventRecord(e1, st));
+    if (empty) {  // a zero-length interval
+      CK(hipEventRecord(e0, st));
+      CK(hipEventRecord(e1, st));
+    }
     ctx->ev_pairs.push_back(e0);
     ctx->ev_pairs.push_back(e1);
     ctx->prof_slots += up.TL ? up.TL->nobs : up.L->slots;

@@ -1,6 +1,7 @@
 // Internal declarations shared by the host orchestration and the kernel files.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -28,6 +29,22 @@ constexpr uint32_t TRD_FLAG_EMPTY_BIT = 1u;     // mirrors TRD_FLAG_EMPTY
 constexpr uint32_t TRD_FLAG_ZERO_DEN_BIT = 2u;  // mirrors TRD_FLAG_ZERO_DEN
 constexpr uint32_t TRD_FLAG_NOTSPD_BIT = 4u;    // mirrors TRD_FLAG_NOTSPD
 constexpr uint32_t TRD_FLAG_CLAMPED_BIT = 8u;   // mirrors TRD_FLAG_CLAMPED
+
+// Optional start / stop events of a timed kernel launch.  They are handed to the launch
+// itself (hipExtLaunchKernel), which sets them at the kernel's start and end without
+// separate marker packets on the stream.
+struct KTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+// KERN: a kernel name (parenthesised when it has template arguments)
+#define TRD_LAUNCH(KERN, G, B, LDS, ST, TM, ...)                                          \
+  do {                                                                                    \
+    if ((TM).start || (TM).stop)                                                          \
+      hipExtLaunchKernelGGL(KERN, G, B, (uint32_t)(LDS), ST, (TM).start, (TM).stop, 0u,   \
+                            __VA_ARGS__);                                                 \
+    else                                                                                  \
+      hipLaunchKernelGGL(KERN, G, B, LDS, ST, __VA_ARGS__);                               \
+  } while (0)
 
 // largest dynamic LDS a work-group may request, and the compute-unit count (both set from
 // the device at context creation)
@@ -197,7 +214,8 @@ struct PassArgs {
   int ct_w, RR, RRP, n_ct;
   int n_cg, cpg;        // column groups (one work-group each per row group), tiles per group
 };
-hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st);
+hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st,
+                       KTiming tm = {});
 bool pass_supported(int RR);
 int pass_rc(int RR);
 int pass_rrp(int RR);
@@ -332,7 +350,7 @@ hipError_t launch_fragments(const uint16_t* V, int64_t ncols, int K, uint16_t* V
                             hipStream_t st);
 hipError_t launch_tile_build(const TLayout& L, const uint8_t* mask, const void* X, int dtype,
                              bool fill, hipStream_t st);
-hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st);
+hipError_t launch_tpass(int mode, int K, const TPassArgs& a, hipStream_t st, KTiming tm = {});
 // d(i_k)[o] = scale * (fixed-order sum of the B-major epilogue partials of slice i_k)
 hipError_t launch_dpart_finish(const float* part, int n_cg, int64_t n_rb, int64_t nB, int64_t Ik,
                                double* d64, float* d_out, double scale, hipStream_t st);
