@@ -286,25 +286,25 @@ int64_t pass_ct_w(int dtype, int prec, int RRP) {
 }
 
 template <typename real, int RC>
-static hipError_t launch_rc(int mode, const PassArgs& a, hipStream_t st, KTiming tm) {
+static hipError_t launch_rc(int mode, const PassArgs& a, hipStream_t st) {
   constexpr int RRP = (RC + 3) / 4 * 4;
   const int64_t nwg = a.n_rg * a.n_cg;
   const size_t lds = (size_t)a.ct_w * lds_item_stride(RRP, (int)sizeof(real)) * sizeof(real);
   dim3 g((unsigned)nwg), b(kPassThreads);
   switch (mode) {
-    case kModeGrad: TRD_LAUNCH((k_pass<real, RC, kModeGrad>), g, b, lds, st, tm, a); break;
-    case kModeGradFast: TRD_LAUNCH((k_pass<real, RC, kModeGradFast>), g, b, lds, st, tm, a); break;
-    case kModeLS: TRD_LAUNCH((k_pass<real, RC, kModeLS>), g, b, lds, st, tm, a); break;
-    case kModeResid: TRD_LAUNCH((k_pass<real, RC, kModeResid>), g, b, lds, st, tm, a); break;
-    default: TRD_LAUNCH((k_pass<real, RC, kModeLoss>), g, b, lds, st, tm, a); break;
+    case kModeGrad: hipLaunchKernelGGL((k_pass<real, RC, kModeGrad>), g, b, lds, st, a); break;
+    case kModeGradFast: hipLaunchKernelGGL((k_pass<real, RC, kModeGradFast>), g, b, lds, st, a); break;
+    case kModeLS: hipLaunchKernelGGL((k_pass<real, RC, kModeLS>), g, b, lds, st, a); break;
+    case kModeResid: hipLaunchKernelGGL((k_pass<real, RC, kModeResid>), g, b, lds, st, a); break;
+    default: hipLaunchKernelGGL((k_pass<real, RC, kModeLoss>), g, b, lds, st, a); break;
   }
   return hipGetLastError();
 }
 
 template <typename real>
-static hipError_t launch_real(int mode, const PassArgs& a, hipStream_t st, KTiming tm) {
+static hipError_t launch_real(int mode, const PassArgs& a, hipStream_t st) {
   switch (pass_rc(a.RR)) {
-#define TRD_CASE(R) case R: return launch_rc<real, R>(mode, a, st, tm);
+#define TRD_CASE(R) case R: return launch_rc<real, R>(mode, a, st);
     TRD_CASE(4) TRD_CASE(8) TRD_CASE(9) TRD_CASE(12) TRD_CASE(16) TRD_CASE(20) TRD_CASE(24)
     TRD_CASE(25) TRD_CASE(28) TRD_CASE(32) TRD_CASE(36) TRD_CASE(40) TRD_CASE(48) TRD_CASE(49)
     TRD_CASE(56) TRD_CASE(64) TRD_CASE(80) TRD_CASE(81) TRD_CASE(100) TRD_CASE(112) TRD_CASE(128)
@@ -313,14 +313,13 @@ static hipError_t launch_real(int mode, const PassArgs& a, hipStream_t st, KTimi
   }
 }
 
-hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st,
-                       KTiming tm) {
+hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st) {
   (void)prec;
   if (a.n_rg * a.n_cg <= 0) return hipSuccess;
   if (pass_rrp(a.RR) != a.RRP) return hipErrorInvalidValue;
   if (a.cpg < 1 || (int64_t)a.n_cg * a.cpg < a.n_ct || (int64_t)(a.n_cg - 1) * a.cpg >= a.n_ct)
     return hipErrorInvalidValue;
-  return dtype == 0 ? launch_real<float>(mode, a, st, tm) : launch_real<double>(mode, a, st, tm);
+  return dtype == 0 ? launch_real<float>(mode, a, st) : launch_real<double>(mode, a, st);
 }
 
 }  // namespace trd

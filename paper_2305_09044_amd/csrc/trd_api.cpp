@@ -934,30 +934,33 @@ int launch_tile_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, b
 
 int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep_w = false,
              const ItemRef* Uc = nullptr) {
-  // profiling: the pass's own start and end, set by the launch (no marker packets)
+  // profiling: the tile passes hand their start and stop events to the launch, which sets
+  // them at the kernel's own start and end (no marker packets on the stream); the
+  // sliced-ELL passes (FP32 form, sketches: short, launch-bound updates, where a launch
+  // with events costs more host time than two records) are bracketed by records
   const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
   }
-  KTiming tm;
-  tm.start = e0;
-  tm.stop = e1;
-  bool empty;  // a pass with no work-groups launches nothing (its events stay unset)
   if (up.TL) {
+    KTiming tm;
+    tm.start = e0;
+    tm.stop = e1;
     TRY(launch_tile_pass(ctx, up, mode, st, keep_w, Uc, tm));
-    empty = up.TL->n_rg * up.TL->n_cg <= 0 || up.TL->n_chunks <= 0;
-  } else {
-    PassArgs a = pass_args(ctx, up);
-    CK(launch_pass(ctx->dtype, 0, mode, a, st, tm));
-    empty = a.n_rg * a.n_cg <= 0;
-  }
-  if (timed) {
-    if (empty) {  // a zero-length interval
+    // a pass with no work-groups launches nothing: a zero-length interval
+    if (timed && (up.TL->n_rg * up.TL->n_cg <= 0 || up.TL->n_chunks <= 0)) {
       CK(hipEventRecord(e0, st));
       CK(hipEventRecord(e1, st));
     }
+  } else {
+    PassArgs a = pass_args(ctx, up);
+    if (timed) CK(hipEventRecord(e0, st));
+    CK(launch_pass(ctx->dtype, 0, mode, a, st));
+    if (timed) CK(hipEventRecord(e1, st));
+  }
+  if (timed) {
     ctx->ev_pairs.push_back(e0);
     ctx->ev_pairs.push_back(e1);
     ctx->prof_slots += up.TL ? up.TL->nobs : up.L->slots;

@@ -214,8 +214,7 @@ struct PassArgs {
   int ct_w, RR, RRP, n_ct;
   int n_cg, cpg;        // column groups (one work-group each per row group), tiles per group
 };
-hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st,
-                       KTiming tm = {});
+hipError_t launch_pass(int dtype, int prec, int mode, const PassArgs& a, hipStream_t st);
 bool pass_supported(int RR);
 int pass_rc(int RR);
 int pass_rrp(int RR);
