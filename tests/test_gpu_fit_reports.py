@@ -31,15 +31,25 @@ def _problem(dims, ranks, dtype, **kw):
     return X, P, Z0, device_problem(X, P, dims, ranks, dtype)
 
 
-@pytest.mark.parametrize("dtype", [F32, F64])
-def test_fit_without_stop_test_matches_per_sweep_reports(dtype):
+CASES = [
+    # (dims, ranks, dtype, fit options)
+    ((20, 18, 16), (3, 3, 3), F32, {}),
+    ((20, 18, 16), (3, 3, 3), F64, {}),
+    # the BF16 form on B-major rows (TR rank 8), as the benchmark runs it
+    ((20, 70, 20, 20), (8, 8, 8, 8), F32, {"precision": "bf16"}),
+    # RStS: every update draws its sketch from (seed, sweep, core)
+    ((20, 18, 16), (3, 3, 3), F32, {"sketch_sizes": [6, 5, 4], "seed": 11}),
+]
+
+
+@pytest.mark.parametrize("dims,ranks,dtype,opts", CASES)
+def test_fit_without_stop_test_matches_per_sweep_reports(dims, ranks, dtype, opts):
     # 36 sweeps: the reports of the first 32 are read in one batch, the rest at the end
-    dims, ranks = (20, 18, 16), (3, 3, 3)
     _, _, Z0, prob = _problem(dims, ranks, dtype)
     runs = []
     for tol in (0.0, NEVER):
         cores = device_cores(Z0, dtype)
-        rep = prob.fit(cores, max_sweeps=36, tol=tol)
+        rep = prob.fit(cores, max_sweeps=36, tol=tol, **opts)
         runs.append((cores, rep))
     (ca, ra), (cb, rb) = runs
     assert ra["status"] == rb["status"] == TRD_OK
