@@ -362,7 +362,9 @@ int trd_set_variant(trd_ctx* ctx, int direction, int gram, int sampling);
 
 /*
  * Per-launch timing of the fused reconstruct+weight+gradient pass, for measurement:
- * enable != 0 records HIP events around every launch of that kernel on its stream;
+ * enable != 0 times every launch of that kernel on its stream with a pair of HIP events
+ * (the matrix-core passes hand them to the launch, which sets them at the kernel's own
+ * start and end; the sliced-ELL passes record them just before and after the launch);
  * trd_profile_read returns the number of launches and their summed duration (ms) and
  * summed entry slots since the last read, then resets the counters (synchronizes).
  */
