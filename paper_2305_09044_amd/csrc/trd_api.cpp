@@ -936,8 +936,8 @@ int run_pass(trd_ctx* ctx, const Update& up, int mode, hipStream_t st, bool keep
              const ItemRef* Uc = nullptr) {
   // profiling: the tile passes hand their start and stop events to the launch, which sets
   // them at the kernel's own start and end (no marker packets on the stream); the
-  // sliced-ELL passes (FP32 form, sketches: short, launch-bound updates, where a launch
-  // with events costs more host time than two records) are bracketed by records
+  // sliced-ELL passes (FP32 form, sketches) are bracketed by records: the sketched updates
+  // are short and launch-bound, and launches with events made their sweeps slower
   const bool timed = ctx->prof && (mode == kModeGrad || mode == kModeGradFast);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
