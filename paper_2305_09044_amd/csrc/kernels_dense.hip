@@ -633,18 +633,27 @@ __global__ __launch_bounds__(256) void k_zg(const real* __restrict__ Z, const do
                                             int64_t IN, int n, double* __restrict__ M) {
   __shared__ double Gs[64 * 64];
   const bool staged = n <= 64;  // uniform over the grid
-  if (staged) {
+  if (staged) {  // (unrolled: the loads of a thread are in flight together)
+#pragma unroll 8
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) Gs[t] = G[t];
     __syncthreads();
   }
-  const double* Gp = staged ? Gs : G;
   const int64_t total = IN * n;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = t / n;
     const int c = (int)(t % n);
+    const real* zr = Z + i * n;
+    // the sum in order l = 0 .. n-1; unrolled so that a group of row loads is in flight
+    // together instead of one round trip per term
     double s = 0.0;
-    for (int l = 0; l < n; ++l) s = fma((double)Z[i * n + l], Gp[(int64_t)l * n + c], s);
+    if (staged) {
+#pragma unroll 16
+      for (int l = 0; l < n; ++l) s = fma((double)zr[l], Gs[l * n + c], s);
+    } else {
+#pragma unroll 16
+      for (int l = 0; l < n; ++l) s = fma((double)zr[l], G[(int64_t)l * n + c], s);
+    }
     M[t] = s;
   }
 }
@@ -661,8 +670,11 @@ __global__ __launch_bounds__(256) void k_mzt(const double* __restrict__ M, const
   double a = 0.0, b = 0.0;
   if (t < total) {
     const int64_t i = t / IN, j = t % IN;
-    double s = 0.0;
-    for (int l = 0; l < n; ++l) s = fma(M[i * n + l], (double)Z[j * n + l], s);
+    const double* mr = M + i * n;
+    const real* zr = Z + j * n;
+    double s = 0.0;  // in order l = 0 .. n-1 (unrolled: the loads of a group overlap)
+#pragma unroll 16
+    for (int l = 0; l < n; ++l) s = fma(mr[l], (double)zr[l], s);
     D[t] = s;
     const double dd = have_prev ? s - Dprev[t] : s;
     a = dd * dd;
