@@ -532,8 +532,10 @@ __global__ __launch_bounds__(1024) void k_finish_step(const double* __restrict__
                                                       const uint32_t* halt) {
   __shared__ double bn[1024], bd[1024];
   __shared__ double s_eta;
-  double a = 0.0, b = 0.0;
+  double a = 0.0, b = 0.0;  // (loops unrolled: a thread's loads are in flight together)
+#pragma unroll 4
   for (int64_t r = threadIdx.x; r < n_num; r += 1024) a += pnum[r];
+#pragma unroll 4
   for (int64_t r = threadIdx.x; r < n_den; r += 1024) b += pden[r * 3];
   bn[threadIdx.x] = a;
   bd[threadIdx.x] = b;
@@ -562,8 +564,10 @@ __global__ __launch_bounds__(1024) void k_finish_step(const double* __restrict__
   }
   __syncthreads();
   const double e = s_eta;
-  if (e != 0.0)
+  if (e != 0.0) {
+#pragma unroll 4
     for (int64_t t = threadIdx.x; t < nz; t += 1024) Z[t] = (real)fma(e, h[t], (double)Z[t]);
+  }
 }
 
 hipError_t launch_finish_step(int dtype, const double* pnum, int64_t n_num, const double* pden,

@@ -62,6 +62,8 @@ __global__ void k_merge32(const real* __restrict__ L, int64_t Ls, const int32_t*
       const uint32_t j = dv.nL.div(item), l = item - j * nL;
       const real* Lp = L + (Llist ? (int64_t)Llist[l] : (int64_t)l) * Ls;
       const real* Rp = R + (Rlist ? (int64_t)Rlist[j] : (int64_t)j) * Rs;
+      // in order over b; unrolled so that the operand loads of a group are in flight together
+#pragma unroll 8
       for (int b = 0; b < rB; ++b) acc = fma(Lp[a + rA * b], Rp[b + rB * c], acc);
     }
     put<real, BF>(out, out_lo, (int64_t)t, acc);
@@ -87,7 +89,8 @@ __global__ void k_merge4(const float* __restrict__ L, int64_t Ls, const int32_t*
       const uint32_t j = dv.nL.div(item), l = item - j * nL;
       const float* Lp = L + (Llist ? (int64_t)Llist[l] : (int64_t)l) * Ls;
       const float* Rp = R + (Rlist ? (int64_t)Rlist[j] : (int64_t)j) * Rs;
-      for (int b = 0; b < rB; ++b) {
+#pragma unroll 8
+      for (int b = 0; b < rB; ++b) {  // (in order; unrolled: loads of a group overlap)
         const float4 lv = *reinterpret_cast<const float4*>(Lp + a + rA * b);
         const float rv = Rp[b + rB * c];
         acc[0] = fmaf(lv.x, rv, acc[0]);
@@ -134,6 +137,7 @@ __global__ void k_merge(const real* __restrict__ L, int64_t Ls, const int32_t* _
       const int64_t l = item % nL, j = item / nL;
       const real* Lp = L + (Llist ? (int64_t)Llist[l] : l) * Ls;
       const real* Rp = R + (Rlist ? (int64_t)Rlist[j] : j) * Rs;
+#pragma unroll 8
       for (int b = 0; b < rB; ++b) acc = fma(Lp[a + rA * b], Rp[b + rB * c], acc);
     }
     put<real, BF>(out, out_lo, t, acc);
